@@ -1,0 +1,197 @@
+/*
+ * bfc.h -- exact butterfly counting on one MI355X (gfx950) GPU.
+ *
+ * C ABI of libbfc.so.  Method: vertex-priority butterfly counting (BFC-VP,
+ * Algorithm 2 of Wang, Lin, Qin, Zhang, Zhang, "Efficient Butterfly Counting
+ * for Large Bipartite Networks") on the priority-relabelled graph of its
+ * cache-aware graph projection (Definition 4), with the per-edge extension
+ * of Algorithm 4 and per-vertex counts by Lemma 1.
+ *
+ * Problem (Section 2): G = (U, L, E) is a bipartite graph, E a subset of
+ * U x L.  A butterfly is a 2x2 biclique (Definition 2).  The library returns
+ *   - B_G, the number of butterflies                       (bfc_count_total)
+ *   - B_x for every vertex x of U and of L                 (bfc_count_per_vertex)
+ *   - B_e for every edge e, in input order                 (bfc_count_per_edge)
+ * as exact int64 values.
+ *
+ * Conventions shared by every call:
+ *   - Vertex ids are 0-based per layer: upper ids in [0, n_upper), lower ids
+ *     in [0, n_lower).  For Definition 3's tie-break the library uses the
+ *     global id (lower v -> v, upper u -> n_lower + u), so every upper id is
+ *     larger than every lower id, as Section 2 assumes.
+ *   - "dev" pointers are HIP device memory on the current device; "host"
+ *     pointers are host memory.  `stream` is a hipStream_t (NULL = default
+ *     stream).  Work is ordered on that stream.
+ *   - Every call returns a bfc_status; on failure no output is written, a
+ *     failed bfc_build leaves *out NULL, and bfc_last_error() describes the
+ *     failure.  No C++ exception crosses this interface.
+ *   - Counts are exact: the whole path is integer arithmetic (int32 wedge
+ *     counters, int64 sums; C(c,2) = c(c-1)/2 in int64).
+ */
+#ifndef BFC_H_
+#define BFC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BFC_OK = 0,
+  BFC_ERR_INVALID_ARGUMENT = 1,    /* null pointer, negative size, bad handle or option */
+  BFC_ERR_VERTEX_OUT_OF_RANGE = 2, /* an upper id outside [0,n_upper) or a lower id outside [0,n_lower) */
+  BFC_ERR_DUPLICATE_EDGE = 3,      /* E is a set (Section 2): a repeated (upper, lower) pair is rejected */
+  BFC_ERR_TOO_LARGE = 4,           /* m >= 2^30 or a layer with 2^30 or more vertices */
+  BFC_ERR_OUT_OF_MEMORY = 5,       /* a device allocation failed */
+  BFC_ERR_DEVICE = 6               /* a HIP runtime or kernel error */
+} bfc_status;
+
+/* Opaque handle: the priority-relabelled CSR of one graph and its schedule,
+ * resident in device memory until bfc_destroy.  A built handle is read-only
+ * for the count calls; concurrent count calls on one handle must use
+ * different streams and are serialised by the library. */
+typedef struct bfc_graph_s* bfc_graph;
+
+/*
+ * Builds the relabelled graph (Algorithm 2's first two steps, Definition 3,
+ * Definition 4, and the per-start wedge counts used for scheduling).
+ *   edges_dev  device int32 [m][2], row i = (upper id, lower id) of edge i.
+ *              Read only; the caller keeps ownership.  May be NULL if m == 0.
+ *   m          number of edges, 0 <= m < 2^30.
+ *   n_upper, n_lower  layer sizes, each in [0, 2^30).  Isolated vertices allowed.
+ *   stream     hipStream_t for the build kernels.
+ *   out        receives the handle (owned by the caller; free with bfc_destroy).
+ * Validates ids and distinctness on the device.  Synchronises `stream`.
+ */
+bfc_status bfc_build(const int32_t* edges_dev, int64_t m, int32_t n_upper, int32_t n_lower, void* stream,
+                     bfc_graph* out);
+
+/*
+ * B_G (Lemma 1 Eq. 2, computed as in Algorithm 2): each butterfly is counted
+ * once, from the two wedges through its vertex of highest priority.
+ *   total_host   host int64, receives B_G.
+ *   wedges_host  host int64 or NULL; receives |W|, the number of wedges
+ *                Algorithm 2 processes (Theorem 2's work measure).
+ * Synchronises `stream`.
+ */
+bfc_status bfc_count_total(bfc_graph g, void* stream, int64_t* total_host, int64_t* wedges_host);
+
+/*
+ * Device-output variant of bfc_count_total: writes B_G to total_dev (device
+ * int64 [1]) without synchronising.  For graph capture and pipelining.
+ */
+bfc_status bfc_count_total_async(bfc_graph g, void* stream, int64_t* total_dev);
+
+/*
+ * B_x for every vertex (Lemma 1 Eq. 1).  Each pair (start, end) with c
+ * common lower-priority middles adds C(c,2) to both, and each of its c
+ * wedges adds c-1 to its middle.
+ *   upper_dev  device int64 [n_upper], B_u by upper id (overwritten).
+ *   lower_dev  device int64 [n_lower], B_v by lower id (overwritten).
+ * Asynchronous on `stream`.
+ */
+bfc_status bfc_count_per_vertex(bfc_graph g, void* stream, int64_t* upper_dev, int64_t* lower_dev);
+
+/*
+ * B_e for every edge (Eq. 8 evaluated as in Algorithm 4): a second walk over
+ * the same wedges adds count - 1 to both of each wedge's edges.
+ *   edge_dev  device int64 [m], B_e in the input order of bfc_build (overwritten).
+ * Asynchronous on `stream`.
+ */
+bfc_status bfc_count_per_edge(bfc_graph g, void* stream, int64_t* edge_dev);
+
+/* Sizes of a built graph.  Any output pointer may be NULL.
+ *   device_bytes  device memory the handle holds (CSR, maps, schedule, scratch). */
+bfc_status bfc_graph_info(bfc_graph g, int64_t* m, int32_t* n_upper, int32_t* n_lower, int64_t* wedges,
+                          int64_t* device_bytes);
+
+/* Device memory bfc_build would need for a graph of this size (an upper
+ * bound, for admission control).  Returns 0 on bad sizes. */
+int64_t bfc_estimate_device_bytes(int64_t m, int32_t n_upper, int32_t n_lower);
+
+/* Frees the handle and its device memory.  NULL is a no-op. */
+bfc_status bfc_destroy(bfc_graph g);
+
+/*
+ * Tuning knobs for one handle.  None of them changes any count; they choose
+ * which kernel path handles each start vertex.  A field <= 0 keeps the
+ * current setting (except dense_block, where 0 disables and < 0 keeps).
+ *   light_max_wedges   starts with at most this many wedges (<= 1024) are
+ *                      counted by one wavefront with an LDS hash table;
+ *                      larger ones by a workgroup.  Default 1024.
+ *   dense_min_ratio    a workgroup start uses dense LDS counter windows when
+ *                      wedges * dense_min_ratio >= its end-rank range, else LDS
+ *                      hash windows.  Default 4.
+ *   window_mode        1 = automatic (default), 2 = always dense windows,
+ *                      3 = always hash windows.
+ *   hash_window_wedges wedges aimed at per hash window of a large start (the
+ *                      window is halved when its distinct ends overfill the
+ *                      table).  Default 4096.
+ *   dense_block        vertices per layer in the top-priority block counted
+ *                      with int8 MFMA (0 disables it; multiple of 64).
+ */
+typedef struct {
+  int32_t light_max_wedges;
+  int32_t dense_min_ratio;
+  int32_t window_mode;
+  int32_t hash_window_wedges;
+  int32_t dense_block;
+} bfc_tuning;
+
+bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t);
+bfc_status bfc_get_tuning(bfc_graph g, bfc_tuning* t);
+
+/*
+ * Work split of a built graph (for reporting; all counts are exact integers).
+ *   wedges          |W|, the wedges Algorithm 2 processes (Theorem 2's measure)
+ *   starts_*        start vertices handed to the wavefront (light) and
+ *                   workgroup (heavy) kernels
+ *   wedges_*        wedges those starts process
+ *   middles_*       lower-priority neighbours (middle vertices) they walk
+ *   max_start_wedges  the largest per-start wedge count
+ */
+typedef struct {
+  int64_t wedges;
+  int64_t starts_light, starts_heavy;
+  int64_t wedges_light, wedges_heavy;
+  int64_t middles_light, middles_heavy;
+  int64_t max_start_wedges;
+} bfc_schedule_info;
+
+bfc_status bfc_get_schedule_info(bfc_graph g, bfc_schedule_info* out);
+
+/*
+ * Kernel timing with HIP events recorded on the caller's stream around the
+ * count kernels of every later count call on this handle.  enable != 0
+ * turns it on and resets the sums; 0 turns it off.  Not for use while the
+ * stream is being captured into a graph.
+ *   calls      count calls timed since the reset
+ *   light_ms   summed duration of the light-start (wavefront) kernel
+ *   heavy_ms   summed duration of the heavy-start (workgroup) kernel
+ *   other_ms   summed duration of the remaining count kernels (fold, dense block)
+ * bfc_get_kernel_times waits for the timed calls to finish.
+ */
+typedef struct {
+  int64_t calls;
+  double light_ms;
+  double heavy_ms;
+  double other_ms;
+} bfc_kernel_times;
+
+bfc_status bfc_set_kernel_timing(bfc_graph g, int32_t enable);
+bfc_status bfc_get_kernel_times(bfc_graph g, bfc_kernel_times* out);
+
+/* Text of the last error on the calling thread ("" if none).  Valid until the
+ * next call from that thread. */
+const char* bfc_last_error(void);
+
+/* Library version string. */
+const char* bfc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFC_H_ */

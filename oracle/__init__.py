@@ -53,6 +53,8 @@ def _load():
     lib.orc_total.restype = i32
     lib.orc_edge_counts.argtypes = [vp, i64, i64, i64, i32, i32, vp]
     lib.orc_edge_counts.restype = i32
+    lib.orc_vertex_counts_subset.argtypes = [vp, i64, i64, i64, i32, vp, i64, vp, i32]
+    lib.orc_vertex_counts_subset.restype = i32
     lib.orc_open.argtypes = [vp, i64, i64, i64, vp]
     lib.orc_open.restype = vp
     lib.orc_close.argtypes = [vp]
@@ -118,6 +120,23 @@ def vertex_counts_side(g, side: int, nthreads: int | None = None) -> np.ndarray:
     _check(_load().orc_vertex_counts(p, e.shape[0], g.n_upper, g.n_lower, side, out.ctypes.data, threads(nthreads)),
            "vertex")
     return out
+
+
+def vertex_counts_subset(g, side: int, xs, nthreads: int | None = None) -> np.ndarray:
+    """Eq. 1 for the listed vertices of one layer only."""
+    e, p = _edges(g)
+    xs = np.ascontiguousarray(xs, dtype=np.int64)
+    out = np.zeros(len(xs), dtype=np.int64)
+    _check(_load().orc_vertex_counts_subset(p, e.shape[0], g.n_upper, g.n_lower, side, xs.ctypes.data, len(xs),
+                                            out.ctypes.data, threads(nthreads)), "vertex subset")
+    return out
+
+
+def cheaper_side(g) -> int:
+    """The start layer of the sum-of-squared-degrees rule (0 upper, 1 lower)."""
+    du = np.bincount(g.edges[:, 0], minlength=g.n_upper).astype(np.int64)
+    dl = np.bincount(g.edges[:, 1], minlength=g.n_lower).astype(np.int64)
+    return 1 if int((du * du).sum()) < int((dl * dl).sum()) else 0
 
 
 def edge_counts(g, side: int = -1, nthreads: int | None = None) -> np.ndarray:

@@ -219,6 +219,42 @@ int orc_edge_counts(const int32_t* edges, int64_t m, int64_t nU, int64_t nL, int
   return rc;
 }
 
+/* Eq. 1 for the listed vertices xs[0..k) of layer `side` only (a sample of
+ * starts, for timing the oracle on part of a large graph). */
+int orc_vertex_counts_subset(const int32_t* edges, int64_t m, int64_t nU, int64_t nL, int side,
+                             const int64_t* xs, int64_t k, int64_t* out, int nthreads) {
+  bigraph g;
+  int rc = load_graph(&g, edges, m, nU, nL);
+  if (rc) return rc;
+  const side_csr* S = side == 0 ? &g.up : &g.lo;
+  const side_csr* M = side == 0 ? &g.lo : &g.up;
+  for (int64_t i = 0; i < k; ++i) if (xs[i] < 0 || xs[i] >= S->n) { free_graph(&g); return -1; }
+  int failed = 0;
+#pragma omp parallel num_threads(nthreads)
+  {
+    int32_t* cnt = (int32_t*)calloc((size_t)(S->n > 0 ? S->n : 1), sizeof(int32_t));
+    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * (size_t)(S->n > 0 ? S->n : 1));
+    if (!cnt || !touched) {
+#pragma omp atomic write
+      failed = 1;
+    }
+#pragma omp barrier
+    if (!failed) {
+#pragma omp for schedule(dynamic, 16)
+      for (int64_t i = 0; i < k; ++i) {
+        int64_t s = xs[i];
+        int64_t nt = count_common(S, M, s, cnt, touched);
+        int64_t acc = 0;
+        for (int64_t t = 0; t < nt; ++t) { acc += choose2(cnt[touched[t]]); cnt[touched[t]] = 0; }
+        out[i] = acc;
+      }
+    }
+    free(cnt); free(touched);
+  }
+  free_graph(&g);
+  return failed ? -3 : 0;
+}
+
 /* ------------------------------------------------ single-vertex / edge */
 
 /* Handle for repeated single-vertex and single-edge queries on one graph. */

@@ -1,0 +1,231 @@
+"""Python binding of libbfc (ctypes).  Argument marshalling only.
+
+Every step of the counting path runs in the HIP library: this module passes
+device pointers of torch tensors and the current HIP stream to the C entry
+points of ``include/bfc.h`` and turns status codes into exceptions.  If the
+library has not been built, ``load()`` raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbfc.so")
+_lib = None
+
+OK = 0
+STATUS = {
+    0: "BFC_OK",
+    1: "BFC_ERR_INVALID_ARGUMENT",
+    2: "BFC_ERR_VERTEX_OUT_OF_RANGE",
+    3: "BFC_ERR_DUPLICATE_EDGE",
+    4: "BFC_ERR_TOO_LARGE",
+    5: "BFC_ERR_OUT_OF_MEMORY",
+    6: "BFC_ERR_DEVICE",
+}
+
+EXPORTS = [
+    "bfc_build", "bfc_count_total", "bfc_count_total_async", "bfc_count_per_vertex", "bfc_count_per_edge",
+    "bfc_graph_info", "bfc_estimate_device_bytes", "bfc_destroy", "bfc_set_tuning", "bfc_get_tuning",
+    "bfc_last_error", "bfc_version", "bfc_get_schedule_info", "bfc_set_kernel_timing", "bfc_get_kernel_times",
+]
+
+
+class BfcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("light_max_wedges", ctypes.c_int32), ("dense_min_ratio", ctypes.c_int32),
+                ("window_mode", ctypes.c_int32), ("hash_window_wedges", ctypes.c_int32),
+                ("dense_block", ctypes.c_int32)]
+
+
+class ScheduleInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("wedges", "starts_light", "starts_heavy", "wedges_light",
+                                               "wedges_heavy", "middles_light", "middles_heavy",
+                                               "max_start_wedges")]
+
+
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int64), ("light_ms", ctypes.c_double), ("heavy_ms", ctypes.c_double),
+                ("other_ms", ctypes.c_double)]
+
+
+def load(path: str | None = None):
+    """Loads libbfc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_1812_00283_amd.build`")
+    lib = ctypes.CDLL(p)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    pi64, pi32 = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "bfc_build": ([vp, i64, i32, i32, vp, ctypes.POINTER(vp)], i32),
+        "bfc_count_total": ([vp, vp, pi64, pi64], i32),
+        "bfc_count_total_async": ([vp, vp, vp], i32),
+        "bfc_count_per_vertex": ([vp, vp, vp, vp], i32),
+        "bfc_count_per_edge": ([vp, vp, vp], i32),
+        "bfc_graph_info": ([vp, pi64, pi32, pi32, pi64, pi64], i32),
+        "bfc_estimate_device_bytes": ([i64, i32, i32], i64),
+        "bfc_destroy": ([vp], i32),
+        "bfc_set_tuning": ([vp, ctypes.POINTER(Tuning)], i32),
+        "bfc_get_tuning": ([vp, ctypes.POINTER(Tuning)], i32),
+        "bfc_get_schedule_info": ([vp, ctypes.POINTER(ScheduleInfo)], i32),
+        "bfc_set_kernel_timing": ([vp, i32], i32),
+        "bfc_get_kernel_times": ([vp, ctypes.POINTER(KernelTimes)], i32),
+        "bfc_last_error": ([], ctypes.c_char_p),
+        "bfc_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != OK:
+        raise BfcError(status, load().bfc_last_error().decode())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else None)
+
+
+def version() -> str:
+    return load().bfc_version().decode()
+
+
+def estimate_device_bytes(m: int, n_upper: int, n_lower: int) -> int:
+    return int(load().bfc_estimate_device_bytes(m, n_upper, n_lower))
+
+
+class Graph:
+    """A graph built on the GPU (``bfc_build``) and its count calls."""
+
+    def __init__(self, edges: torch.Tensor, n_upper: int, n_lower: int, stream=None):
+        lib = load()
+        if not isinstance(edges, torch.Tensor) or edges.dtype != torch.int32 or not edges.is_cuda:
+            raise TypeError("edges must be an int32 CUDA tensor of shape [m, 2]")
+        if edges.dim() != 2 or edges.shape[1] != 2:
+            raise ValueError("edges must have shape [m, 2]")
+        edges = edges.contiguous()
+        self.m = int(edges.shape[0])
+        self.n_upper = int(n_upper)
+        self.n_lower = int(n_lower)
+        self.device = edges.device
+        h = ctypes.c_void_p()
+        _check(lib.bfc_build(_ptr(edges), self.m, self.n_upper, self.n_lower, _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    # -- counts -------------------------------------------------------
+    def count_total(self, stream=None) -> tuple[int, int]:
+        """(B_G, |W|): the butterfly count and the wedges Algorithm 2 processes."""
+        t = ctypes.c_int64(0)
+        w = ctypes.c_int64(0)
+        _check(load().bfc_count_total(self._h, _stream(stream), ctypes.byref(t), ctypes.byref(w)))
+        return int(t.value), int(w.value)
+
+    def count_total_async(self, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """Writes B_G into ``out`` (int64 CUDA tensor with one element) without synchronising."""
+        if out.dtype != torch.int64 or not out.is_cuda or out.numel() < 1:
+            raise TypeError("out must be an int64 CUDA tensor")
+        _check(load().bfc_count_total_async(self._h, _stream(stream), _ptr(out)))
+        return out
+
+    def count_per_vertex(self, stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+        up = torch.empty(self.n_upper, dtype=torch.int64, device=self.device)
+        lo = torch.empty(self.n_lower, dtype=torch.int64, device=self.device)
+        _check(load().bfc_count_per_vertex(self._h, _stream(stream), _ptr(up), _ptr(lo)))
+        return up, lo
+
+    def count_per_edge(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.m, dtype=torch.int64, device=self.device)
+        _check(load().bfc_count_per_edge(self._h, _stream(stream), _ptr(out)))
+        return out
+
+    # -- info and tuning ------------------------------------------------
+    def info(self) -> dict:
+        m, nu, nl, w, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().bfc_graph_info(self._h, ctypes.byref(m), ctypes.byref(nu), ctypes.byref(nl), ctypes.byref(w),
+                                     ctypes.byref(b)))
+        return {"m": m.value, "n_upper": nu.value, "n_lower": nl.value, "wedges": w.value, "device_bytes": b.value}
+
+    def set_tuning(self, light_max_wedges: int = 0, dense_min_ratio: int = 0, window_mode: int = 0,
+                   hash_window_wedges: int = 0, dense_block: int = -1) -> None:
+        """Changes which kernel path handles each start; no count changes.
+        window_mode: 1 automatic, 2 dense windows only, 3 hash windows only."""
+        t = Tuning(light_max_wedges, dense_min_ratio, window_mode, hash_window_wedges, dense_block)
+        _check(load().bfc_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(load().bfc_get_tuning(self._h, ctypes.byref(t)))
+        return {"light_max_wedges": t.light_max_wedges, "dense_min_ratio": t.dense_min_ratio,
+                "window_mode": t.window_mode, "hash_window_wedges": t.hash_window_wedges,
+                "dense_block": t.dense_block}
+
+    def schedule_info(self) -> dict:
+        si = ScheduleInfo()
+        _check(load().bfc_get_schedule_info(self._h, ctypes.byref(si)))
+        return {n: int(getattr(si, n)) for n, _ in ScheduleInfo._fields_}
+
+    def set_kernel_timing(self, enable: bool) -> None:
+        """Records HIP events around the count kernels of later calls (resets the sums)."""
+        _check(load().bfc_set_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_times(self) -> dict:
+        kt = KernelTimes()
+        _check(load().bfc_get_kernel_times(self._h, ctypes.byref(kt)))
+        return {"calls": int(kt.calls), "light_ms": kt.light_ms, "heavy_ms": kt.heavy_ms, "other_ms": kt.other_ms}
+
+    # -- lifetime --------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(load().bfc_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# Module-level names matching the C entry points.
+def build(edges: torch.Tensor, n_upper: int, n_lower: int, stream=None) -> Graph:
+    return Graph(edges, n_upper, n_lower, stream)
+
+
+def count_total(g: Graph, stream=None) -> tuple[int, int]:
+    return g.count_total(stream)
+
+
+def count_per_vertex(g: Graph, stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+    return g.count_per_vertex(stream)
+
+
+def count_per_edge(g: Graph, stream=None) -> torch.Tensor:
+    return g.count_per_edge(stream)

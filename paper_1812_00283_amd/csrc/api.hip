@@ -1,0 +1,309 @@
+// C-ABI entry points of libbfc (declared in include/bfc.h).
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+namespace bfc {
+
+void set_error(bfc_status, const std::string& what) { g_last_error = what; }
+
+namespace {
+
+template <typename F>
+bfc_status guard(F&& f) {
+  g_last_error.clear();
+  try {
+    f();
+    return BFC_OK;
+  } catch (const Error& e) {
+    set_error(e.status, e.what);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_error(BFC_ERR_OUT_OF_MEMORY, "host allocation failed");
+    return BFC_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    set_error(BFC_ERR_DEVICE, "unexpected internal error");
+    return BFC_ERR_DEVICE;
+  }
+}
+
+// Restores the caller's current device on scope exit.
+struct DeviceScope {
+  int prev = -1;
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) BFC_HIP(hipSetDevice(dev));
+  }
+  ~DeviceScope() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+void zero_i64(int64_t* p, int64_t n, hipStream_t s) { zero_u64(p, n, s); }
+
+bfc_graph_s* checked(bfc_graph g) {
+  if (!g) throw Error{BFC_ERR_INVALID_ARGUMENT, "null graph handle"};
+  return g;
+}
+
+}  // namespace
+}  // namespace bfc
+
+int64_t bfc_graph_s::device_bytes() const {
+  int64_t b = 0;
+  for (int x = 0; x < 2; ++x) {
+    const bfc::Side& s = side[x];
+    b += s.off.bytes + s.adj.bytes + s.rev.bytes + s.lo.bytes + s.id_of.bytes + s.work.bytes;
+  }
+  b += eslot.bytes + sched.light.bytes + sched.heavy.bytes + scratch.bytes + acc.bytes;
+  return b;
+}
+
+namespace {
+
+// Orders this count call after the previous one on the handle when the
+// streams differ, and records its completion for the next one.
+struct CountSection {
+  bfc_graph_s* g;
+  hipStream_t s;
+  std::unique_lock<std::mutex> hold;
+  CountSection(bfc_graph_s* h, hipStream_t stream) : g(h), s(stream), hold(h->mu) {
+    if (g->used && g->last != s) BFC_HIP(hipStreamWaitEvent(s, g->done, 0));
+  }
+  void finish() {
+    BFC_HIP(hipEventRecord(g->done, s));
+    g->last = s;
+    g->used = true;
+  }
+};
+
+}  // namespace
+
+using namespace bfc;
+
+extern "C" {
+
+const char* bfc_last_error(void) { return g_last_error.c_str(); }
+
+const char* bfc_version(void) { return "bfc-mi355x 0.1 (gfx950)"; }
+
+int64_t bfc_estimate_device_bytes(int64_t m, int32_t n_upper, int32_t n_lower) {
+  if (m < 0 || n_upper < 0 || n_lower < 0) return 0;
+  const int64_t n = (int64_t)n_upper + n_lower;
+  // resident: 2 sides x (adj + rev) + eslot + per-vertex arrays
+  const int64_t resident = m * 4 * 5 + n * (4 + 4 + 4 + 8) + 2 * 4 * (int64_t)2 + 4096;
+  // build peak: resident + sort buffers (2 x (8 + 4) bytes per edge) + slots
+  const int64_t build_peak = resident + m * (24 + 8) + n * 16;
+  // per-edge counting: 2 int64 accumulators per edge
+  const int64_t edge_peak = resident + m * 16;
+  return build_peak > edge_peak ? build_peak : edge_peak;
+}
+
+bfc_status bfc_build(const int32_t* edges_dev, int64_t m, int32_t n_upper, int32_t n_lower, void* stream,
+                     bfc_graph* out) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    if (!out) throw Error{BFC_ERR_INVALID_ARGUMENT, "out is null"};
+    if (m < 0 || n_upper < 0 || n_lower < 0) throw Error{BFC_ERR_INVALID_ARGUMENT, "negative size"};
+    if (m > 0 && !edges_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "edges_dev is null"};
+    if (m >= (int64_t(1) << 30) || n_upper >= (1 << 30) || n_lower >= (1 << 30))
+      throw Error{BFC_ERR_TOO_LARGE, "m and each layer size must be below 2^30"};
+    if (m > (int64_t)n_upper * (int64_t)n_lower)
+      throw Error{BFC_ERR_DUPLICATE_EDGE, "more edges than (upper, lower) pairs: some pair repeats"};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bfc_graph_s* g = new bfc_graph_s();
+    try {
+      BFC_HIP(hipGetDevice(&g->device));
+      BFC_HIP(hipEventCreateWithFlags(&g->done, hipEventDisableTiming));
+      g->m = m;
+      g->n_upper = n_upper;
+      g->n_lower = n_lower;
+      build_graph(g, edges_dev, s);
+      build_schedule(g, s);
+      prepare_count(g);
+    } catch (...) {
+      if (g->done) (void)hipEventDestroy(g->done);
+      delete g;
+      throw;
+    }
+    *out = g;
+  });
+}
+
+bfc_status bfc_count_total(bfc_graph g, void* stream, int64_t* total_host, int64_t* wedges_host) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!total_host) throw Error{BFC_ERR_INVALID_ARGUMENT, "total_host is null"};
+    DeviceScope ds(h->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TmpBuf tot;
+    tot.alloc(sizeof(int64_t), s);
+    {
+      CountSection cs(h, s);
+      zero_i64(tot.as<int64_t>(), 1, s);
+      count(h, kTotal, tot.as<int64_t>(), nullptr, nullptr, s);
+      cs.finish();
+    }
+    int64_t v = 0;
+    BFC_HIP(hipMemcpyAsync(&v, tot.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    BFC_HIP(hipStreamSynchronize(s));
+    *total_host = v;
+    if (wedges_host) *wedges_host = h->sched.wedges;
+  });
+}
+
+bfc_status bfc_count_total_async(bfc_graph g, void* stream, int64_t* total_dev) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!total_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "total_dev is null"};
+    DeviceScope ds(h->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    CountSection cs(h, s);
+    zero_i64(total_dev, 1, s);
+    count(h, kTotal, total_dev, nullptr, nullptr, s);
+    cs.finish();
+  });
+}
+
+bfc_status bfc_count_per_vertex(bfc_graph g, void* stream, int64_t* upper_dev, int64_t* lower_dev) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if ((h->n_upper > 0 && !upper_dev) || (h->n_lower > 0 && !lower_dev))
+      throw Error{BFC_ERR_INVALID_ARGUMENT, "output pointer is null"};
+    DeviceScope ds(h->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    CountSection cs(h, s);
+    zero_i64(upper_dev, h->n_upper, s);
+    zero_i64(lower_dev, h->n_lower, s);
+    count(h, kVertex, nullptr, upper_dev, lower_dev, s);
+    cs.finish();
+  });
+}
+
+bfc_status bfc_count_per_edge(bfc_graph g, void* stream, int64_t* edge_dev) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (h->m > 0 && !edge_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "edge_dev is null"};
+    DeviceScope ds(h->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    CountSection cs(h, s);
+    count(h, kEdge, nullptr, edge_dev, nullptr, s);
+    cs.finish();
+  });
+}
+
+bfc_status bfc_graph_info(bfc_graph g, int64_t* m, int32_t* n_upper, int32_t* n_lower, int64_t* wedges,
+                          int64_t* device_bytes) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (m) *m = h->m;
+    if (n_upper) *n_upper = h->n_upper;
+    if (n_lower) *n_lower = h->n_lower;
+    if (wedges) *wedges = h->sched.wedges;
+    if (device_bytes) *device_bytes = h->device_bytes();
+  });
+}
+
+bfc_status bfc_destroy(bfc_graph g) {
+  if (!g) return BFC_OK;
+  return guard([&] {
+    {
+      DeviceScope ds(g->device);
+      if (g->used) BFC_HIP(hipEventSynchronize(g->done));
+      collect_times(g);
+      (void)hipEventDestroy(g->done);
+      delete g;
+    }
+  });
+}
+
+bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!t) throw Error{BFC_ERR_INVALID_ARGUMENT, "tuning is null"};
+    DeviceScope ds(h->device);
+    std::lock_guard<std::mutex> hold(h->mu);
+    if (t->light_max_wedges > 1024)
+      throw Error{BFC_ERR_INVALID_ARGUMENT, "light_max_wedges must be at most 1024"};
+    if (t->dense_block > 0 && t->dense_block % 64)
+      throw Error{BFC_ERR_INVALID_ARGUMENT, "dense_block must be a multiple of 64"};
+    if (t->window_mode > 3) throw Error{BFC_ERR_INVALID_ARGUMENT, "window_mode must be 1, 2 or 3"};
+    Tuning nt = h->tune;
+    if (t->light_max_wedges > 0) nt.light_max_wedges = t->light_max_wedges;
+    if (t->dense_min_ratio > 0) nt.dense_min_ratio = t->dense_min_ratio;
+    if (t->window_mode > 0) nt.window_mode = t->window_mode;
+    if (t->hash_window_wedges > 0) nt.hash_window_wedges = t->hash_window_wedges;
+    if (t->dense_block >= 0) nt.dense_block = t->dense_block;
+    const bool resched = nt.light_max_wedges != h->tune.light_max_wedges;
+    h->tune = nt;
+    if (resched) {
+      if (h->used) BFC_HIP(hipEventSynchronize(h->done));
+      BFC_HIP(hipDeviceSynchronize());
+      build_schedule(h, nullptr);
+      prepare_count(h);
+    }
+  });
+}
+
+bfc_status bfc_get_schedule_info(bfc_graph g, bfc_schedule_info* out) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!out) throw Error{BFC_ERR_INVALID_ARGUMENT, "out is null"};
+    const Schedule& sc = h->sched;
+    out->wedges = sc.wedges;
+    out->starts_light = sc.n_light;
+    out->starts_heavy = sc.n_heavy;
+    out->wedges_light = sc.wedges_light;
+    out->wedges_heavy = sc.wedges_heavy;
+    out->middles_light = sc.middles_light;
+    out->middles_heavy = sc.middles_heavy;
+    out->max_start_wedges = sc.max_start_wedges;
+  });
+}
+
+bfc_status bfc_set_kernel_timing(bfc_graph g, int32_t enable) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    DeviceScope ds(h->device);
+    std::lock_guard<std::mutex> hold(h->mu);
+    collect_times(h);
+    h->timing = enable != 0;
+    h->timed_calls = 0;
+    h->light_ms = h->heavy_ms = h->other_ms = 0;
+  });
+}
+
+bfc_status bfc_get_kernel_times(bfc_graph g, bfc_kernel_times* out) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!out) throw Error{BFC_ERR_INVALID_ARGUMENT, "out is null"};
+    DeviceScope ds(h->device);
+    std::lock_guard<std::mutex> hold(h->mu);
+    collect_times(h);
+    out->calls = h->timed_calls;
+    out->light_ms = h->light_ms;
+    out->heavy_ms = h->heavy_ms;
+    out->other_ms = h->other_ms;
+  });
+}
+
+bfc_status bfc_get_tuning(bfc_graph g, bfc_tuning* t) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!t) throw Error{BFC_ERR_INVALID_ARGUMENT, "tuning is null"};
+    t->light_max_wedges = h->tune.light_max_wedges;
+    t->dense_min_ratio = h->tune.dense_min_ratio;
+    t->window_mode = h->tune.window_mode;
+    t->hash_window_wedges = h->tune.hash_window_wedges;
+    t->dense_block = h->tune.dense_block;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,333 @@
+// Graph build: validation, priorities (Definition 3), the relabelled CSR of
+// the graph projection (Definition 4) and the per-start wedge counts that
+// drive the schedule of the counting kernels.
+//
+// Layout produced (per layer X in {upper, lower}, "other" = the other layer):
+//   rank_X(x)   position of x in ascending priority among the vertices of X.
+//               Definition 3 orders by degree, ties by id; restricted to one
+//               layer this is a stable sort of the layer's ids by degree.
+//   off_X, adj_X  CSR by rank; adj holds the neighbours' ranks in the other
+//               layer in ascending order (the sorted neighbour lists of
+//               Algorithm 2, built by sorting (rank, neighbour rank) keys).
+//   rev_X[k]    slot, in adj_other, of the reverse of arc k.
+//   lo_X[r]     number of neighbours of r with lower priority than r; they
+//               form a prefix of r's list.  Across layers the global id makes
+//               every upper id larger than every lower id, so for an edge
+//               (u upper, v lower): p(v) < p(u)  <=>  deg(v) <= deg(u).
+//   work_X[r]   wedges Algorithm 2 processes from start r: for each middle v
+//               in the prefix, the ends are the entries of N(v) before r,
+//               i.e. rev[k] - off_other[v] of them.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace bfc {
+
+namespace {
+
+__global__ void degree_kernel(const int32_t* __restrict__ edges, int64_t m, int32_t nU, int32_t nL,
+                              int32_t* __restrict__ degU, int32_t* __restrict__ degL, int32_t* __restrict__ status) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int2 e = reinterpret_cast<const int2*>(edges)[i];
+    if (e.x < 0 || e.x >= nU || e.y < 0 || e.y >= nL) {
+      atomicOr(&status[0], 1);
+      continue;
+    }
+    atomicAdd(&degU[e.x], 1);
+    atomicAdd(&degL[e.y], 1);
+  }
+}
+
+__global__ void iota_kernel(uint32_t* __restrict__ a, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = (uint32_t)i;
+}
+
+__global__ void invert_kernel(const uint32_t* __restrict__ id_of, int32_t* __restrict__ rank_of, int64_t n) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    rank_of[id_of[r]] = (int32_t)r;
+}
+
+// keys for one side's CSR sort: (rank of source) << bits_other | rank of neighbour
+__global__ void arc_keys_kernel(const int32_t* __restrict__ edges, int64_t m, int src_col,
+                                const int32_t* __restrict__ rank_src, const int32_t* __restrict__ rank_dst,
+                                int bits_dst, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int2 e = reinterpret_cast<const int2*>(edges)[i];
+    const int32_t a = src_col == 0 ? e.x : e.y;
+    const int32_t b = src_col == 0 ? e.y : e.x;
+    keys[i] = ((uint64_t)(uint32_t)rank_src[a] << bits_dst) | (uint64_t)(uint32_t)rank_dst[b];
+    vals[i] = (uint32_t)i;
+  }
+}
+
+__global__ void arc_unpack_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t m,
+                                  uint64_t mask_dst, int32_t* __restrict__ adj, int32_t* __restrict__ slot_of_edge,
+                                  int32_t* __restrict__ status) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = keys[k];
+    adj[k] = (int32_t)(key & mask_dst);
+    slot_of_edge[vals[k]] = (int32_t)k;
+    if (k > 0 && keys[k - 1] == key) atomicOr(&status[1], 1);
+  }
+}
+
+__global__ void link_kernel(const int32_t* __restrict__ edges, int64_t m, const int32_t* __restrict__ slotU,
+                            const int32_t* __restrict__ slotL, const int32_t* __restrict__ rankU,
+                            const int32_t* __restrict__ rankL, const int32_t* __restrict__ degU,
+                            const int32_t* __restrict__ degL, const int32_t* __restrict__ offU,
+                            const int32_t* __restrict__ offL, int32_t* __restrict__ revU, int32_t* __restrict__ revL,
+                            int32_t* __restrict__ loU, int32_t* __restrict__ loL, unsigned long long* __restrict__ workU,
+                            unsigned long long* __restrict__ workL, int32_t* __restrict__ eslot) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int2 e = reinterpret_cast<const int2*>(edges)[i];
+    const int32_t su = slotU[i];
+    const int32_t sl = slotL[i];
+    revU[su] = sl;
+    revL[sl] = su;
+    eslot[i] = su;
+    const int32_t ru = rankU[e.x];
+    const int32_t rl = rankL[e.y];
+    if (degL[e.y] <= degU[e.x]) {
+      // v has lower priority: arc u->v is a middle arc of start u; ends = N(v) before u
+      atomicAdd(&loU[ru], 1);
+      atomicAdd(&workU[ru], (unsigned long long)(sl - offL[rl]));
+    } else {
+      atomicAdd(&loL[rl], 1);
+      atomicAdd(&workL[rl], (unsigned long long)(su - offU[ru]));
+    }
+  }
+}
+
+unsigned grid_1d(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
+  const int64_t m = g->m;
+  const int32_t n[2] = {g->n_upper, g->n_lower};
+
+  TmpBuf status;
+  status.alloc(4 * sizeof(int32_t), s);
+  BFC_HIP(hipMemsetAsync(status.p, 0, 4 * sizeof(int32_t), s));
+  TmpBuf deg[2];
+  for (int x = 0; x < 2; ++x) {
+    deg[x].alloc(sizeof(int32_t) * (size_t)(n[x] + 1), s);
+    BFC_HIP(hipMemsetAsync(deg[x].p, 0, sizeof(int32_t) * (size_t)(n[x] + 1), s));
+  }
+  if (m > 0) {
+    degree_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, n[0], n[1], deg[0].as<int32_t>(), deg[1].as<int32_t>(),
+                                              status.as<int32_t>());
+    BFC_LAUNCH_CHECK();
+  }
+  int32_t st[4] = {0, 0, 0, 0};
+  BFC_HIP(hipMemcpyAsync(st, status.p, sizeof(st), hipMemcpyDeviceToHost, s));
+  BFC_HIP(hipStreamSynchronize(s));
+  if (st[0]) throw Error{BFC_ERR_VERTEX_OUT_OF_RANGE, "an edge has an upper id outside [0,n_upper) or a lower id outside [0,n_lower)"};
+
+  // ---- priorities: stable sort of each layer's ids by degree
+  TmpBuf rank_of[2];
+  for (int x = 0; x < 2; ++x) {
+    Side& sd = g->side[x];
+    sd.n = n[x];
+    const int64_t nx = n[x];
+    TmpBuf keys, ktmp, vtmp;
+    sd.id_of.alloc(sizeof(uint32_t) * (size_t)nx);
+    DevBuf& vals = sd.id_of;
+    keys.alloc(sizeof(uint32_t) * (size_t)nx, s);
+    ktmp.alloc(sizeof(uint32_t) * (size_t)nx, s);
+    vtmp.alloc(sizeof(uint32_t) * (size_t)nx, s);
+    if (nx > 0) {
+      BFC_HIP(hipMemcpyAsync(keys.p, deg[x].p, sizeof(uint32_t) * (size_t)nx, hipMemcpyDeviceToDevice, s));
+      iota_kernel<<<grid_1d(nx), 256, 0, s>>>(vals.as<uint32_t>(), nx);
+      BFC_LAUNCH_CHECK();
+      const int64_t max_deg = m < n[1 - x] ? m : n[1 - x];
+      radix_sort_u32(keys.as<uint32_t>(), vals.as<uint32_t>(), ktmp.as<uint32_t>(), vtmp.as<uint32_t>(), nx,
+                     bits_for((uint64_t)max_deg), s);
+    }
+    // keys = degrees in rank order; vals = id_of
+    rank_of[x].alloc(sizeof(int32_t) * (size_t)nx, s);
+    if (nx > 0) {
+      invert_kernel<<<grid_1d(nx), 256, 0, s>>>(sd.id_of.as<uint32_t>(), rank_of[x].as<int32_t>(), nx);
+      BFC_LAUNCH_CHECK();
+    }
+    sd.off.alloc(sizeof(int32_t) * (size_t)(nx + 1));
+    exclusive_scan_i32(keys.as<int32_t>(), sd.off.as<int32_t>(), nx, sd.off.as<int32_t>() + nx, s);
+  }
+
+  // ---- per-side CSR by sorting (rank, neighbour rank) keys
+  TmpBuf slot[2];
+  const int bits[2] = {bits_for((uint64_t)(n[0] > 1 ? n[0] - 1 : 1)), bits_for((uint64_t)(n[1] > 1 ? n[1] - 1 : 1))};
+  {
+    TmpBuf keys, vals, ktmp, vtmp;
+    keys.alloc(sizeof(uint64_t) * (size_t)m, s);
+    vals.alloc(sizeof(uint32_t) * (size_t)m, s);
+    ktmp.alloc(sizeof(uint64_t) * (size_t)m, s);
+    vtmp.alloc(sizeof(uint32_t) * (size_t)m, s);
+    for (int x = 0; x < 2; ++x) {
+      Side& sd = g->side[x];
+      sd.adj.alloc(sizeof(int32_t) * (size_t)m);
+      slot[x].alloc(sizeof(int32_t) * (size_t)m, s);
+      if (m == 0) continue;
+      const int bd = bits[1 - x];
+      arc_keys_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, x, rank_of[x].as<int32_t>(), rank_of[1 - x].as<int32_t>(),
+                                                   bd, keys.as<uint64_t>(), vals.as<uint32_t>());
+      BFC_LAUNCH_CHECK();
+      radix_sort_u64(keys.as<uint64_t>(), vals.as<uint32_t>(), ktmp.as<uint64_t>(), vtmp.as<uint32_t>(), m,
+                     bits[0] + bits[1], s);
+      arc_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(keys.as<uint64_t>(), vals.as<uint32_t>(), m,
+                                                     (1ull << bd) - 1ull, sd.adj.as<int32_t>(), slot[x].as<int32_t>(),
+                                                     status.as<int32_t>());
+      BFC_LAUNCH_CHECK();
+    }
+  }
+
+  // ---- reverse slots, lower-priority prefix lengths, per-start work
+  for (int x = 0; x < 2; ++x) {
+    Side& sd = g->side[x];
+    sd.rev.alloc(sizeof(int32_t) * (size_t)m);
+    sd.lo.alloc(sizeof(int32_t) * (size_t)sd.n);
+    sd.work.alloc(sizeof(int64_t) * (size_t)sd.n);
+    BFC_HIP(hipMemsetAsync(sd.lo.p, 0, sizeof(int32_t) * (size_t)sd.n, s));
+    BFC_HIP(hipMemsetAsync(sd.work.p, 0, sizeof(int64_t) * (size_t)sd.n, s));
+  }
+  g->eslot.alloc(sizeof(int32_t) * (size_t)m);
+  if (m > 0) {
+    link_kernel<<<grid_1d(m), 256, 0, s>>>(
+        edges, m, slot[0].as<int32_t>(), slot[1].as<int32_t>(), rank_of[0].as<int32_t>(), rank_of[1].as<int32_t>(),
+        deg[0].as<int32_t>(), deg[1].as<int32_t>(), g->side[0].off.as<int32_t>(), g->side[1].off.as<int32_t>(),
+        g->side[0].rev.as<int32_t>(), g->side[1].rev.as<int32_t>(), g->side[0].lo.as<int32_t>(),
+        g->side[1].lo.as<int32_t>(), g->side[0].work.as<unsigned long long>(),
+        g->side[1].work.as<unsigned long long>(), g->eslot.as<int32_t>());
+    BFC_LAUNCH_CHECK();
+  }
+  BFC_HIP(hipMemcpyAsync(st, status.p, sizeof(st), hipMemcpyDeviceToHost, s));
+  BFC_HIP(hipStreamSynchronize(s));
+  if (st[1]) throw Error{BFC_ERR_DUPLICATE_EDGE, "the edge list repeats an (upper, lower) pair"};
+}
+
+// ---------------------------------------------------------------- schedule
+namespace {
+
+// Classifies start (x, r): 0 = no pair can reach a count of 2, 1 = light, 2 = heavy.
+// sums: [0] |W|, [1] max prefix of a heavy start, [2] light wedges,
+// [3] heavy wedges, [4] light middles, [5] heavy middles, [6] max start wedges
+__global__ void classify_kernel(const int64_t* __restrict__ work0, const int32_t* __restrict__ lo0, int32_t n0,
+                                const int64_t* __restrict__ work1, const int32_t* __restrict__ lo1, int32_t n1,
+                                int64_t light_max, int32_t* __restrict__ is_light, int32_t* __restrict__ is_heavy,
+                                unsigned long long* __restrict__ sums) {
+  const int64_t n = (int64_t)n0 + n1;
+  unsigned long long s_all = 0, s_lw = 0, s_hw = 0, s_lm = 0, s_hm = 0, max_w = 0;
+  int32_t max_pre = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t w = i < n0 ? work0[i] : work1[i - n0];
+    const int32_t pre = i < n0 ? lo0[i] : lo1[i - n0];
+    const bool light = w >= 2 && w <= light_max;
+    const bool heavy = w > light_max;
+    s_all += (unsigned long long)w;
+    is_light[i] = light ? 1 : 0;
+    is_heavy[i] = heavy ? 1 : 0;
+    if (light) { s_lw += (unsigned long long)w; s_lm += (unsigned long long)pre; }
+    if (heavy) {
+      s_hw += (unsigned long long)w;
+      s_hm += (unsigned long long)pre;
+      max_pre = pre > max_pre ? pre : max_pre;
+    }
+    max_w = (unsigned long long)w > max_w ? (unsigned long long)w : max_w;
+  }
+  s_all = wave_sum(s_all);
+  s_lw = wave_sum(s_lw);
+  s_hw = wave_sum(s_hw);
+  s_lm = wave_sum(s_lm);
+  s_hm = wave_sum(s_hm);
+  if (__lane_id() == 0) {
+    if (s_all) atomicAdd(&sums[0], s_all);
+    if (s_lw) atomicAdd(&sums[2], s_lw);
+    if (s_hw) atomicAdd(&sums[3], s_hw);
+    if (s_lm) atomicAdd(&sums[4], s_lm);
+    if (s_hm) atomicAdd(&sums[5], s_hm);
+  }
+  if (max_pre) atomicMax(&sums[1], (unsigned long long)max_pre);
+  if (max_w) atomicMax(&sums[6], max_w);
+}
+
+__global__ void compact_kernel(const int32_t* __restrict__ is_light, const int32_t* __restrict__ is_heavy,
+                               const int32_t* __restrict__ pos_light, const int32_t* __restrict__ pos_heavy,
+                               int32_t n0, int32_t n1, const int64_t* __restrict__ work0,
+                               const int64_t* __restrict__ work1, int32_t* __restrict__ light,
+                               int32_t* __restrict__ heavy, uint32_t* __restrict__ heavy_key) {
+  const int64_t n = (int64_t)n0 + n1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t code = i < n0 ? (int32_t)i : (int32_t)((1u << 30) | (uint32_t)(i - n0));
+    if (is_light[i]) light[pos_light[i]] = code;
+    if (is_heavy[i]) {
+      const int64_t w = i < n0 ? work0[i] : work1[i - n0];
+      heavy[pos_heavy[i]] = code;
+      heavy_key[pos_heavy[i]] = 0xFFFFFFFFu - (uint32_t)w;  // ascending key = descending work
+    }
+  }
+}
+
+}  // namespace
+
+void build_schedule(bfc_graph_s* g, hipStream_t s) {
+  Schedule& sc = g->sched;
+  const int32_t n0 = g->side[0].n, n1 = g->side[1].n;
+  const int64_t n = (int64_t)n0 + n1;
+  TmpBuf flags_l, flags_h, pos_l, pos_h, sums;
+  flags_l.alloc(sizeof(int32_t) * (size_t)n, s);
+  flags_h.alloc(sizeof(int32_t) * (size_t)n, s);
+  pos_l.alloc(sizeof(int32_t) * (size_t)(n + 1), s);
+  pos_h.alloc(sizeof(int32_t) * (size_t)(n + 1), s);
+  sums.alloc(8 * sizeof(int64_t), s);
+  BFC_HIP(hipMemsetAsync(sums.p, 0, 8 * sizeof(int64_t), s));
+  const int64_t light_max = g->tune.light_max_wedges;
+  if (n > 0) {
+    classify_kernel<<<grid_1d(n), 256, 0, s>>>(g->side[0].work.as<int64_t>(), g->side[0].lo.as<int32_t>(), n0,
+                                                g->side[1].work.as<int64_t>(), g->side[1].lo.as<int32_t>(), n1,
+                                                light_max, flags_l.as<int32_t>(), flags_h.as<int32_t>(),
+                                                sums.as<unsigned long long>());
+    BFC_LAUNCH_CHECK();
+  }
+  exclusive_scan_i32(flags_l.as<int32_t>(), pos_l.as<int32_t>(), n, pos_l.as<int32_t>() + n, s);
+  exclusive_scan_i32(flags_h.as<int32_t>(), pos_h.as<int32_t>(), n, pos_h.as<int32_t>() + n, s);
+  int32_t counts[2] = {0, 0};
+  int64_t wsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  BFC_HIP(hipMemcpyAsync(&counts[0], pos_l.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  BFC_HIP(hipMemcpyAsync(&counts[1], pos_h.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  BFC_HIP(hipMemcpyAsync(wsum, sums.p, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BFC_HIP(hipStreamSynchronize(s));
+  sc.n_light = counts[0];
+  sc.n_heavy = counts[1];
+  sc.wedges = wsum[0];
+  sc.max_prefix = (int32_t)wsum[1];
+  sc.wedges_light = wsum[2];
+  sc.wedges_heavy = wsum[3];
+  sc.middles_light = wsum[4];
+  sc.middles_heavy = wsum[5];
+  sc.max_start_wedges = wsum[6];
+  sc.light_max = g->tune.light_max_wedges;
+  sc.light.alloc(sizeof(int32_t) * (size_t)sc.n_light);
+  sc.heavy.alloc(sizeof(int32_t) * (size_t)sc.n_heavy);
+  TmpBuf hkey, hkey_tmp, hval_tmp;
+  hkey.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
+  hkey_tmp.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
+  hval_tmp.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
+  if (n > 0) {
+    compact_kernel<<<grid_1d(n), 256, 0, s>>>(flags_l.as<int32_t>(), flags_h.as<int32_t>(), pos_l.as<int32_t>(),
+                                               pos_h.as<int32_t>(), n0, n1, g->side[0].work.as<int64_t>(),
+                                               g->side[1].work.as<int64_t>(), sc.light.as<int32_t>(),
+                                               sc.heavy.as<int32_t>(), hkey.as<uint32_t>());
+    BFC_LAUNCH_CHECK();
+  }
+  if (sc.n_heavy > 1) {
+    radix_sort_u32(hkey.as<uint32_t>(), sc.heavy.as<uint32_t>(), hkey_tmp.as<uint32_t>(), hval_tmp.as<uint32_t>(),
+                   sc.n_heavy, 32, s);
+  }
+  BFC_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace bfc

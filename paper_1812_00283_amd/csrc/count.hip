@@ -1,0 +1,597 @@
+// Wedge enumeration and counting: the hot loop of BFC-VP (Algorithm 2), its
+// per-edge second pass (Algorithm 4) and per-vertex counts (Lemma 1).
+//
+// For a start r of layer X (rank r in X's ascending priority order):
+//   middles  = the first lo_X[r] entries of N(r)             (p(v) < p(r))
+//   ends     = for middle v reached through slot k, the entries of N(v)
+//              before r, i.e. adj_other[off_other[v] .. rev_X[k])  (p(w) < p(r))
+// count_wedge(w) is accumulated on chip and each distinct end adds
+// C(count,2) = count(count-1)/2 (int64) to the total.  Ends are ranks of X,
+// all below r, so a window [lo, hi) of end ranks selects, in every middle's
+// (sorted) list, one contiguous sub-slice.
+//
+// Work split (from the per-start wedge counts computed at build time):
+//   light starts (2 <= wedges <= light_max): one wavefront each, with a
+//     wavefront-private LDS hash table of >= 2x the start's wedges.
+//   heavy starts (> light_max), in decreasing order of wedges: one 1024-thread
+//     workgroup each, taken from a global ticket.  The workgroup walks end-rank
+//     windows; per window it either keeps dense LDS counters (32K int32, when
+//     wedges >= range / dense_min_ratio) or an LDS hash table (16K entries;
+//     a window whose distinct ends would overfill it is halved and redone).
+//     Middles are processed 1024 at a time; a workgroup prefix sum of their
+//     slice lengths spreads the wedges evenly over the threads and each
+//     thread finds its middle by binary search in LDS, so global reads of
+//     end ids stay coalesced.
+// The count of a pair is final once its window has been walked, so the
+// per-edge and per-vertex second pass runs window by window.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace bfc {
+
+namespace {
+
+struct SideView {
+  const int32_t* off;
+  const int32_t* adj;
+  const int32_t* rev;
+  const int32_t* lo;
+  const int32_t* id_of;
+  const int64_t* work;
+};
+
+struct CountParams {
+  SideView sv[2];
+  const int32_t* list;
+  int32_t n_list;
+  int32_t mode;
+  unsigned long long* total;
+  unsigned long long* vout[2];
+  unsigned long long* acc[2];
+  int32_t* cursor;
+  int64_t cursor_stride;
+  unsigned int* ticket;
+  int32_t dense_ratio;
+  int32_t window_mode;
+  int32_t hash_window_wedges;
+};
+
+__device__ __forceinline__ SideView pick(const CountParams& p, int x) {
+  SideView s;
+  s.off = x ? p.sv[1].off : p.sv[0].off;
+  s.adj = x ? p.sv[1].adj : p.sv[0].adj;
+  s.rev = x ? p.sv[1].rev : p.sv[0].rev;
+  s.lo = x ? p.sv[1].lo : p.sv[0].lo;
+  s.id_of = x ? p.sv[1].id_of : p.sv[0].id_of;
+  s.work = x ? p.sv[1].work : p.sv[0].work;
+  return s;
+}
+
+__device__ __forceinline__ unsigned long long* pick_ptr(unsigned long long* const* a, int x) { return x ? a[1] : a[0]; }
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x *= 0x9E3779B1u;
+  return x ^ (x >> 15);
+}
+
+__device__ __forceinline__ unsigned long long choose2(int32_t c) {
+  return (unsigned long long)c * (unsigned long long)(c - 1) / 2ull;
+}
+
+// first index in [lo, hi) with a[index] >= key (a ascending), by galloping from lo
+__device__ __forceinline__ int32_t gallop_lower_bound(const int32_t* __restrict__ a, int32_t lo, int32_t hi,
+                                                      int32_t key) {
+  if (lo >= hi || a[lo] >= key) return lo;
+  int32_t prev = lo;  // a[prev] < key
+  int32_t step = 1;
+  while (prev + step < hi && a[prev + step] < key) {
+    prev += step;
+    step <<= 1;
+  }
+  int32_t l = prev + 1;
+  int32_t h = prev + step < hi ? prev + step : hi;
+  while (l < h) {
+    const int32_t mid = (l + h) >> 1;
+    if (a[mid] < key) l = mid + 1; else h = mid;
+  }
+  return l;
+}
+
+// ------------------------------------------------------------ light
+constexpr int kLightNT = 256;
+constexpr int kLightWaves = kLightNT / 64;
+constexpr int kLightCap = 2048;  // table entries per wavefront; light_max <= kLightCap / 2
+
+__device__ __forceinline__ void wave_hash_add(int32_t* keys, int32_t* cnt, uint32_t mask, int32_t w) {
+  const int32_t key = w + 1;
+  uint32_t h = mix32((uint32_t)w) & mask;
+  for (;;) {
+    const int32_t cur = keys[h];
+    if (cur == key) { atomicAdd(&cnt[h], 1); return; }
+    if (cur == 0) {
+      const int32_t old = atomicCAS(&keys[h], 0, key);
+      if (old == 0 || old == key) { atomicAdd(&cnt[h], 1); return; }
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__device__ __forceinline__ int32_t hash_get(const int32_t* keys, const int32_t* cnt, uint32_t mask, int32_t w) {
+  const int32_t key = w + 1;
+  uint32_t h = mix32((uint32_t)w) & mask;
+  while (keys[h] != key) h = (h + 1) & mask;
+  return cnt[h];
+}
+
+// Visits every wedge of a light start: fn(middle index j, middle v, end slot, end w).
+template <typename Fn>
+__device__ __forceinline__ void wave_for_wedges(const SideView& S, const SideView& O, int32_t base, int32_t pre,
+                                                Fn fn) {
+  const int lane = __lane_id();
+  for (int32_t mb = 0; mb < pre; mb += 64) {
+    const int32_t j = mb + lane;
+    int32_t s0 = 0, c = 0, v = 0;
+    if (j < pre) {
+      const int32_t k = base + j;
+      v = S.adj[k];
+      s0 = O.off[v];
+      c = S.rev[k] - s0;
+    }
+    const int32_t inc = wave_inclusive_scan(c);
+    const int32_t tot = __shfl(inc, 63, 64);
+    const int32_t exc = inc - c;
+    for (int32_t f0 = 0; f0 < tot; f0 += 64) {
+      const int32_t f = f0 + lane;
+      int jj = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int cand = jj + step;
+        const int32_t e = __shfl(exc, cand, 64);
+        if (e <= f) jj = cand;
+      }
+      const int32_t sj = __shfl(s0, jj, 64);
+      const int32_t ej = __shfl(exc, jj, 64);
+      const int32_t vj = __shfl(v, jj, 64);
+      if (f < tot) {
+        const int32_t slot = sj + (f - ej);
+        fn(mb + jj, vj, slot, O.adj[slot]);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
+  __shared__ int32_t tkeys[kLightWaves][kLightCap];
+  __shared__ int32_t tcnt[kLightWaves][kLightCap];
+  const int lane = __lane_id();
+  const int wv = threadIdx.x >> 6;
+  int32_t* keys = tkeys[wv];
+  int32_t* cnt = tcnt[wv];
+  for (int h = lane; h < kLightCap; h += 64) { keys[h] = 0; cnt[h] = 0; }
+  unsigned long long acc_total = 0;
+  const int mode = p.mode;
+  for (int64_t idx = (int64_t)blockIdx.x * kLightWaves + wv; idx < p.n_list;
+       idx += (int64_t)gridDim.x * kLightWaves) {
+    const int32_t code = p.list[idx];
+    const int x = (int)((uint32_t)code >> 30);
+    const int32_t r = code & ((1 << 30) - 1);
+    const SideView S = pick(p, x);
+    const SideView O = pick(p, 1 - x);
+    const int32_t base = S.off[r];
+    const int32_t pre = S.lo[r];
+    const int64_t W = S.work[r];
+    uint32_t cap = 64;
+    while ((int64_t)cap < 2 * W) cap <<= 1;
+    const uint32_t mask = cap - 1;
+    wave_for_wedges(S, O, base, pre, [&](int32_t, int32_t, int32_t, int32_t w) { wave_hash_add(keys, cnt, mask, w); });
+    unsigned long long a = 0;
+    if (mode == kVertex) {
+      unsigned long long* vs = pick_ptr(p.vout, x);
+      for (uint32_t h = lane; h < cap; h += 64) {
+        const int32_t c = cnt[h];
+        if (c > 1) {
+          const unsigned long long cc = choose2(c);
+          a += cc;
+          atomicAdd(&vs[S.id_of[keys[h] - 1]], cc);
+        }
+      }
+      a = wave_sum(a);
+      if (lane == 0 && a) atomicAdd(&vs[S.id_of[r]], a);
+    } else if (mode == kTotal) {
+      for (uint32_t h = lane; h < cap; h += 64) {
+        const int32_t c = cnt[h];
+        if (c > 1) a += choose2(c);
+      }
+      acc_total += a;
+    }
+    if (mode != kTotal) {
+      unsigned long long* vmid = pick_ptr(p.vout, 1 - x);
+      unsigned long long* acc_s = pick_ptr(p.acc, x);
+      unsigned long long* acc_o = pick_ptr(p.acc, 1 - x);
+      wave_for_wedges(S, O, base, pre, [&](int32_t j, int32_t v, int32_t slot, int32_t w) {
+        const int32_t d = hash_get(keys, cnt, mask, w) - 1;
+        if (d > 0) {
+          if (mode == kEdge) {
+            atomicAdd(&acc_o[slot], (unsigned long long)d);
+            atomicAdd(&acc_s[base + j], (unsigned long long)d);
+          } else {
+            atomicAdd(&vmid[O.id_of[v]], (unsigned long long)d);
+          }
+        }
+      });
+    }
+    for (uint32_t h = lane; h < cap; h += 64) { keys[h] = 0; cnt[h] = 0; }
+  }
+  if (mode == kTotal) {
+    acc_total = wave_sum(acc_total);
+    if (lane == 0 && acc_total) atomicAdd(p.total, acc_total);
+  }
+}
+
+// ------------------------------------------------------------ heavy
+constexpr int kHeavyNT = 1024;
+constexpr int kHeavyWaves = kHeavyNT / 64;
+constexpr int kTableWords = 32768;          // 128 KB of LDS
+constexpr int kHashCap = kTableWords / 2;   // keys | counts
+constexpr int kDenseWin = kTableWords;      // dense counters per window
+constexpr int kHashSingleMax = 8192;        // one hash window suffices below this many wedges
+
+__device__ __forceinline__ void block_hash_add(int32_t* table, uint32_t cap, int32_t w, int32_t* s_fill,
+                                               int32_t* s_over) {
+  int32_t* keys = table;
+  int32_t* cnt = table + cap;
+  const int32_t key = w + 1;
+  const uint32_t mask = cap - 1;
+  uint32_t h = mix32((uint32_t)w) & mask;
+  for (uint32_t probe = 0; probe < cap; ++probe) {
+    const int32_t cur = keys[h];
+    if (cur == key) { atomicAdd(&cnt[h], 1); return; }
+    if (cur == 0) {
+      const int32_t old = atomicCAS(&keys[h], 0, key);
+      if (old == 0) {
+        atomicAdd(&cnt[h], 1);
+        if (atomicAdd(s_fill, 1) >= (int32_t)(cap - cap / 4)) *s_over = 1;
+        return;
+      }
+      if (old == key) { atomicAdd(&cnt[h], 1); return; }
+    }
+    h = (h + 1) & mask;
+  }
+  *s_over = 1;
+}
+
+__device__ __forceinline__ int block_find_middle(const int32_t* s_exc, int nvalid, int32_t f) {
+  int lo = 0, hi = nvalid;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (s_exc[mid] <= f) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
+  __shared__ int32_t table[kTableWords];
+  __shared__ int32_t s_cs[kHeavyNT];
+  __shared__ int32_t s_exc[kHeavyNT];
+  __shared__ unsigned long long s_delta[kHeavyNT];
+  __shared__ int32_t s_red[kHeavyWaves + 1];
+  __shared__ unsigned long long s_red64[kHeavyWaves + 1];
+  __shared__ int32_t s_idx, s_fill, s_over;
+
+  const int t = threadIdx.x;
+  const int mode = p.mode;
+  int32_t* cur_in = p.cursor + (int64_t)blockIdx.x * 2 * p.cursor_stride;
+  int32_t* cur_out = cur_in + p.cursor_stride;
+  for (int i = t; i < kTableWords; i += kHeavyNT) table[i] = 0;
+  unsigned long long acc_total = 0;
+
+  for (;;) {
+    if (t == 0) s_idx = (int32_t)atomicAdd(p.ticket, 1u);
+    __syncthreads();
+    const int32_t idx = s_idx;
+    __syncthreads();
+    if (idx >= p.n_list) break;
+    const int32_t code = p.list[idx];
+    const int x = (int)((uint32_t)code >> 30);
+    const int32_t r = code & ((1 << 30) - 1);
+    const SideView S = pick(p, x);
+    const SideView O = pick(p, 1 - x);
+    const int32_t base = S.off[r];
+    const int32_t pre = S.lo[r];
+    const int64_t W = S.work[r];
+    const int32_t range = r;
+    const bool dense = p.window_mode == 2 || (p.window_mode == 1 && W * (int64_t)p.dense_ratio >= (int64_t)range);
+    int32_t width;
+    uint32_t cap = kHashCap;
+    if (dense) {
+      width = kDenseWin;
+    } else if (W <= kHashSingleMax) {
+      width = range;
+      cap = 512;
+      while ((int64_t)cap < 2 * W) cap <<= 1;
+    } else {
+      int64_t wd = (int64_t)range * p.hash_window_wedges / W;
+      width = (int32_t)(wd < 256 ? 256 : wd);
+    }
+    unsigned long long start_acc = 0;
+    int32_t lo_w = 0;
+    while (lo_w < range) {
+      int32_t hi_w = (int64_t)lo_w + width >= range ? range : lo_w + width;
+      bool multi = !(lo_w == 0 && hi_w == range);
+      // ---- pass 1: count the wedges whose end lies in [lo_w, hi_w)
+      for (;;) {
+        if (t == 0) { s_fill = 0; s_over = 0; }
+        __syncthreads();
+        for (int32_t c0 = 0; c0 < pre; c0 += kHeavyNT) {
+          const int32_t j = c0 + t;
+          int32_t cs = 0, ce = 0;
+          if (j < pre) {
+            const int32_t k = base + j;
+            const int32_t v = S.adj[k];
+            const int32_t e = S.rev[k];
+            cs = lo_w == 0 ? O.off[v] : cur_in[j];
+            ce = hi_w >= range ? e : gallop_lower_bound(O.adj, cs, e, hi_w);
+            if (multi) cur_out[j] = ce;
+          }
+          int32_t tot;
+          const int32_t exc = block_exclusive_scan<int32_t, kHeavyNT>(ce - cs, s_red, &tot);
+          s_cs[t] = cs;
+          s_exc[t] = exc;
+          __syncthreads();
+          const int nvalid = pre - c0 < kHeavyNT ? pre - c0 : kHeavyNT;
+          if (dense) {
+            for (int32_t f = t; f < tot; f += kHeavyNT) {
+              const int jj = block_find_middle(s_exc, nvalid, f);
+              const int32_t w = O.adj[s_cs[jj] + (f - s_exc[jj])];
+              atomicAdd(&table[w - lo_w], 1);
+            }
+          } else {
+            for (int32_t f = t; f < tot; f += kHeavyNT) {
+              if (*(volatile int32_t*)&s_over) break;
+              const int jj = block_find_middle(s_exc, nvalid, f);
+              const int32_t w = O.adj[s_cs[jj] + (f - s_exc[jj])];
+              block_hash_add(table, cap, w, &s_fill, &s_over);
+            }
+          }
+          __syncthreads();
+          if (!dense && s_over) break;
+        }
+        if (dense || !s_over) break;
+        // the window holds too many distinct ends for the table: halve it and redo
+        for (int i = t; i < (int)(2 * cap); i += kHeavyNT) table[i] = 0;
+        __syncthreads();
+        hi_w = lo_w + ((hi_w - lo_w) > 1 ? (hi_w - lo_w) / 2 : 1);
+        multi = true;
+      }
+      // ---- pass 2 (per-vertex / per-edge): count - 1 to both edges of every wedge
+      if (mode != kTotal) {
+        unsigned long long* acc_s = pick_ptr(p.acc, x);
+        unsigned long long* acc_o = pick_ptr(p.acc, 1 - x);
+        unsigned long long* vmid = pick_ptr(p.vout, 1 - x);
+        for (int32_t c0 = 0; c0 < pre; c0 += kHeavyNT) {
+          const int32_t j = c0 + t;
+          int32_t cs = 0, ce = 0, v = 0;
+          if (j < pre) {
+            const int32_t k = base + j;
+            v = S.adj[k];
+            cs = lo_w == 0 ? O.off[v] : cur_in[j];
+            ce = multi ? cur_out[j] : S.rev[k];
+          }
+          int32_t tot;
+          const int32_t exc = block_exclusive_scan<int32_t, kHeavyNT>(ce - cs, s_red, &tot);
+          s_cs[t] = cs;
+          s_exc[t] = exc;
+          s_delta[t] = 0;
+          __syncthreads();
+          const int nvalid = pre - c0 < kHeavyNT ? pre - c0 : kHeavyNT;
+          for (int32_t f = t; f < tot; f += kHeavyNT) {
+            const int jj = block_find_middle(s_exc, nvalid, f);
+            const int32_t slot = s_cs[jj] + (f - s_exc[jj]);
+            const int32_t w = O.adj[slot];
+            const int32_t c = dense ? table[w - lo_w] : hash_get(table, table + cap, cap - 1, w);
+            if (c > 1) {
+              const unsigned long long d = (unsigned long long)(c - 1);
+              if (mode == kEdge) atomicAdd(&acc_o[slot], d);
+              atomicAdd(&s_delta[jj], d);
+            }
+          }
+          __syncthreads();
+          if (j < pre && s_delta[t]) {
+            if (mode == kEdge) atomicAdd(&acc_s[base + j], s_delta[t]);
+            else atomicAdd(&vmid[O.id_of[v]], s_delta[t]);
+          }
+          __syncthreads();
+        }
+      }
+      // ---- finalize the window: C(count,2) per end, then clear the table
+      unsigned long long* vs = pick_ptr(p.vout, x);
+      if (dense) {
+        const int32_t wn = hi_w - lo_w;
+        for (int32_t i = t; i < wn; i += kHeavyNT) {
+          const int32_t c = table[i];
+          if (c) {
+            if (c > 1) {
+              const unsigned long long cc = choose2(c);
+              start_acc += cc;
+              if (mode == kVertex) atomicAdd(&vs[S.id_of[lo_w + i]], cc);
+            }
+            table[i] = 0;
+          }
+        }
+      } else {
+        for (uint32_t h = t; h < cap; h += kHeavyNT) {
+          const int32_t key = table[h];
+          if (key) {
+            const int32_t c = table[cap + h];
+            if (c > 1) {
+              const unsigned long long cc = choose2(c);
+              start_acc += cc;
+              if (mode == kVertex) atomicAdd(&vs[S.id_of[key - 1]], cc);
+            }
+            table[h] = 0;
+            table[cap + h] = 0;
+          }
+        }
+      }
+      __syncthreads();
+      if (multi) {
+        int32_t* tmp = cur_in;
+        cur_in = cur_out;
+        cur_out = tmp;
+      }
+      lo_w = hi_w;
+    }
+    if (mode == kVertex) {
+      const unsigned long long sa = block_sum<unsigned long long, kHeavyNT>(start_acc, s_red64);
+      if (t == 0 && sa) atomicAdd(&pick_ptr(p.vout, x)[S.id_of[r]], sa);
+    } else {
+      acc_total += start_acc;
+    }
+  }
+  if (mode == kTotal) {
+    const unsigned long long s = block_sum<unsigned long long, kHeavyNT>(acc_total, s_red64);
+    if (t == 0 && s) atomicAdd(p.total, s);
+  }
+}
+
+__global__ void fold_edges_kernel(const int32_t* __restrict__ eslot, const int32_t* __restrict__ rev0,
+                                  const unsigned long long* __restrict__ acc0,
+                                  const unsigned long long* __restrict__ acc1, int64_t m,
+                                  unsigned long long* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = eslot[i];
+    out[i] = acc0[a] + acc1[rev0[a]];
+  }
+}
+
+int num_cus() {
+  int dev = 0;
+  BFC_HIP(hipGetDevice(&dev));
+  int cus = 0;
+  BFC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  return cus > 0 ? cus : 1;
+}
+
+}  // namespace
+
+namespace {
+
+int heavy_grid_for(const bfc_graph_s* g) {
+  const int cus = num_cus();
+  return g->sched.n_heavy < cus ? g->sched.n_heavy : cus;
+}
+
+int64_t cursor_stride_for(const bfc_graph_s* g) { return ((int64_t)g->sched.max_prefix + 63) / 64 * 64; }
+
+__global__ void fill_zero_kernel(unsigned long long* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+}  // namespace
+
+void zero_u64(void* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t grid = (n + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  fill_zero_kernel<<<(unsigned)grid, 256, 0, s>>>(static_cast<unsigned long long*>(p), n);
+  BFC_LAUNCH_CHECK();
+}
+
+void prepare_count(bfc_graph_s* g) {
+  // two cursor arrays per heavy workgroup, then 256 bytes for the ticket
+  const size_t need = (size_t)heavy_grid_for(g) * 2 * (size_t)cursor_stride_for(g) * sizeof(int32_t) + 256;
+  if (g->scratch_bytes < need) {
+    g->scratch.alloc(need);
+    g->scratch_bytes = need;
+  }
+}
+
+void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, int64_t* out1, hipStream_t s) {
+  const Schedule& sc = g->sched;
+  const int cus = num_cus();
+  const int heavy_grid = heavy_grid_for(g);
+  const int64_t stride = cursor_stride_for(g);
+  int32_t* cursor = g->scratch.as<int32_t>();
+  unsigned int* ticket = reinterpret_cast<unsigned int*>(g->scratch.as<char>() + g->scratch_bytes - 256);
+
+  CountParams p{};
+  for (int x = 0; x < 2; ++x) {
+    p.sv[x].off = g->side[x].off.as<int32_t>();
+    p.sv[x].adj = g->side[x].adj.as<int32_t>();
+    p.sv[x].rev = g->side[x].rev.as<int32_t>();
+    p.sv[x].lo = g->side[x].lo.as<int32_t>();
+    p.sv[x].id_of = g->side[x].id_of.as<int32_t>();
+    p.sv[x].work = g->side[x].work.as<int64_t>();
+  }
+  p.mode = mode;
+  p.total = reinterpret_cast<unsigned long long*>(total_dev);
+  p.cursor = cursor;
+  p.cursor_stride = stride;
+  p.ticket = ticket;
+  p.dense_ratio = g->tune.dense_min_ratio;
+  p.window_mode = g->tune.window_mode;
+  p.hash_window_wedges = g->tune.hash_window_wedges;
+  if (mode == kVertex) {
+    p.vout[0] = reinterpret_cast<unsigned long long*>(out0);
+    p.vout[1] = reinterpret_cast<unsigned long long*>(out1);
+  } else if (mode == kEdge) {
+    const size_t need = sizeof(int64_t) * 2 * (size_t)(g->m > 0 ? g->m : 1);
+    if (g->acc.bytes < need) g->acc.alloc(need);
+    zero_u64(g->acc.p, 2 * g->m, s);
+    p.acc[0] = g->acc.as<unsigned long long>();
+    p.acc[1] = g->acc.as<unsigned long long>() + g->m;
+  }
+  if (sc.n_heavy > 0) zero_u64(ticket, 1, s);
+  bfc_graph_s::TimedCall tc{};
+  if (g->timing) {
+    for (int i = 0; i < 4; ++i) BFC_HIP(hipEventCreate(&tc.ev[i]));
+    BFC_HIP(hipEventRecord(tc.ev[0], s));
+  }
+  if (sc.n_light > 0) {
+    p.list = g->sched.light.as<int32_t>();
+    p.n_list = sc.n_light;
+    int64_t grid = ((int64_t)sc.n_light + kLightWaves - 1) / kLightWaves;
+    if (grid > (int64_t)cus * 16) grid = (int64_t)cus * 16;
+    light_kernel<<<(unsigned)grid, kLightNT, 0, s>>>(p);
+    BFC_LAUNCH_CHECK();
+  }
+  if (g->timing) BFC_HIP(hipEventRecord(tc.ev[1], s));
+  if (sc.n_heavy > 0) {
+    p.list = g->sched.heavy.as<int32_t>();
+    p.n_list = sc.n_heavy;
+    heavy_kernel<<<(unsigned)heavy_grid, kHeavyNT, 0, s>>>(p);
+    BFC_LAUNCH_CHECK();
+  }
+  if (g->timing) BFC_HIP(hipEventRecord(tc.ev[2], s));
+  if (mode == kEdge && g->m > 0) {
+    int64_t grid = (g->m + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    fold_edges_kernel<<<(unsigned)grid, 256, 0, s>>>(g->eslot.as<int32_t>(), g->side[0].rev.as<int32_t>(),
+                                                     p.acc[0], p.acc[1], g->m,
+                                                     reinterpret_cast<unsigned long long*>(out0));
+    BFC_LAUNCH_CHECK();
+  }
+  if (g->timing) {
+    BFC_HIP(hipEventRecord(tc.ev[3], s));
+    g->timed.push_back(tc);
+  }
+}
+
+void collect_times(bfc_graph_s* g) {
+  for (auto& tc : g->timed) {
+    BFC_HIP(hipEventSynchronize(tc.ev[3]));
+    float a = 0, b = 0, c = 0;
+    BFC_HIP(hipEventElapsedTime(&a, tc.ev[0], tc.ev[1]));
+    BFC_HIP(hipEventElapsedTime(&b, tc.ev[1], tc.ev[2]));
+    BFC_HIP(hipEventElapsedTime(&c, tc.ev[2], tc.ev[3]));
+    g->light_ms += a;
+    g->heavy_ms += b;
+    g->other_ms += c;
+    g->timed_calls += 1;
+    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(tc.ev[i]);
+  }
+  g->timed.clear();
+}
+
+}  // namespace bfc

@@ -1,0 +1,193 @@
+// Internal declarations shared by the HIP translation units of libbfc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <vector>
+#include <string>
+
+#include "bfc.h"
+
+namespace bfc {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------ errors
+struct Error {
+  bfc_status status;
+  std::string what;
+};
+
+void set_error(bfc_status s, const std::string& what);
+
+#define BFC_HIP(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) throw ::bfc::Error{e_ == hipErrorOutOfMemory ? BFC_ERR_OUT_OF_MEMORY \
+                                                                       : BFC_ERR_DEVICE,     \
+                                             std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define BFC_LAUNCH_CHECK() BFC_HIP(hipGetLastError())
+
+// ------------------------------------------------------------ memory
+// A device buffer owned by a graph handle or by a temporary scope.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) n = 256;
+    BFC_HIP(hipMalloc(&p, n));
+    bytes = n;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// A stream-ordered temporary: allocated and freed in order on one stream,
+// so it may go out of scope while kernels that use it are still queued.
+struct TmpBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t s = nullptr;
+  TmpBuf() = default;
+  TmpBuf(const TmpBuf&) = delete;
+  TmpBuf& operator=(const TmpBuf&) = delete;
+  ~TmpBuf() { release(); }
+  void alloc(size_t n, hipStream_t stream) {
+    release();
+    if (n == 0) n = 256;
+    s = stream;
+    BFC_HIP(hipMallocAsync(&p, n, s));
+    bytes = n;
+  }
+  void release() {
+    if (p) (void)hipFreeAsync(p, s);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------ graph
+// One layer's side of the relabelled graph: vertices of this layer in
+// ascending priority (local rank r), each with its neighbours' local ranks
+// in the other layer, ascending (so ascending priority).
+struct Side {
+  int32_t n = 0;
+  DevBuf off;      // int32 [n+1] CSR offsets by local rank
+  DevBuf adj;      // int32 [m] neighbour local ranks (other layer)
+  DevBuf rev;      // int32 [m] slot of the reverse arc in the other side's adj
+  DevBuf lo;       // int32 [n] number of neighbours with lower priority (a prefix of the list)
+  DevBuf id_of;    // int32 [n] local rank -> input id
+  DevBuf work;     // int64 [n] wedges Algorithm 2 processes from this start
+};
+
+struct Schedule {
+  int32_t n_light = 0;   // starts counted by one wavefront
+  int32_t n_heavy = 0;   // starts counted by one workgroup
+  DevBuf light;          // int32 codes (side << 30 | rank)
+  DevBuf heavy;          // int32 codes, by decreasing work
+  int64_t wedges = 0;    // |W|
+  int32_t max_prefix = 0;
+  int64_t wedges_light = 0, wedges_heavy = 0;
+  int64_t middles_light = 0, middles_heavy = 0;
+  int64_t max_start_wedges = 0;
+  int32_t light_max = 0; // threshold the lists were built with
+};
+
+struct Tuning {
+  int32_t light_max_wedges = 1024;
+  int32_t dense_min_ratio = 4;
+  int32_t window_mode = 1;  // 1 auto, 2 dense only, 3 hash only
+  int32_t hash_window_wedges = 4096;
+  int32_t dense_block = 0;
+};
+
+}  // namespace bfc
+
+struct bfc_graph_s {
+  int64_t m = 0;
+  int32_t n_upper = 0, n_lower = 0;
+  bfc::Side side[2];      // 0 = upper layer, 1 = lower layer
+  bfc::DevBuf eslot;      // int32 [m] slot of edge i in side[0].adj
+  bfc::Schedule sched;
+  bfc::Tuning tune;
+  bfc::DevBuf scratch;    // per-workgroup cursors and the work ticket of the count kernels
+  size_t scratch_bytes = 0;
+  bfc::DevBuf acc;        // int64 [2m] per-arc accumulators of the per-edge count (allocated on first use)
+  int device = 0;
+  // count calls share scratch: they are serialised on the device with `done`
+  std::mutex mu;
+  hipEvent_t done = nullptr;
+  hipStream_t last = nullptr;
+  bool used = false;
+  // optional kernel timing: events around the count kernels of each call
+  bool timing = false;
+  struct TimedCall { hipEvent_t ev[4]; };
+  std::vector<TimedCall> timed;
+  int64_t timed_calls = 0;
+  double light_ms = 0, heavy_ms = 0, other_ms = 0;
+  int64_t device_bytes() const;
+};
+
+namespace bfc {
+
+// ------------------------------------------------------------ primitives
+// Exclusive prefix sum of n values; `out` may alias `in`.  Returns the
+// total through total_dev (device, may be null).
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev, hipStream_t s);
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total_dev, hipStream_t s);
+void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs on bits [0, bits).  Sorted
+// output ends in keys/vals; tmp buffers must hold n elements.
+void radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp, int64_t n, int bits,
+                    hipStream_t s);
+void radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, int64_t n, int bits,
+                    hipStream_t s);
+
+// ------------------------------------------------------------ build and count
+void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s);
+void build_schedule(bfc_graph_s* g, hipStream_t s);
+
+enum CountMode { kTotal = 0, kVertex = 1, kEdge = 2 };
+// Runs the wedge kernels.  kTotal: adds B_G into total_dev.  kVertex: adds
+// per-vertex counts into out0 (upper, by id) and out1 (lower, by id), which
+// must be zeroed.  kEdge: writes per-edge counts into out0 (int64 [m]).
+void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, int64_t* out1, hipStream_t s);
+// Allocates the count kernels' scratch for the current schedule (not capture-safe; called at build).
+void prepare_count(bfc_graph_s* g);
+// Sums the durations of timed count calls (waits for them).
+void collect_times(bfc_graph_s* g);
+// Zero fill by kernel (safe inside captured graphs, unlike a memset node).
+void zero_u64(void* p, int64_t n, hipStream_t s);
+
+inline int bits_for(uint64_t x) {
+  int b = 0;
+  while (b < 64 && (x >> b)) ++b;
+  return b < 1 ? 1 : b;
+}
+
+inline unsigned grid_for(int64_t n, int per_block) {
+  int64_t g = (n + per_block - 1) / per_block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace bfc

@@ -1,0 +1,168 @@
+"""Parity of the HIP path with the CPU oracle (bit-exact: the path is integer).
+
+Every case runs bfc_build, bfc_count_total, bfc_count_per_vertex and
+bfc_count_per_edge through the C ABI and compares each output element by
+element with the oracle's plain definitions (Lemma 1, Eq. 8), and |W| with
+the oracle's count of the wedges Algorithm 2 processes.
+"""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+from gpu_util import check_against_oracle, gpu_all, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_paper_fig3(gpu_lib):
+    g = gg.paper_fig3()
+    tot, wed, up, lo, be = gpu_all(gpu_lib, g)
+    assert tot == 999000 and wed == 2000
+    assert up[0] == up[1] == lo[1000] == lo[1001] == 499500
+    assert (up[2:] == 999).all() and (lo[:1000] == 999).all() and (be == 999).all()
+    check_against_oracle(gpu_lib, g)
+
+
+def test_paper_fig2a(gpu_lib):
+    g = gg.paper_fig2a()
+    tot, wed, up, lo, be = gpu_all(gpu_lib, g)
+    assert tot == 0 and wed == 2000
+    assert not up.any() and not lo.any() and not be.any()
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (2, 2), (3, 5), (17, 9), (64, 64), (100, 300), (700, 20)])
+def test_complete_bipartite(gpu_lib, a, b):
+    g = gg.complete_bipartite(a, b)
+    c2 = lambda k: k * (k - 1) // 2
+    tot, wed, up, lo, be = gpu_all(gpu_lib, g)
+    assert tot == c2(a) * c2(b)
+    assert (up == (a - 1) * c2(b)).all() and (lo == (b - 1) * c2(a)).all()
+    assert (be == (a - 1) * (b - 1)).all()
+    assert wed == oracle.vp_wedges(g)
+
+
+def test_zero_butterfly_graphs(gpu_lib):
+    for g in [gg.even_cycle(3), gg.even_cycle(40), gg.random_forest(1, 500, 300), gg.random_forest(2, 50, 900)]:
+        tot, wed, up, lo, be = gpu_all(gpu_lib, g)
+        assert tot == 0 and not up.any() and not lo.any() and not be.any()
+        assert wed == oracle.vp_wedges(g)
+    tot, *_ = gpu_all(gpu_lib, gg.even_cycle(2))
+    assert tot == 1
+
+
+def test_random_tiny_graphs(gpu_lib):
+    rng = np.random.default_rng(77)
+    for i in range(120):
+        g = gg.random_small(9000 + i, int(rng.integers(1, 12)), int(rng.integers(1, 12)),
+                            float(rng.choice([0.2, 0.5, 0.8, 1.0])))
+        check_against_oracle(gpu_lib, g)
+
+
+def test_union_of_many_small_graphs(gpu_lib):
+    rng = np.random.default_rng(5)
+    parts, ou, ol = [], 0, 0
+    for i in range(1500):
+        nu, nl = int(rng.integers(1, 30)), int(rng.integers(1, 30))
+        g = gg.random_small(20000 + i, nu, nl, float(rng.uniform(0.05, 0.9)))
+        parts.append(g.edges + np.array([ou, ol], np.int32))
+        ou += nu
+        ol += nl
+    e = np.concatenate(parts)
+    e = e[np.random.default_rng(6).permutation(len(e))]
+    big = gg.Graph(np.ascontiguousarray(e), ou, ol, "union")
+    check_against_oracle(gpu_lib, big)
+
+
+def test_uniform_workload_2k_3k_20k(gpu_lib):
+    check_against_oracle(gpu_lib, gg.workload("uniform-2k-3k-20k"))
+
+
+@pytest.fixture(scope="module")
+def hub_graph():
+    # hubs in both layers, layers wider than one dense window (32K ranks)
+    return gg.chung_lu(31, 90_000, 70_000, 600_000, 2.0, 2.1, 4000.0, blocks=3, block=40, density=0.9, name="hubs")
+
+
+@pytest.fixture(scope="module")
+def hub_oracle(hub_graph):
+    g = hub_graph
+    up, lo = oracle.vertex_counts(g)
+    return oracle.total(g), oracle.vp_wedges(g), up, lo, oracle.edge_counts(g)
+
+
+TUNINGS = {
+    "default": {},
+    "all-workgroup": {"light_max_wedges": 1},
+    "dense-windows": {"light_max_wedges": 16, "window_mode": 2},
+    "hash-windows": {"light_max_wedges": 16, "window_mode": 3},
+    "hash-tiny-windows": {"light_max_wedges": 1, "window_mode": 3, "hash_window_wedges": 64},
+    "hash-overfull": {"light_max_wedges": 64, "window_mode": 3, "hash_window_wedges": 1 << 30},
+    "dense-ratio-1": {"dense_min_ratio": 1},
+}
+
+
+@pytest.mark.parametrize("name", list(TUNINGS))
+def test_hub_graph_every_kernel_path(gpu_lib, hub_graph, hub_oracle, name):
+    tot, wed, up, lo, be = gpu_all(gpu_lib, hub_graph, TUNINGS[name] or None)
+    o_tot, o_wed, o_up, o_lo, o_be = hub_oracle
+    assert tot == o_tot and wed == o_wed
+    np.testing.assert_array_equal(up, o_up)
+    np.testing.assert_array_equal(lo, o_lo)
+    np.testing.assert_array_equal(be, o_be)
+
+
+def test_repeat_and_async_and_streams(gpu_lib, hub_graph, hub_oracle):
+    o_tot = hub_oracle[0]
+    with gpu_lib.Graph(to_dev(hub_graph), hub_graph.n_upper, hub_graph.n_lower) as h:
+        out = torch.zeros(1, dtype=torch.int64, device="cuda")
+        s2 = torch.cuda.Stream()
+        for _ in range(3):
+            assert h.count_total()[0] == o_tot
+            h.count_total_async(out)
+            torch.cuda.synchronize()
+            assert int(out.item()) == o_tot
+            assert h.count_total(stream=s2)[0] == o_tot
+        info = h.info()
+        assert info["m"] == hub_graph.m and info["wedges"] == hub_oracle[1]
+        assert info["device_bytes"] <= gpu_lib.estimate_device_bytes(hub_graph.m, hub_graph.n_upper,
+                                                                     hub_graph.n_lower)
+
+
+def test_empty_and_degenerate_inputs(gpu_lib):
+    empty = gg.Graph(np.zeros((0, 2), np.int32), 4, 7)
+    tot, wed, up, lo, be = gpu_all(gpu_lib, empty)
+    assert tot == 0 and wed == 0 and up.shape == (4,) and lo.shape == (7,) and be.shape == (0,)
+    nothing = gg.Graph(np.zeros((0, 2), np.int32), 0, 0)
+    tot, wed, up, lo, be = gpu_all(gpu_lib, nothing)
+    assert tot == 0 and up.shape == (0,) and lo.shape == (0,)
+    one = gg.from_pairs([(2, 3)], 5, 5)
+    tot, wed, up, lo, be = gpu_all(gpu_lib, one)
+    assert tot == 0 and wed == 0 and be.tolist() == [0]
+    star = gg.from_pairs([(0, v) for v in range(5000)], 1, 5000)
+    tot, wed, *_ = gpu_all(gpu_lib, star)
+    assert tot == 0 and wed == 0
+    # isolated vertices around a K_{3,3}
+    k = gg.complete_bipartite(3, 3)
+    iso = gg.Graph(k.edges + np.array([10, 20], np.int32), 40, 60)
+    tot, wed, up, lo, be = gpu_all(gpu_lib, iso)
+    assert tot == 9 and up[10:13].tolist() == [6, 6, 6] and up.sum() == 18 and (be == 4).all()
+
+
+def test_input_errors(gpu_lib):
+    bad = torch.tensor([[0, 0], [5, 1]], dtype=torch.int32, device="cuda")
+    with pytest.raises(gpu_lib.BfcError) as e:
+        gpu_lib.Graph(bad, 5, 5)
+    assert e.value.status == 2
+    neg = torch.tensor([[0, -1]], dtype=torch.int32, device="cuda")
+    with pytest.raises(gpu_lib.BfcError) as e:
+        gpu_lib.Graph(neg, 5, 5)
+    assert e.value.status == 2
+    dup = torch.tensor([[1, 2], [0, 0], [1, 2]], dtype=torch.int32, device="cuda")
+    with pytest.raises(gpu_lib.BfcError) as e:
+        gpu_lib.Graph(dup, 5, 5)
+    assert e.value.status == 3
+    # the library stays usable after errors
+    tot, *_ = gpu_all(gpu_lib, gg.complete_bipartite(4, 4))
+    assert tot == 36
