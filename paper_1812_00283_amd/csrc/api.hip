@@ -48,6 +48,23 @@ struct DeviceScope {
 
 void zero_i64(int64_t* p, int64_t n, hipStream_t s) { zero_u64(p, n, s); }
 
+std::mutex g_pool_mu;
+bool g_pool_warm[64] = {};
+
+}  // namespace
+
+void keep_pool_warm(int device) {
+  std::lock_guard<std::mutex> hold(g_pool_mu);
+  if (device < 0 || device >= 64 || g_pool_warm[device]) return;
+  hipMemPool_t pool = nullptr;
+  BFC_HIP(hipDeviceGetDefaultMemPool(&pool, device));
+  uint64_t threshold = UINT64_MAX;
+  BFC_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold));
+  g_pool_warm[device] = true;
+}
+
+namespace {
+
 bfc_graph_s* checked(bfc_graph g) {
   if (!g) throw Error{BFC_ERR_INVALID_ARGUMENT, "null graph handle"};
   return g;
@@ -125,9 +142,11 @@ bfc_status bfc_build(const int32_t* edges_dev, int64_t m, int32_t n_upper, int32
       g->m = m;
       g->n_upper = n_upper;
       g->n_lower = n_lower;
+      keep_pool_warm(g->device);
       build_graph(g, edges_dev, s);
       build_schedule(g, s);
-      prepare_count(g);
+      prepare_count(g, s);
+      BFC_HIP(hipStreamSynchronize(s));
     } catch (...) {
       if (g->done) (void)hipEventDestroy(g->done);
       delete g;
@@ -247,7 +266,8 @@ bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t) {
       if (h->used) BFC_HIP(hipEventSynchronize(h->done));
       BFC_HIP(hipDeviceSynchronize());
       build_schedule(h, nullptr);
-      prepare_count(h);
+      prepare_count(h, nullptr);
+      BFC_HIP(hipStreamSynchronize(nullptr));
     }
   });
 }

@@ -135,7 +135,7 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
     sd.n = n[x];
     const int64_t nx = n[x];
     TmpBuf keys, ktmp, vtmp;
-    sd.id_of.alloc(sizeof(uint32_t) * (size_t)nx);
+    sd.id_of.alloc(sizeof(uint32_t) * (size_t)nx, s);
     DevBuf& vals = sd.id_of;
     keys.alloc(sizeof(uint32_t) * (size_t)nx, s);
     ktmp.alloc(sizeof(uint32_t) * (size_t)nx, s);
@@ -154,7 +154,7 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
       invert_kernel<<<grid_1d(nx), 256, 0, s>>>(sd.id_of.as<uint32_t>(), rank_of[x].as<int32_t>(), nx);
       BFC_LAUNCH_CHECK();
     }
-    sd.off.alloc(sizeof(int32_t) * (size_t)(nx + 1));
+    sd.off.alloc(sizeof(int32_t) * (size_t)(nx + 1), s);
     exclusive_scan_i32(keys.as<int32_t>(), sd.off.as<int32_t>(), nx, sd.off.as<int32_t>() + nx, s);
   }
 
@@ -169,7 +169,7 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
     vtmp.alloc(sizeof(uint32_t) * (size_t)m, s);
     for (int x = 0; x < 2; ++x) {
       Side& sd = g->side[x];
-      sd.adj.alloc(sizeof(int32_t) * (size_t)m);
+      sd.adj.alloc(sizeof(int32_t) * (size_t)m, s);
       slot[x].alloc(sizeof(int32_t) * (size_t)m, s);
       if (m == 0) continue;
       const int bd = bits[1 - x];
@@ -188,13 +188,13 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
   // ---- reverse slots, lower-priority prefix lengths, per-start work
   for (int x = 0; x < 2; ++x) {
     Side& sd = g->side[x];
-    sd.rev.alloc(sizeof(int32_t) * (size_t)m);
-    sd.lo.alloc(sizeof(int32_t) * (size_t)sd.n);
-    sd.work.alloc(sizeof(int64_t) * (size_t)sd.n);
+    sd.rev.alloc(sizeof(int32_t) * (size_t)m, s);
+    sd.lo.alloc(sizeof(int32_t) * (size_t)sd.n, s);
+    sd.work.alloc(sizeof(int64_t) * (size_t)sd.n, s);
     BFC_HIP(hipMemsetAsync(sd.lo.p, 0, sizeof(int32_t) * (size_t)sd.n, s));
     BFC_HIP(hipMemsetAsync(sd.work.p, 0, sizeof(int64_t) * (size_t)sd.n, s));
   }
-  g->eslot.alloc(sizeof(int32_t) * (size_t)m);
+  g->eslot.alloc(sizeof(int32_t) * (size_t)m, s);
   if (m > 0) {
     link_kernel<<<grid_1d(m), 256, 0, s>>>(
         edges, m, slot[0].as<int32_t>(), slot[1].as<int32_t>(), rank_of[0].as<int32_t>(), rank_of[1].as<int32_t>(),
@@ -310,8 +310,8 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   sc.middles_heavy = wsum[5];
   sc.max_start_wedges = wsum[6];
   sc.light_max = g->tune.light_max_wedges;
-  sc.light.alloc(sizeof(int32_t) * (size_t)sc.n_light);
-  sc.heavy.alloc(sizeof(int32_t) * (size_t)sc.n_heavy);
+  sc.light.alloc(sizeof(int32_t) * (size_t)sc.n_light, s);
+  sc.heavy.alloc(sizeof(int32_t) * (size_t)sc.n_heavy, s);
   TmpBuf hkey, hkey_tmp, hval_tmp;
   hkey.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
   hkey_tmp.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);

@@ -97,11 +97,65 @@ __device__ __forceinline__ int32_t gallop_lower_bound(const int32_t* __restrict_
   return l;
 }
 
-// ------------------------------------------------------------ light
-constexpr int kLightNT = 256;
-constexpr int kLightWaves = kLightNT / 64;
-constexpr int kLightCap = 2048;  // table entries per wavefront; light_max <= kLightCap / 2
+// ------------------------------------------------------------ wavefront walk
+// Up to this many end-id loads are in flight per lane.
+constexpr int kInFlight = 4;
 
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_max(T v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T o = __shfl_up(v, d, 64);
+    if (lane >= d && o > v) v = o;
+  }
+  return v;
+}
+
+// Visits every wedge of a group of up to 64 middles.  Lane l holds middle l's
+// end slice [cs, cs + len) in adj_other.  Wedges are numbered 0..tot-1 in
+// middle order and the wavefront takes 64 consecutive numbers per step, so
+// consecutive lanes load consecutive end ids.  The middle of position f is
+// found without a search: lanes mark the positions where a middle starts
+// (wavefront-private LDS `mark`), a running maximum over lanes spreads each
+// middle to its positions, and a ballot gives the middle already open at the
+// step's first position.  fn(middle lane, slot, end) is called per wedge.
+template <typename Fn>
+__device__ __forceinline__ void wave_walk(const int32_t* __restrict__ oadj, int32_t cs, int32_t len,
+                                          int32_t* mark, Fn&& fn) {
+  const int lane = __lane_id();
+  const int32_t inc = wave_inclusive_scan(len);
+  const int32_t tot = __shfl(inc, 63, 64);
+  const int32_t exc = inc - len;
+  const bool open = len > 0;
+  for (int32_t f0 = 0; f0 < tot; f0 += 64 * kInFlight) {
+    int32_t slot[kInFlight];
+    int mid[kInFlight];
+    int32_t w[kInFlight];
+#pragma unroll
+    for (int q = 0; q < kInFlight; ++q) {
+      const int32_t fb = f0 + 64 * q;
+      const uint64_t before = __ballot(open && exc <= fb);
+      const int first = before ? 63 - __clzll(before) : 0;
+      mark[lane] = -1;
+      __builtin_amdgcn_wave_barrier();
+      if (open && exc > fb && exc < fb + 64) mark[exc - fb] = lane;
+      __builtin_amdgcn_wave_barrier();
+      int mk = mark[lane];
+      __builtin_amdgcn_wave_barrier();
+      mk = wave_inclusive_max(mk > first ? mk : first);
+      mid[q] = mk;
+      slot[q] = __shfl(cs, mk, 64) + (fb + lane - __shfl(exc, mk, 64));
+    }
+#pragma unroll
+    for (int q = 0; q < kInFlight; ++q) w[q] = (f0 + 64 * q + lane < tot) ? oadj[slot[q]] : -1;
+#pragma unroll
+    for (int q = 0; q < kInFlight; ++q)
+      if (w[q] >= 0) fn(mid[q], slot[q], w[q]);
+  }
+}
+
+// ------------------------------------------------------------ hash tables
 __device__ __forceinline__ void wave_hash_add(int32_t* keys, int32_t* cnt, uint32_t mask, int32_t w) {
   const int32_t key = w + 1;
   uint32_t h = mix32((uint32_t)w) & mask;
@@ -123,51 +177,24 @@ __device__ __forceinline__ int32_t hash_get(const int32_t* keys, const int32_t* 
   return cnt[h];
 }
 
-// Visits every wedge of a light start: fn(middle index j, middle v, end slot, end w).
-template <typename Fn>
-__device__ __forceinline__ void wave_for_wedges(const SideView& S, const SideView& O, int32_t base, int32_t pre,
-                                                Fn fn) {
-  const int lane = __lane_id();
-  for (int32_t mb = 0; mb < pre; mb += 64) {
-    const int32_t j = mb + lane;
-    int32_t s0 = 0, c = 0, v = 0;
-    if (j < pre) {
-      const int32_t k = base + j;
-      v = S.adj[k];
-      s0 = O.off[v];
-      c = S.rev[k] - s0;
-    }
-    const int32_t inc = wave_inclusive_scan(c);
-    const int32_t tot = __shfl(inc, 63, 64);
-    const int32_t exc = inc - c;
-    for (int32_t f0 = 0; f0 < tot; f0 += 64) {
-      const int32_t f = f0 + lane;
-      int jj = 0;
-#pragma unroll
-      for (int step = 32; step >= 1; step >>= 1) {
-        const int cand = jj + step;
-        const int32_t e = __shfl(exc, cand, 64);
-        if (e <= f) jj = cand;
-      }
-      const int32_t sj = __shfl(s0, jj, 64);
-      const int32_t ej = __shfl(exc, jj, 64);
-      const int32_t vj = __shfl(v, jj, 64);
-      if (f < tot) {
-        const int32_t slot = sj + (f - ej);
-        fn(mb + jj, vj, slot, O.adj[slot]);
-      }
-    }
-  }
-}
+// ------------------------------------------------------------ light
+constexpr int kLightNT = 256;
+constexpr int kLightWaves = kLightNT / 64;
+constexpr int kLightCap = 2048;  // table entries per wavefront; light_max <= kLightCap / 2
 
 __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
   __shared__ int32_t tkeys[kLightWaves][kLightCap];
   __shared__ int32_t tcnt[kLightWaves][kLightCap];
+  __shared__ int32_t tmark[kLightWaves][64];
+  __shared__ unsigned long long tdelta[kLightWaves][64];
   const int lane = __lane_id();
   const int wv = threadIdx.x >> 6;
   int32_t* keys = tkeys[wv];
   int32_t* cnt = tcnt[wv];
+  int32_t* mark = tmark[wv];
+  unsigned long long* dsum = tdelta[wv];
   for (int h = lane; h < kLightCap; h += 64) { keys[h] = 0; cnt[h] = 0; }
+  dsum[lane] = 0;
   unsigned long long acc_total = 0;
   const int mode = p.mode;
   for (int64_t idx = (int64_t)blockIdx.x * kLightWaves + wv; idx < p.n_list;
@@ -183,7 +210,16 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
     uint32_t cap = 64;
     while ((int64_t)cap < 2 * W) cap <<= 1;
     const uint32_t mask = cap - 1;
-    wave_for_wedges(S, O, base, pre, [&](int32_t, int32_t, int32_t, int32_t w) { wave_hash_add(keys, cnt, mask, w); });
+    for (int32_t j0 = 0; j0 < pre; j0 += 64) {
+      const int32_t j = j0 + lane;
+      int32_t cs = 0, len = 0;
+      if (j < pre) {
+        const int32_t k = base + j;
+        cs = O.off[S.adj[k]];
+        len = S.rev[k] - cs;
+      }
+      wave_walk(O.adj, cs, len, mark, [&](int, int32_t, int32_t w) { wave_hash_add(keys, cnt, mask, w); });
+    }
     unsigned long long a = 0;
     if (mode == kVertex) {
       unsigned long long* vs = pick_ptr(p.vout, x);
@@ -208,17 +244,31 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
       unsigned long long* vmid = pick_ptr(p.vout, 1 - x);
       unsigned long long* acc_s = pick_ptr(p.acc, x);
       unsigned long long* acc_o = pick_ptr(p.acc, 1 - x);
-      wave_for_wedges(S, O, base, pre, [&](int32_t j, int32_t v, int32_t slot, int32_t w) {
-        const int32_t d = hash_get(keys, cnt, mask, w) - 1;
-        if (d > 0) {
-          if (mode == kEdge) {
-            atomicAdd(&acc_o[slot], (unsigned long long)d);
-            atomicAdd(&acc_s[base + j], (unsigned long long)d);
-          } else {
-            atomicAdd(&vmid[O.id_of[v]], (unsigned long long)d);
-          }
+      for (int32_t j0 = 0; j0 < pre; j0 += 64) {
+        const int32_t j = j0 + lane;
+        int32_t cs = 0, len = 0, v = 0;
+        if (j < pre) {
+          const int32_t k = base + j;
+          v = S.adj[k];
+          cs = O.off[v];
+          len = S.rev[k] - cs;
         }
-      });
+        wave_walk(O.adj, cs, len, mark, [&](int mid, int32_t slot, int32_t w) {
+          const int32_t c = hash_get(keys, cnt, mask, w);
+          if (c > 1) {
+            const unsigned long long d = (unsigned long long)(c - 1);
+            if (mode == kEdge) atomicAdd(&acc_o[slot], d);
+            atomicAdd(&dsum[mid], d);
+          }
+        });
+        __builtin_amdgcn_wave_barrier();
+        const unsigned long long d = dsum[lane];
+        if (d) {
+          if (mode == kEdge) atomicAdd(&acc_s[base + j], d);
+          else atomicAdd(&vmid[O.id_of[v]], d);
+          dsum[lane] = 0;
+        }
+      }
     }
     for (uint32_t h = lane; h < cap; h += 64) { keys[h] = 0; cnt[h] = 0; }
   }
@@ -233,7 +283,6 @@ constexpr int kHeavyNT = 1024;
 constexpr int kHeavyWaves = kHeavyNT / 64;
 constexpr int kTableWords = 32768;          // 128 KB of LDS
 constexpr int kHashCap = kTableWords / 2;   // keys | counts
-constexpr int kDenseWin = kTableWords;      // dense counters per window
 constexpr int kHashSingleMax = 8192;        // one hash window suffices below this many wedges
 
 __device__ __forceinline__ void block_hash_add(int32_t* table, uint32_t cap, int32_t w, int32_t* s_fill,
@@ -260,29 +309,35 @@ __device__ __forceinline__ void block_hash_add(int32_t* table, uint32_t cap, int
   *s_over = 1;
 }
 
-__device__ __forceinline__ int block_find_middle(const int32_t* s_exc, int nvalid, int32_t f) {
-  int lo = 0, hi = nvalid;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (s_exc[mid] <= f) lo = mid; else hi = mid;
-  }
-  return lo;
+// Dense window counters: 32-bit, or two 16-bit counters per word when every
+// count fits (a count is at most the start's number of middles).
+__device__ __forceinline__ void dense_add(int32_t* table, int32_t i, bool half) {
+  if (half) atomicAdd(reinterpret_cast<uint32_t*>(&table[i >> 1]), 1u << ((i & 1) << 4));
+  else atomicAdd(&table[i], 1);
+}
+
+__device__ __forceinline__ int32_t dense_get(const int32_t* table, int32_t i, bool half) {
+  if (half) return (int32_t)((reinterpret_cast<const uint32_t*>(table)[i >> 1] >> ((i & 1) << 4)) & 0xFFFFu);
+  return table[i];
 }
 
 __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
   __shared__ int32_t table[kTableWords];
-  __shared__ int32_t s_cs[kHeavyNT];
-  __shared__ int32_t s_exc[kHeavyNT];
-  __shared__ unsigned long long s_delta[kHeavyNT];
-  __shared__ int32_t s_red[kHeavyWaves + 1];
+  __shared__ int32_t tmark[kHeavyWaves][64];
+  __shared__ unsigned long long tdelta[kHeavyWaves][64];
   __shared__ unsigned long long s_red64[kHeavyWaves + 1];
-  __shared__ int32_t s_idx, s_fill, s_over;
+  __shared__ int32_t s_idx, s_fill, s_over, s_next;
 
   const int t = threadIdx.x;
+  const int lane = __lane_id();
+  const int wv = t >> 6;
   const int mode = p.mode;
+  int32_t* mark = tmark[wv];
+  unsigned long long* dsum = tdelta[wv];
   int32_t* cur_in = p.cursor + (int64_t)blockIdx.x * 2 * p.cursor_stride;
   int32_t* cur_out = cur_in + p.cursor_stride;
   for (int i = t; i < kTableWords; i += kHeavyNT) table[i] = 0;
+  dsum[lane] = 0;
   unsigned long long acc_total = 0;
 
   for (;;) {
@@ -301,17 +356,18 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
     const int64_t W = S.work[r];
     const int32_t range = r;
     const bool dense = p.window_mode == 2 || (p.window_mode == 1 && W * (int64_t)p.dense_ratio >= (int64_t)range);
+    const bool half = dense && pre < 65536;
     int32_t width;
     uint32_t cap = kHashCap;
     if (dense) {
-      width = kDenseWin;
+      width = half ? 2 * kTableWords : kTableWords;
     } else if (W <= kHashSingleMax) {
       width = range;
       cap = 512;
       while ((int64_t)cap < 2 * W) cap <<= 1;
     } else {
-      int64_t wd = (int64_t)range * p.hash_window_wedges / W;
-      width = (int32_t)(wd < 256 ? 256 : wd);
+      const int64_t wd = (int64_t)range * p.hash_window_wedges / W;
+      width = (int32_t)(wd < 256 ? 256 : (wd > range ? range : wd));
     }
     unsigned long long start_acc = 0;
     int32_t lo_w = 0;
@@ -320,10 +376,15 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       bool multi = !(lo_w == 0 && hi_w == range);
       // ---- pass 1: count the wedges whose end lies in [lo_w, hi_w)
       for (;;) {
-        if (t == 0) { s_fill = 0; s_over = 0; }
+        if (t == 0) { s_fill = 0; s_over = 0; s_next = 0; }
         __syncthreads();
-        for (int32_t c0 = 0; c0 < pre; c0 += kHeavyNT) {
-          const int32_t j = c0 + t;
+        for (;;) {
+          int32_t g = 0;
+          if (lane == 0) g = atomicAdd(&s_next, 1);
+          g = __shfl(g, 0, 64);
+          const int32_t j0 = g * 64;
+          if (j0 >= pre) break;
+          const int32_t j = j0 + lane;
           int32_t cs = 0, ce = 0;
           if (j < pre) {
             const int32_t k = base + j;
@@ -333,29 +394,15 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
             ce = hi_w >= range ? e : gallop_lower_bound(O.adj, cs, e, hi_w);
             if (multi) cur_out[j] = ce;
           }
-          int32_t tot;
-          const int32_t exc = block_exclusive_scan<int32_t, kHeavyNT>(ce - cs, s_red, &tot);
-          s_cs[t] = cs;
-          s_exc[t] = exc;
-          __syncthreads();
-          const int nvalid = pre - c0 < kHeavyNT ? pre - c0 : kHeavyNT;
           if (dense) {
-            for (int32_t f = t; f < tot; f += kHeavyNT) {
-              const int jj = block_find_middle(s_exc, nvalid, f);
-              const int32_t w = O.adj[s_cs[jj] + (f - s_exc[jj])];
-              atomicAdd(&table[w - lo_w], 1);
-            }
+            wave_walk(O.adj, cs, ce - cs, mark, [&](int, int32_t, int32_t w) { dense_add(table, w - lo_w, half); });
           } else {
-            for (int32_t f = t; f < tot; f += kHeavyNT) {
-              if (*(volatile int32_t*)&s_over) break;
-              const int jj = block_find_middle(s_exc, nvalid, f);
-              const int32_t w = O.adj[s_cs[jj] + (f - s_exc[jj])];
-              block_hash_add(table, cap, w, &s_fill, &s_over);
-            }
+            wave_walk(O.adj, cs, ce - cs, mark,
+                      [&](int, int32_t, int32_t w) { block_hash_add(table, cap, w, &s_fill, &s_over); });
+            if (*(volatile int32_t*)&s_over) break;
           }
-          __syncthreads();
-          if (!dense && s_over) break;
         }
+        __syncthreads();
         if (dense || !s_over) break;
         // the window holds too many distinct ends for the table: halve it and redo
         for (int i = t; i < (int)(2 * cap); i += kHeavyNT) table[i] = 0;
@@ -368,8 +415,15 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         unsigned long long* acc_s = pick_ptr(p.acc, x);
         unsigned long long* acc_o = pick_ptr(p.acc, 1 - x);
         unsigned long long* vmid = pick_ptr(p.vout, 1 - x);
-        for (int32_t c0 = 0; c0 < pre; c0 += kHeavyNT) {
-          const int32_t j = c0 + t;
+        if (t == 0) s_next = 0;
+        __syncthreads();
+        for (;;) {
+          int32_t g = 0;
+          if (lane == 0) g = atomicAdd(&s_next, 1);
+          g = __shfl(g, 0, 64);
+          const int32_t j0 = g * 64;
+          if (j0 >= pre) break;
+          const int32_t j = j0 + lane;
           int32_t cs = 0, ce = 0, v = 0;
           if (j < pre) {
             const int32_t k = base + j;
@@ -377,41 +431,46 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
             cs = lo_w == 0 ? O.off[v] : cur_in[j];
             ce = multi ? cur_out[j] : S.rev[k];
           }
-          int32_t tot;
-          const int32_t exc = block_exclusive_scan<int32_t, kHeavyNT>(ce - cs, s_red, &tot);
-          s_cs[t] = cs;
-          s_exc[t] = exc;
-          s_delta[t] = 0;
-          __syncthreads();
-          const int nvalid = pre - c0 < kHeavyNT ? pre - c0 : kHeavyNT;
-          for (int32_t f = t; f < tot; f += kHeavyNT) {
-            const int jj = block_find_middle(s_exc, nvalid, f);
-            const int32_t slot = s_cs[jj] + (f - s_exc[jj]);
-            const int32_t w = O.adj[slot];
-            const int32_t c = dense ? table[w - lo_w] : hash_get(table, table + cap, cap - 1, w);
+          wave_walk(O.adj, cs, ce - cs, mark, [&](int mid, int32_t slot, int32_t w) {
+            const int32_t c = dense ? dense_get(table, w - lo_w, half) : hash_get(table, table + cap, cap - 1, w);
             if (c > 1) {
               const unsigned long long d = (unsigned long long)(c - 1);
               if (mode == kEdge) atomicAdd(&acc_o[slot], d);
-              atomicAdd(&s_delta[jj], d);
+              atomicAdd(&dsum[mid], d);
             }
+          });
+          __builtin_amdgcn_wave_barrier();
+          const unsigned long long d = dsum[lane];
+          if (d) {
+            if (mode == kEdge) atomicAdd(&acc_s[base + j], d);
+            else atomicAdd(&vmid[O.id_of[v]], d);
+            dsum[lane] = 0;
           }
-          __syncthreads();
-          if (j < pre && s_delta[t]) {
-            if (mode == kEdge) atomicAdd(&acc_s[base + j], s_delta[t]);
-            else atomicAdd(&vmid[O.id_of[v]], s_delta[t]);
-          }
-          __syncthreads();
         }
+        __syncthreads();
       }
       // ---- finalize the window: C(count,2) per end, then clear the table
       unsigned long long* vs = pick_ptr(p.vout, x);
       if (dense) {
         const int32_t wn = hi_w - lo_w;
-        for (int32_t i = t; i < wn; i += kHeavyNT) {
-          const int32_t c = table[i];
-          if (c) {
-            if (c > 1) {
-              const unsigned long long cc = choose2(c);
+        const int32_t words = half ? (wn + 1) >> 1 : wn;
+        for (int32_t i = t; i < words; i += kHeavyNT) {
+          const uint32_t word = (uint32_t)table[i];
+          if (word) {
+            if (half) {
+              const int32_t c0 = (int32_t)(word & 0xFFFFu), c1 = (int32_t)(word >> 16);
+              if (c0 > 1) {
+                const unsigned long long cc = choose2(c0);
+                start_acc += cc;
+                if (mode == kVertex) atomicAdd(&vs[S.id_of[lo_w + 2 * i]], cc);
+              }
+              if (c1 > 1) {
+                const unsigned long long cc = choose2(c1);
+                start_acc += cc;
+                if (mode == kVertex) atomicAdd(&vs[S.id_of[lo_w + 2 * i + 1]], cc);
+              }
+            } else if ((int32_t)word > 1) {
+              const unsigned long long cc = choose2((int32_t)word);
               start_acc += cc;
               if (mode == kVertex) atomicAdd(&vs[S.id_of[lo_w + i]], cc);
             }
@@ -498,11 +557,11 @@ void zero_u64(void* p, int64_t n, hipStream_t s) {
   BFC_LAUNCH_CHECK();
 }
 
-void prepare_count(bfc_graph_s* g) {
+void prepare_count(bfc_graph_s* g, hipStream_t s) {
   // two cursor arrays per heavy workgroup, then 256 bytes for the ticket
   const size_t need = (size_t)heavy_grid_for(g) * 2 * (size_t)cursor_stride_for(g) * sizeof(int32_t) + 256;
   if (g->scratch_bytes < need) {
-    g->scratch.alloc(need);
+    g->scratch.alloc(need, s);
     g->scratch_bytes = need;
   }
 }
@@ -537,7 +596,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     p.vout[1] = reinterpret_cast<unsigned long long*>(out1);
   } else if (mode == kEdge) {
     const size_t need = sizeof(int64_t) * 2 * (size_t)(g->m > 0 ? g->m : 1);
-    if (g->acc.bytes < need) g->acc.alloc(need);
+    if (g->acc.bytes < need) g->acc.alloc(need, s);
     zero_u64(g->acc.p, 2 * g->m, s);
     p.acc[0] = g->acc.as<unsigned long long>();
     p.acc[1] = g->acc.as<unsigned long long>() + g->m;

@@ -33,32 +33,33 @@ void set_error(bfc_status s, const std::string& what);
 #define BFC_LAUNCH_CHECK() BFC_HIP(hipGetLastError())
 
 // ------------------------------------------------------------ memory
-// A device buffer owned by a graph handle or by a temporary scope.
+// A device buffer owned by a graph handle.  Allocated in stream order from
+// the device's default memory pool (kept warm, so rebuilding a graph does not
+// go back to the driver); freed when the handle is destroyed, after all work
+// that uses it has completed.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
-  DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
-    return *this;
-  }
   ~DevBuf() { release(); }
-  void alloc(size_t n) {
+  void alloc(size_t n, hipStream_t s) {
     release();
     if (n == 0) n = 256;
-    BFC_HIP(hipMalloc(&p, n));
+    BFC_HIP(hipMallocAsync(&p, n, s));
     bytes = n;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, nullptr);
     p = nullptr;
     bytes = 0;
   }
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
+
+// Keeps freed pool memory cached on the device (called once per device).
+void keep_pool_warm(int device);
 
 // A stream-ordered temporary: allocated and freed in order on one stream,
 // so it may go out of scope while kernels that use it are still queued.
@@ -172,8 +173,9 @@ enum CountMode { kTotal = 0, kVertex = 1, kEdge = 2 };
 // per-vertex counts into out0 (upper, by id) and out1 (lower, by id), which
 // must be zeroed.  kEdge: writes per-edge counts into out0 (int64 [m]).
 void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, int64_t* out1, hipStream_t s);
-// Allocates the count kernels' scratch for the current schedule (not capture-safe; called at build).
-void prepare_count(bfc_graph_s* g);
+// Allocates the count kernels' scratch for the current schedule on stream s
+// (not capture-safe; called when a schedule is built).
+void prepare_count(bfc_graph_s* g, hipStream_t s);
 // Sums the durations of timed count calls (waits for them).
 void collect_times(bfc_graph_s* g);
 // Zero fill by kernel (safe inside captured graphs, unlike a memset node).
