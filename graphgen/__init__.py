@@ -189,6 +189,55 @@ def batch_specs(seed: int = BATCH_SEED, count: int = BATCH_COUNT, m_lo: int = 1_
     return specs
 
 
+def spec_graphs(specs: list[GraphSpec], threads: int = 16) -> list[Graph]:
+    """Generates many graphs in parallel (each from its own seed, so the
+    result does not depend on the thread count)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    _load()
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        return list(ex.map(spec_graph, specs))
+
+
+@dataclass
+class Batch:
+    """Graphs laid out back to back: graph g owns edge rows [offsets[g], offsets[g+1])."""
+
+    edges: np.ndarray        # int32 [sum m, 2]
+    offsets: np.ndarray      # int64 [G+1]
+    n_upper: np.ndarray      # int32 [G]
+    n_lower: np.ndarray      # int32 [G]
+
+    @property
+    def count(self) -> int:
+        return len(self.n_upper)
+
+    def graph(self, g: int) -> Graph:
+        e = self.edges[self.offsets[g]:self.offsets[g + 1]]
+        return Graph(np.ascontiguousarray(e), int(self.n_upper[g]), int(self.n_lower[g]), f"g{g}")
+
+    def sha256(self) -> str:
+        h = hashlib.sha256()
+        for a in (self.offsets, self.n_upper, self.n_lower, self.edges):
+            h.update(np.ascontiguousarray(a).tobytes())
+        return h.hexdigest()
+
+
+def concat(graphs: list[Graph]) -> Batch:
+    offsets = np.zeros(len(graphs) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum([g.m for g in graphs])
+    edges = np.empty((int(offsets[-1]), 2), dtype=np.int32)
+    for i, g in enumerate(graphs):
+        edges[offsets[i]:offsets[i + 1]] = g.edges
+    return Batch(edges, offsets, np.array([g.n_upper for g in graphs], np.int32),
+                 np.array([g.n_lower for g in graphs], np.int32))
+
+
+def batch_workload(count: int = BATCH_COUNT, threads: int = 16) -> Batch:
+    """The batched workload: ``count`` graphs from batch_specs (seed 3)."""
+    return concat(spec_graphs(batch_specs(count=count), threads))
+
+
 def spec_graph(s: GraphSpec) -> Graph:
     if s.kind == "uniform":
         return uniform(s.seed, s.n_upper, s.n_lower, s.m, name=f"g{s.index}")

@@ -102,6 +102,44 @@ bfc_status bfc_count_per_vertex(bfc_graph g, void* stream, int64_t* upper_dev, i
  */
 bfc_status bfc_count_per_edge(bfc_graph g, void* stream, int64_t* edge_dev);
 
+/*
+ * Batched form: G independent graphs built into one handle and counted by
+ * one set of kernel launches.  Graph g's edges are rows
+ * [edge_offsets[g], edge_offsets[g+1]) of edges_dev, with its own 0-based
+ * ids (upper < n_upper[g], lower < n_lower[g]).  The handle stores the
+ * disjoint union of the graphs (graph g's ids shifted past those of graphs
+ * 0..g-1); Definition 3's order restricted to one graph is the same in the
+ * union, so every per-graph count and wedge total equals that of building
+ * the graph alone.  bfc_count_per_vertex / bfc_count_per_edge on a batch
+ * handle return the concatenation of the per-graph outputs (graph order).
+ *   edge_offsets_host  host int64 [G+1], non-decreasing, edge_offsets[0] = 0.
+ *   n_upper_host, n_lower_host  host int32 [G].
+ *   G >= 1; the total edge and vertex counts obey the limits of bfc_build.
+ * Synchronises `stream`.
+ */
+bfc_status bfc_build_batch(const int32_t* edges_dev, const int64_t* edge_offsets_host, const int32_t* n_upper_host,
+                           const int32_t* n_lower_host, int32_t G, void* stream, bfc_graph* out);
+
+/* Per-graph totals of a batch handle: totals_dev (device int64 [G], or [1]
+ * for a handle from bfc_build) receives B_G of every graph.  Asynchronous. */
+bfc_status bfc_count_total_batch(bfc_graph g, void* stream, int64_t* totals_dev);
+
+/* Per-graph processed-wedge counts |W| (host int64 [G]). */
+bfc_status bfc_batch_wedges(bfc_graph g, int64_t* wedges_host);
+
+/*
+ * Graph capture of the total count: records one bfc_count_total_batch(g, .,
+ * totals_dev) into a HIP graph owned by the handle (replacing an earlier
+ * one); bfc_graph_replay launches it on `stream`.  The captured work
+ * allocates nothing and records no memset nodes.  totals_dev must stay valid
+ * while the capture is in use.
+ */
+bfc_status bfc_graph_capture_total(bfc_graph g, void* stream, int64_t* totals_dev);
+bfc_status bfc_graph_replay(bfc_graph g, void* stream);
+
+/* Number of graphs in a handle (1 for bfc_build). */
+bfc_status bfc_graph_count(bfc_graph g, int32_t* graphs);
+
 /* Sizes of a built graph.  Any output pointer may be NULL.
  *   device_bytes  device memory the handle holds (CSR, maps, schedule, scratch). */
 bfc_status bfc_graph_info(bfc_graph g, int64_t* m, int32_t* n_upper, int32_t* n_lower, int64_t* wedges,

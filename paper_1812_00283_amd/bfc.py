@@ -31,6 +31,8 @@ EXPORTS = [
     "bfc_build", "bfc_count_total", "bfc_count_total_async", "bfc_count_per_vertex", "bfc_count_per_edge",
     "bfc_graph_info", "bfc_estimate_device_bytes", "bfc_destroy", "bfc_set_tuning", "bfc_get_tuning",
     "bfc_last_error", "bfc_version", "bfc_get_schedule_info", "bfc_set_kernel_timing", "bfc_get_kernel_times",
+    "bfc_build_batch", "bfc_count_total_batch", "bfc_batch_wedges", "bfc_graph_capture_total", "bfc_graph_replay",
+    "bfc_graph_count",
 ]
 
 
@@ -82,6 +84,12 @@ def load(path: str | None = None):
         "bfc_get_schedule_info": ([vp, ctypes.POINTER(ScheduleInfo)], i32),
         "bfc_set_kernel_timing": ([vp, i32], i32),
         "bfc_get_kernel_times": ([vp, ctypes.POINTER(KernelTimes)], i32),
+        "bfc_build_batch": ([vp, vp, vp, vp, i32, vp, ctypes.POINTER(vp)], i32),
+        "bfc_count_total_batch": ([vp, vp, vp], i32),
+        "bfc_batch_wedges": ([vp, vp], i32),
+        "bfc_graph_capture_total": ([vp, vp, vp], i32),
+        "bfc_graph_replay": ([vp, vp], i32),
+        "bfc_graph_count": ([vp, pi32], i32),
         "bfc_last_error": ([], ctypes.c_char_p),
         "bfc_version": ([], ctypes.c_char_p),
     }
@@ -119,8 +127,9 @@ def estimate_device_bytes(m: int, n_upper: int, n_lower: int) -> int:
 class Graph:
     """A graph built on the GPU (``bfc_build``) and its count calls."""
 
-    def __init__(self, edges: torch.Tensor, n_upper: int, n_lower: int, stream=None):
+    def __init__(self, edges: torch.Tensor, n_upper: int, n_lower: int, stream=None, _batch=None):
         lib = load()
+        self.graphs = 1
         if not isinstance(edges, torch.Tensor) or edges.dtype != torch.int32 or not edges.is_cuda:
             raise TypeError("edges must be an int32 CUDA tensor of shape [m, 2]")
         if edges.dim() != 2 or edges.shape[1] != 2:
@@ -131,7 +140,20 @@ class Graph:
         self.n_lower = int(n_lower)
         self.device = edges.device
         h = ctypes.c_void_p()
-        _check(lib.bfc_build(_ptr(edges), self.m, self.n_upper, self.n_lower, _stream(stream), ctypes.byref(h)))
+        if _batch is None:
+            _check(lib.bfc_build(_ptr(edges), self.m, self.n_upper, self.n_lower, _stream(stream), ctypes.byref(h)))
+        else:
+            import numpy as np
+
+            eoff, nus, nls = _batch
+            eoff = np.ascontiguousarray(eoff, dtype=np.int64)
+            nus = np.ascontiguousarray(nus, dtype=np.int32)
+            nls = np.ascontiguousarray(nls, dtype=np.int32)
+            if eoff[-1] != self.m:
+                raise ValueError("edge offsets must end at the number of edges")
+            self.graphs = len(nus)
+            _check(lib.bfc_build_batch(_ptr(edges), eoff.ctypes.data, nus.ctypes.data, nls.ctypes.data,
+                                       self.graphs, _stream(stream), ctypes.byref(h)))
         self._h = h
 
     # -- counts -------------------------------------------------------
@@ -159,6 +181,28 @@ class Graph:
         out = torch.empty(self.m, dtype=torch.int64, device=self.device)
         _check(load().bfc_count_per_edge(self._h, _stream(stream), _ptr(out)))
         return out
+
+    def count_total_batch(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Per-graph totals (int64 CUDA tensor [graphs]); asynchronous."""
+        if out is None:
+            out = torch.empty(self.graphs, dtype=torch.int64, device=self.device)
+        _check(load().bfc_count_total_batch(self._h, _stream(stream), _ptr(out)))
+        return out
+
+    def batch_wedges(self):
+        import numpy as np
+
+        w = np.zeros(self.graphs, dtype=np.int64)
+        _check(load().bfc_batch_wedges(self._h, w.ctypes.data))
+        return w
+
+    def capture_total(self, out: torch.Tensor, stream=None) -> None:
+        """Captures the per-graph total count into a HIP graph held by the handle."""
+        self._captured_out = out
+        _check(load().bfc_graph_capture_total(self._h, _stream(stream), _ptr(out)))
+
+    def replay(self, stream=None) -> None:
+        _check(load().bfc_graph_replay(self._h, _stream(stream)))
 
     # -- info and tuning ------------------------------------------------
     def info(self) -> dict:
@@ -217,6 +261,12 @@ class Graph:
 # Module-level names matching the C entry points.
 def build(edges: torch.Tensor, n_upper: int, n_lower: int, stream=None) -> Graph:
     return Graph(edges, n_upper, n_lower, stream)
+
+
+def build_batch(edges: torch.Tensor, edge_offsets, n_upper, n_lower, stream=None) -> Graph:
+    """Batched build: graph g owns edge rows [edge_offsets[g], edge_offsets[g+1])."""
+    return Graph(edges, int(sum(int(x) for x in n_upper)), int(sum(int(x) for x in n_lower)), stream,
+                 _batch=(edge_offsets, n_upper, n_lower))
 
 
 def count_total(g: Graph, stream=None) -> tuple[int, int]:

@@ -91,10 +91,15 @@ struct CountSection {
   bfc_graph_s* g;
   hipStream_t s;
   std::unique_lock<std::mutex> hold;
+  bool capturing = false;
   CountSection(bfc_graph_s* h, hipStream_t stream) : g(h), s(stream), hold(h->mu) {
-    if (g->used && g->last != s) BFC_HIP(hipStreamWaitEvent(s, g->done, 0));
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    BFC_HIP(hipStreamIsCapturing(s, &cs));
+    capturing = cs != hipStreamCaptureStatusNone;
+    if (!capturing && g->used && g->last != s) BFC_HIP(hipStreamWaitEvent(s, g->done, 0));
   }
   void finish() {
+    if (capturing) return;
     BFC_HIP(hipEventRecord(g->done, s));
     g->last = s;
     g->used = true;
@@ -178,6 +183,107 @@ bfc_status bfc_count_total(bfc_graph g, void* stream, int64_t* total_host, int64
   });
 }
 
+bfc_status bfc_build_batch(const int32_t* edges_dev, const int64_t* edge_offsets_host, const int32_t* n_upper_host,
+                           const int32_t* n_lower_host, int32_t G, void* stream, bfc_graph* out) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    if (!out || !edge_offsets_host || !n_upper_host || !n_lower_host || G < 1)
+      throw Error{BFC_ERR_INVALID_ARGUMENT, "null batch description or G < 1"};
+    if (edge_offsets_host[0] != 0) throw Error{BFC_ERR_INVALID_ARGUMENT, "edge_offsets[0] must be 0"};
+    const int64_t m = edge_offsets_host[G];
+    if (m < 0) throw Error{BFC_ERR_INVALID_ARGUMENT, "negative edge count"};
+    if (m > 0 && !edges_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "edges_dev is null"};
+    if (m >= (int64_t(1) << 30)) throw Error{BFC_ERR_TOO_LARGE, "total edges must be below 2^30"};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bfc_graph_s* g = new bfc_graph_s();
+    try {
+      BFC_HIP(hipGetDevice(&g->device));
+      BFC_HIP(hipEventCreateWithFlags(&g->done, hipEventDisableTiming));
+      keep_pool_warm(g->device);
+      build_batch(g, edges_dev, edge_offsets_host, n_upper_host, n_lower_host, G, s);
+      build_schedule(g, s);
+      prepare_count(g, s);
+      BFC_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      if (g->done) (void)hipEventDestroy(g->done);
+      delete g;
+      throw;
+    }
+    *out = g;
+  });
+}
+
+bfc_status bfc_count_total_batch(bfc_graph g, void* stream, int64_t* totals_dev) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!totals_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "totals_dev is null"};
+    DeviceScope ds(h->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    CountSection cs(h, s);
+    zero_i64(totals_dev, h->n_graphs, s);
+    count(h, kTotal, nullptr, nullptr, nullptr, s, totals_dev);
+    cs.finish();
+  });
+}
+
+bfc_status bfc_batch_wedges(bfc_graph g, int64_t* wedges_host) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!wedges_host) throw Error{BFC_ERR_INVALID_ARGUMENT, "wedges_host is null"};
+    if (h->graph_wedges.empty()) wedges_host[0] = h->sched.wedges;
+    else for (int32_t i = 0; i < h->n_graphs; ++i) wedges_host[i] = h->graph_wedges[i];
+  });
+}
+
+bfc_status bfc_graph_count(bfc_graph g, int32_t* graphs) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!graphs) throw Error{BFC_ERR_INVALID_ARGUMENT, "graphs is null"};
+    *graphs = h->n_graphs;
+  });
+}
+
+bfc_status bfc_graph_capture_total(bfc_graph g, void* stream, int64_t* totals_dev) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!totals_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "totals_dev is null"};
+    DeviceScope ds(h->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> hold(h->mu);
+    if (h->used) BFC_HIP(hipEventSynchronize(h->done));
+    if (h->cap_exec) { (void)hipGraphExecDestroy(h->cap_exec); h->cap_exec = nullptr; }
+    if (h->cap_graph) { (void)hipGraphDestroy(h->cap_graph); h->cap_graph = nullptr; }
+    const bool timing = h->timing;
+    h->timing = false;
+    BFC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      zero_i64(totals_dev, h->n_graphs, s);
+      count(h, kTotal, nullptr, nullptr, nullptr, s, totals_dev);
+    } catch (...) {
+      hipGraph_t tmp = nullptr;
+      (void)hipStreamEndCapture(s, &tmp);
+      if (tmp) (void)hipGraphDestroy(tmp);
+      h->timing = timing;
+      throw;
+    }
+    h->timing = timing;
+    BFC_HIP(hipStreamEndCapture(s, &h->cap_graph));
+    BFC_HIP(hipGraphInstantiate(&h->cap_exec, h->cap_graph, nullptr, nullptr, 0));
+  });
+}
+
+bfc_status bfc_graph_replay(bfc_graph g, void* stream) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!h->cap_exec) throw Error{BFC_ERR_INVALID_ARGUMENT, "nothing captured on this handle"};
+    DeviceScope ds(h->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    CountSection cs(h, s);
+    BFC_HIP(hipGraphLaunch(h->cap_exec, s));
+    cs.finish();
+  });
+}
+
 bfc_status bfc_count_total_async(bfc_graph g, void* stream, int64_t* total_dev) {
   return guard([&] {
     bfc_graph_s* h = checked(g);
@@ -237,6 +343,8 @@ bfc_status bfc_destroy(bfc_graph g) {
       DeviceScope ds(g->device);
       if (g->used) BFC_HIP(hipEventSynchronize(g->done));
       collect_times(g);
+      if (g->cap_exec) (void)hipGraphExecDestroy(g->cap_exec);
+      if (g->cap_graph) (void)hipGraphDestroy(g->cap_graph);
       (void)hipEventDestroy(g->done);
       delete g;
     }

@@ -17,6 +17,8 @@
 //   work_X[r]   wedges Algorithm 2 processes from start r: for each middle v
 //               in the prefix, the ends are the entries of N(v) before r,
 //               i.e. rev[k] - off_other[v] of them.
+#include <vector>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -327,6 +329,113 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
     radix_sort_u32(hkey.as<uint32_t>(), sc.heavy.as<uint32_t>(), hkey_tmp.as<uint32_t>(), hval_tmp.as<uint32_t>(),
                    sc.n_heavy, 32, s);
   }
+  BFC_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------- batches
+namespace {
+
+// largest g in [0, G) with off[g] <= x (off non-decreasing, off[0] <= x)
+template <typename T>
+__device__ __forceinline__ int32_t graph_of(const T* __restrict__ off, int32_t G, T x) {
+  int32_t lo = 0, hi = G;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void shift_kernel(const int32_t* __restrict__ edges, int64_t m, const int64_t* __restrict__ eoff,
+                             int32_t G, const int32_t* __restrict__ uoff, const int32_t* __restrict__ loff,
+                             int32_t* __restrict__ out, int32_t* __restrict__ status) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t gi = graph_of<int64_t>(eoff, G, i);
+    const int2 e = reinterpret_cast<const int2*>(edges)[i];
+    const int32_t nu = uoff[gi + 1] - uoff[gi];
+    const int32_t nl = loff[gi + 1] - loff[gi];
+    int2 o;
+    if (e.x < 0 || e.x >= nu || e.y < 0 || e.y >= nl) {
+      atomicOr(&status[0], 1);
+      o.x = 0;
+      o.y = 0;
+    } else {
+      o.x = e.x + uoff[gi];
+      o.y = e.y + loff[gi];
+    }
+    reinterpret_cast<int2*>(out)[i] = o;
+  }
+}
+
+__global__ void gid_kernel(const int32_t* __restrict__ id_of, int32_t n, const int32_t* __restrict__ voff, int32_t G,
+                           int32_t* __restrict__ gid, const int64_t* __restrict__ work,
+                           unsigned long long* __restrict__ gw) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t gi = graph_of<int32_t>(voff, G, id_of[r]);
+    gid[r] = gi;
+    const int64_t w = work[r];
+    if (w) atomicAdd(&gw[gi], (unsigned long long)w);
+  }
+}
+
+}  // namespace
+
+void build_batch(bfc_graph_s* g, const int32_t* edges, const int64_t* eoff_host, const int32_t* nu_host,
+                 const int32_t* nl_host, int32_t G, hipStream_t s) {
+  std::vector<int32_t> uoff(G + 1, 0), loff(G + 1, 0);
+  int64_t su = 0, sl = 0;
+  for (int32_t i = 0; i < G; ++i) {
+    if (nu_host[i] < 0 || nl_host[i] < 0) throw Error{BFC_ERR_INVALID_ARGUMENT, "negative layer size in batch"};
+    if (eoff_host[i + 1] < eoff_host[i]) throw Error{BFC_ERR_INVALID_ARGUMENT, "edge offsets must not decrease"};
+    if (eoff_host[i + 1] - eoff_host[i] > (int64_t)nu_host[i] * nl_host[i])
+      throw Error{BFC_ERR_DUPLICATE_EDGE, "a graph of the batch has more edges than (upper, lower) pairs"};
+    su += nu_host[i];
+    sl += nl_host[i];
+    if (su >= (1 << 30) || sl >= (1 << 30)) throw Error{BFC_ERR_TOO_LARGE, "batch layers must stay below 2^30"};
+    uoff[i + 1] = (int32_t)su;
+    loff[i + 1] = (int32_t)sl;
+  }
+  const int64_t m = eoff_host[G];
+  g->m = m;
+  g->n_upper = (int32_t)su;
+  g->n_lower = (int32_t)sl;
+  g->n_graphs = G;
+  TmpBuf d_eoff, d_uoff, d_loff, shifted, status;
+  d_eoff.alloc(sizeof(int64_t) * (size_t)(G + 1), s);
+  d_uoff.alloc(sizeof(int32_t) * (size_t)(G + 1), s);
+  d_loff.alloc(sizeof(int32_t) * (size_t)(G + 1), s);
+  shifted.alloc(sizeof(int32_t) * 2 * (size_t)m, s);
+  status.alloc(4 * sizeof(int32_t), s);
+  BFC_HIP(hipMemcpyAsync(d_eoff.p, eoff_host, sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
+  BFC_HIP(hipMemcpyAsync(d_uoff.p, uoff.data(), sizeof(int32_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
+  BFC_HIP(hipMemcpyAsync(d_loff.p, loff.data(), sizeof(int32_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
+  BFC_HIP(hipMemsetAsync(status.p, 0, 4 * sizeof(int32_t), s));
+  if (m > 0) {
+    shift_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, d_eoff.as<int64_t>(), G, d_uoff.as<int32_t>(),
+                                             d_loff.as<int32_t>(), shifted.as<int32_t>(), status.as<int32_t>());
+    BFC_LAUNCH_CHECK();
+  }
+  int32_t st[4] = {0, 0, 0, 0};
+  BFC_HIP(hipMemcpyAsync(st, status.p, sizeof(st), hipMemcpyDeviceToHost, s));
+  BFC_HIP(hipStreamSynchronize(s));
+  if (st[0]) throw Error{BFC_ERR_VERTEX_OUT_OF_RANGE, "a batch edge has an id outside its graph's layers"};
+  build_graph(g, shifted.as<int32_t>(), s);
+  TmpBuf gw;
+  gw.alloc(sizeof(int64_t) * (size_t)G, s);
+  BFC_HIP(hipMemsetAsync(gw.p, 0, sizeof(int64_t) * (size_t)G, s));
+  const TmpBuf* voff[2] = {&d_uoff, &d_loff};
+  for (int x = 0; x < 2; ++x) {
+    Side& sd = g->side[x];
+    g->gid[x].alloc(sizeof(int32_t) * (size_t)sd.n, s);
+    if (sd.n > 0) {
+      gid_kernel<<<grid_1d(sd.n), 256, 0, s>>>(sd.id_of.as<int32_t>(), sd.n, voff[x]->as<int32_t>(), G,
+                                                g->gid[x].as<int32_t>(), sd.work.as<int64_t>(),
+                                                gw.as<unsigned long long>());
+      BFC_LAUNCH_CHECK();
+    }
+  }
+  g->graph_wedges.assign(G, 0);
+  BFC_HIP(hipMemcpyAsync(g->graph_wedges.data(), gw.p, sizeof(int64_t) * (size_t)G, hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
 }
 

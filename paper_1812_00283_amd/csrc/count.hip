@@ -54,7 +54,14 @@ struct CountParams {
   int32_t dense_ratio;
   int32_t window_mode;
   int32_t hash_window_wedges;
+  unsigned long long* gtotal;  // per-graph totals of a batch (kTotal), else null
+  const int32_t* gid[2];       // graph index of every rank, per layer (null: one graph)
 };
+
+__device__ __forceinline__ int32_t graph_index(const CountParams& p, int x, int32_t r) {
+  const int32_t* g = x ? p.gid[1] : p.gid[0];
+  return g ? g[r] : 0;
+}
 
 __device__ __forceinline__ SideView pick(const CountParams& p, int x) {
   SideView s;
@@ -238,7 +245,12 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
         const int32_t c = cnt[h];
         if (c > 1) a += choose2(c);
       }
-      acc_total += a;
+      if (p.gtotal) {
+        a = wave_sum(a);
+        if (lane == 0 && a) atomicAdd(&p.gtotal[graph_index(p, x, r)], a);
+      } else {
+        acc_total += a;
+      }
     }
     if (mode != kTotal) {
       unsigned long long* vmid = pick_ptr(p.vout, 1 - x);
@@ -272,7 +284,7 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
     }
     for (uint32_t h = lane; h < cap; h += 64) { keys[h] = 0; cnt[h] = 0; }
   }
-  if (mode == kTotal) {
+  if (mode == kTotal && p.total) {
     acc_total = wave_sum(acc_total);
     if (lane == 0 && acc_total) atomicAdd(p.total, acc_total);
   }
@@ -503,11 +515,14 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
     if (mode == kVertex) {
       const unsigned long long sa = block_sum<unsigned long long, kHeavyNT>(start_acc, s_red64);
       if (t == 0 && sa) atomicAdd(&pick_ptr(p.vout, x)[S.id_of[r]], sa);
+    } else if (mode == kTotal && p.gtotal) {
+      const unsigned long long sa = block_sum<unsigned long long, kHeavyNT>(start_acc, s_red64);
+      if (t == 0 && sa) atomicAdd(&p.gtotal[graph_index(p, x, r)], sa);
     } else {
       acc_total += start_acc;
     }
   }
-  if (mode == kTotal) {
+  if (mode == kTotal && p.total) {
     const unsigned long long s = block_sum<unsigned long long, kHeavyNT>(acc_total, s_red64);
     if (t == 0 && s) atomicAdd(p.total, s);
   }
@@ -566,7 +581,8 @@ void prepare_count(bfc_graph_s* g, hipStream_t s) {
   }
 }
 
-void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, int64_t* out1, hipStream_t s) {
+void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, int64_t* out1, hipStream_t s,
+           int64_t* gtotals) {
   const Schedule& sc = g->sched;
   const int cus = num_cus();
   const int heavy_grid = heavy_grid_for(g);
@@ -591,6 +607,12 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   p.dense_ratio = g->tune.dense_min_ratio;
   p.window_mode = g->tune.window_mode;
   p.hash_window_wedges = g->tune.hash_window_wedges;
+  if (gtotals) {
+    p.total = nullptr;
+    p.gtotal = reinterpret_cast<unsigned long long*>(gtotals);
+    p.gid[0] = g->gid[0].as<int32_t>();
+    p.gid[1] = g->gid[1].as<int32_t>();
+  }
   if (mode == kVertex) {
     p.vout[0] = reinterpret_cast<unsigned long long*>(out0);
     p.vout[1] = reinterpret_cast<unsigned long long*>(out1);

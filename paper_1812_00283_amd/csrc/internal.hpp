@@ -128,6 +128,13 @@ struct bfc_graph_s {
   int32_t n_upper = 0, n_lower = 0;
   bfc::Side side[2];      // 0 = upper layer, 1 = lower layer
   bfc::DevBuf eslot;      // int32 [m] slot of edge i in side[0].adj
+  // batches: graph index of every rank (per layer) and per-graph |W|
+  int32_t n_graphs = 1;
+  bfc::DevBuf gid[2];
+  std::vector<int64_t> graph_wedges;
+  // captured total count
+  hipGraph_t cap_graph = nullptr;
+  hipGraphExec_t cap_exec = nullptr;
   bfc::Schedule sched;
   bfc::Tuning tune;
   bfc::DevBuf scratch;    // per-workgroup cursors and the work ticket of the count kernels
@@ -172,7 +179,13 @@ enum CountMode { kTotal = 0, kVertex = 1, kEdge = 2 };
 // Runs the wedge kernels.  kTotal: adds B_G into total_dev.  kVertex: adds
 // per-vertex counts into out0 (upper, by id) and out1 (lower, by id), which
 // must be zeroed.  kEdge: writes per-edge counts into out0 (int64 [m]).
-void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, int64_t* out1, hipStream_t s);
+// gtotals (kTotal only): per-graph totals [n_graphs] instead of total_dev.
+void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, int64_t* out1, hipStream_t s,
+           int64_t* gtotals = nullptr);
+// Batch build: shifts each graph's ids into the union, validates them per
+// graph and builds the union; fills gid[] and graph_wedges.
+void build_batch(bfc_graph_s* g, const int32_t* edges, const int64_t* eoff_host, const int32_t* nu_host,
+                 const int32_t* nl_host, int32_t G, hipStream_t s);
 // Allocates the count kernels' scratch for the current schedule on stream s
 // (not capture-safe; called when a schedule is built).
 void prepare_count(bfc_graph_s* g, hipStream_t s);

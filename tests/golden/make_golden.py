@@ -8,6 +8,9 @@ list, the total, the number of wedges Algorithm 2 processes, SHA-256 digests
 of the per-vertex and per-edge int64 arrays (little-endian), and a seeded
 sample of individual values for readable failures.
 
+With the single argument ``batch-4096`` it writes ``batch.json`` instead: each
+graph's total and |W| for the 4,096-graph batch.
+
 For the 200M-edge workload the lower layer's per-vertex counts are taken from
 the per-edge counts by the identity 2 B_v = sum of B_e over the edges at v
 (each butterfly through v uses two of its edges); a walk started from that
@@ -30,6 +33,7 @@ import graphgen as gg  # noqa: E402
 import oracle  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "workloads.json")
+OUT_BATCH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "batch.json")
 SAMPLES = 64
 
 
@@ -89,7 +93,38 @@ def one(name: str) -> dict:
     return rec
 
 
+def batch(name: str = "batch-4096") -> dict:
+    """Per-graph totals and |W| of the 4,096-graph batch (seed 3), each graph
+    counted on its own by the oracle (threads over graphs, one OpenMP thread each)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    b = gg.batch_workload()
+    log(f"{name}: generated {b.count} graphs, {int(b.offsets[-1])} edges")
+    graphs = [b.graph(i) for i in range(b.count)]
+    order = sorted(range(b.count), key=lambda i: -graphs[i].m)
+    totals = [0] * b.count
+    wedges = [0] * b.count
+
+    def one_graph(i):
+        totals[i] = oracle.total(graphs[i], nthreads=1)
+        wedges[i] = oracle.vp_wedges(graphs[i], nthreads=1)
+
+    with ThreadPoolExecutor(max_workers=oracle.threads()) as ex:
+        for k, _ in enumerate(ex.map(one_graph, order)):
+            if k % 256 == 0:
+                log(f"  {k}/{b.count} graphs")
+    return {"sha256": b.sha256(), "graphs": b.count, "edges": int(b.offsets[-1]), "totals": totals,
+            "vp_wedges": wedges}
+
+
 def main(names: list[str]) -> None:
+    if names == ["batch-4096"]:
+        rec = batch("batch-4096")
+        with open(OUT_BATCH, "w") as f:
+            json.dump({"_about": "Oracle per-graph totals and |W| for the 4,096-graph batch, written by "
+                                 "tests/golden/make_golden.py", "batch-4096": rec}, f)
+            f.write("\n")
+        return
     data = {}
     if os.path.exists(OUT):
         with open(OUT) as f:

@@ -1,0 +1,109 @@
+"""Batched form: many graphs in one handle, counted by one set of launches.
+
+Per-graph totals and |W| from bfc_build_batch / bfc_count_total_batch must
+equal the oracle's per-graph values, and equal a one-graph-per-handle loop
+(bfc_build + bfc_count_total).  The captured HIP graph replays must give
+the same totals every time, with eager work in between.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "batch.json")
+
+
+def small_batch(count=60, seed=11):
+    rng = np.random.default_rng(seed)
+    graphs = []
+    for i in range(count):
+        kind = i % 4
+        if kind == 0:
+            g = gg.random_small(seed * 1000 + i, int(rng.integers(1, 25)), int(rng.integers(1, 25)), 0.4)
+        elif kind == 1:
+            g = gg.complete_bipartite(int(rng.integers(1, 20)), int(rng.integers(1, 20)))
+        elif kind == 2:
+            g = gg.chung_lu(seed * 1000 + i, 3000, 2000, int(rng.integers(1000, 30000)), 2.1, 2.1, 800.0)
+        else:
+            g = gg.Graph(np.zeros((0, 2), np.int32), int(rng.integers(0, 5)), int(rng.integers(0, 5)))
+        graphs.append(g)
+    return graphs
+
+
+def test_small_batch_matches_oracle_and_plain_loop(gpu_lib):
+    graphs = small_batch()
+    b = gg.concat(graphs)
+    with gpu_lib.build_batch(torch.from_numpy(b.edges).cuda(), b.offsets, b.n_upper, b.n_lower) as h:
+        totals = h.count_total_batch().cpu().numpy()
+        wedges = h.batch_wedges()
+        up, lo = h.count_per_vertex()
+        be = h.count_per_edge()
+        up, lo, be = up.cpu().numpy(), lo.cpu().numpy(), be.cpu().numpy()
+    ou = ol = 0
+    for i, g in enumerate(graphs):
+        assert totals[i] == oracle.total(g), i
+        assert wedges[i] == oracle.vp_wedges(g), i
+        o_up, o_lo = oracle.vertex_counts(g)
+        np.testing.assert_array_equal(up[ou:ou + g.n_upper], o_up)
+        np.testing.assert_array_equal(lo[ol:ol + g.n_lower], o_lo)
+        np.testing.assert_array_equal(be[b.offsets[i]:b.offsets[i + 1]], oracle.edge_counts(g))
+        ou += g.n_upper
+        ol += g.n_lower
+        if g.m:
+            with gpu_lib.Graph(torch.from_numpy(g.edges).cuda(), g.n_upper, g.n_lower) as p:
+                assert p.count_total() == (int(totals[i]), int(wedges[i]))
+
+
+def test_batch_errors(gpu_lib):
+    e = torch.tensor([[0, 0], [1, 1], [2, 0]], dtype=torch.int32, device="cuda")
+    with pytest.raises(gpu_lib.BfcError) as err:   # edge 2 is outside graph 1's upper layer
+        gpu_lib.build_batch(e, [0, 2, 3], [2, 2], [2, 2])
+    assert err.value.status == 2
+    with pytest.raises(gpu_lib.BfcError) as err:   # duplicate inside graph 0
+        gpu_lib.build_batch(torch.tensor([[0, 0], [0, 0]], dtype=torch.int32, device="cuda"), [0, 2], [2], [2])
+    assert err.value.status == 3
+
+
+def test_capture_and_replay(gpu_lib):
+    graphs = small_batch(40, seed=12)
+    b = gg.concat(graphs)
+    expect = np.array([oracle.total(g) for g in graphs], np.int64)
+    with gpu_lib.build_batch(torch.from_numpy(b.edges).cuda(), b.offsets, b.n_upper, b.n_lower) as h:
+        h.set_tuning(light_max_wedges=64)
+        out = torch.full((len(graphs),), -1, dtype=torch.int64, device="cuda")
+        s = torch.cuda.Stream()
+        h.capture_total(out, stream=s)
+        for k in range(4):
+            out.fill_(-7)
+            torch.cuda.synchronize()
+            h.replay(stream=s)
+            s.synchronize()
+            np.testing.assert_array_equal(out.cpu().numpy(), expect)
+            # eager work between replays, on the same handle
+            eager = h.count_total_batch().cpu().numpy()
+            np.testing.assert_array_equal(eager, expect)
+            assert h.count_total()[0] == int(expect.sum())
+
+
+def test_batch_4096_workload(gpu_lib):
+    if not os.path.exists(GOLDEN):
+        pytest.skip("no stored oracle results")
+    with open(GOLDEN) as f:
+        rec = json.load(f).get("batch-4096")
+    if rec is None:
+        pytest.skip("no stored oracle results for the batch")
+    b = gg.batch_workload()
+    print(f"batch: {b.count} graphs, {int(b.offsets[-1])} edges", flush=True)
+    assert b.sha256() == rec["sha256"]
+    with gpu_lib.build_batch(torch.from_numpy(b.edges).cuda(), b.offsets, b.n_upper, b.n_lower) as h:
+        totals = h.count_total_batch().cpu().numpy()
+        wedges = h.batch_wedges()
+    np.testing.assert_array_equal(totals, np.array(rec["totals"], np.int64))
+    np.testing.assert_array_equal(wedges, np.array(rec["vp_wedges"], np.int64))
