@@ -359,8 +359,8 @@ bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t) {
     std::lock_guard<std::mutex> hold(h->mu);
     if (t->light_max_wedges > 1024)
       throw Error{BFC_ERR_INVALID_ARGUMENT, "light_max_wedges must be at most 1024"};
-    if (t->dense_block > 0 && t->dense_block % 64)
-      throw Error{BFC_ERR_INVALID_ARGUMENT, "dense_block must be a multiple of 64"};
+    if (t->dense_block > 0 && (t->dense_block % 64 || t->dense_block > 32768))
+      throw Error{BFC_ERR_INVALID_ARGUMENT, "dense_block must be a multiple of 64 and at most 32768"};
     if (t->window_mode > 3) throw Error{BFC_ERR_INVALID_ARGUMENT, "window_mode must be 1, 2 or 3"};
     Tuning nt = h->tune;
     if (t->light_max_wedges > 0) nt.light_max_wedges = t->light_max_wedges;
@@ -368,7 +368,7 @@ bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t) {
     if (t->window_mode > 0) nt.window_mode = t->window_mode;
     if (t->hash_window_wedges > 0) nt.hash_window_wedges = t->hash_window_wedges;
     if (t->dense_block >= 0) nt.dense_block = t->dense_block;
-    const bool resched = nt.light_max_wedges != h->tune.light_max_wedges;
+    const bool resched = nt.light_max_wedges != h->tune.light_max_wedges || nt.dense_block != h->tune.dense_block;
     h->tune = nt;
     if (resched) {
       if (h->used) BFC_HIP(hipEventSynchronize(h->done));

@@ -217,18 +217,21 @@ namespace {
 // Classifies start (x, r): 0 = no pair can reach a count of 2, 1 = light, 2 = heavy.
 // sums: [0] |W|, [1] max prefix of a heavy start, [2] light wedges,
 // [3] heavy wedges, [4] light middles, [5] heavy middles, [6] max start wedges
+// Starts in the dense block (the top KU / KL ranks) always go to the
+// workgroup kernel, which seeds them with the block's MFMA products.
 __global__ void classify_kernel(const int64_t* __restrict__ work0, const int32_t* __restrict__ lo0, int32_t n0,
                                 const int64_t* __restrict__ work1, const int32_t* __restrict__ lo1, int32_t n1,
-                                int64_t light_max, int32_t* __restrict__ is_light, int32_t* __restrict__ is_heavy,
-                                unsigned long long* __restrict__ sums) {
+                                int64_t light_max, int32_t KU, int32_t KL, int32_t* __restrict__ is_light,
+                                int32_t* __restrict__ is_heavy, unsigned long long* __restrict__ sums) {
   const int64_t n = (int64_t)n0 + n1;
   unsigned long long s_all = 0, s_lw = 0, s_hw = 0, s_lm = 0, s_hm = 0, max_w = 0;
   int32_t max_pre = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t w = i < n0 ? work0[i] : work1[i - n0];
     const int32_t pre = i < n0 ? lo0[i] : lo1[i - n0];
-    const bool light = w >= 2 && w <= light_max;
-    const bool heavy = w > light_max;
+    const bool in_block = i < n0 ? i >= (int64_t)n0 - KU : (i - n0) >= (int64_t)n1 - KL;
+    const bool heavy = w > light_max || (in_block && w >= 2);
+    const bool light = w >= 2 && !heavy;
     s_all += (unsigned long long)w;
     is_light[i] = light ? 1 : 0;
     is_heavy[i] = heavy ? 1 : 0;
@@ -287,10 +290,14 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   sums.alloc(8 * sizeof(int64_t), s);
   BFC_HIP(hipMemsetAsync(sums.p, 0, 8 * sizeof(int64_t), s));
   const int64_t light_max = g->tune.light_max_wedges;
+  const int32_t K = g->tune.dense_block;
+  int32_t KU = K > 0 ? (K < n0 ? K : n0) : 0;
+  int32_t KL = K > 0 ? (K < n1 ? K : n1) : 0;
+  if (KU == 0 || KL == 0) KU = KL = 0;
   if (n > 0) {
     classify_kernel<<<grid_1d(n), 256, 0, s>>>(g->side[0].work.as<int64_t>(), g->side[0].lo.as<int32_t>(), n0,
                                                 g->side[1].work.as<int64_t>(), g->side[1].lo.as<int32_t>(), n1,
-                                                light_max, flags_l.as<int32_t>(), flags_h.as<int32_t>(),
+                                                light_max, KU, KL, flags_l.as<int32_t>(), flags_h.as<int32_t>(),
                                                 sums.as<unsigned long long>());
     BFC_LAUNCH_CHECK();
   }

@@ -56,6 +56,9 @@ struct CountParams {
   int32_t hash_window_wedges;
   unsigned long long* gtotal;  // per-graph totals of a batch (kTotal), else null
   const int32_t* gid[2];       // graph index of every rank, per layer (null: one graph)
+  int32_t dtop[2];             // first rank of the dense block per layer (n_X when disabled)
+  const int32_t* dC[2];        // MFMA products CU, CL (row-major)
+  int32_t dld[2];              // their row strides
 };
 
 __device__ __forceinline__ int32_t graph_index(const CountParams& p, int x, int32_t r) {
@@ -382,10 +385,42 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       width = (int32_t)(wd < 256 ? 256 : (wd > range ? range : wd));
     }
     unsigned long long start_acc = 0;
+    // Starts in the dense block: the last window covers the block's end ranks
+    // [top, r); its counters start from the MFMA products and its pass 1 walks
+    // only middles outside the other layer's block.
+    const int32_t top = x ? p.dtop[1] : p.dtop[0];
+    const bool in_block = r > top;
+    const int32_t sparse_end = in_block ? top : range;
+    int32_t pre_out = pre;  // middles outside the other layer's block (a prefix)
+    if (in_block) {
+      const int32_t otop = x ? p.dtop[0] : p.dtop[1];
+      int32_t a = 0, b = pre;
+      while (a < b) {
+        const int32_t mid = (a + b) >> 1;
+        if (S.adj[base + mid] < otop) a = mid + 1; else b = mid;
+      }
+      pre_out = a;
+    }
     int32_t lo_w = 0;
-    while (lo_w < range) {
-      int32_t hi_w = (int64_t)lo_w + width >= range ? range : lo_w + width;
+    for (;;) {
+      int32_t hi_w;
+      bool wdense = dense, whalf = half;
+      const bool seeded = lo_w >= sparse_end;
+      if (!seeded) {
+        hi_w = (int64_t)lo_w + width >= sparse_end ? sparse_end : lo_w + width;
+      } else if (in_block && lo_w < range) {
+        hi_w = range;
+        wdense = true;
+        whalf = false;
+      } else {
+        break;
+      }
+      const int32_t pre1 = seeded ? pre_out : pre;
       bool multi = !(lo_w == 0 && hi_w == range);
+      if (seeded) {
+        const int32_t* crow = (x ? p.dC[1] : p.dC[0]) + (int64_t)(r - top) * (x ? p.dld[1] : p.dld[0]);
+        for (int32_t i = t; i < range - top; i += kHeavyNT) table[i] = crow[i];
+      }
       // ---- pass 1: count the wedges whose end lies in [lo_w, hi_w)
       for (;;) {
         if (t == 0) { s_fill = 0; s_over = 0; s_next = 0; }
@@ -395,19 +430,19 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
           if (lane == 0) g = atomicAdd(&s_next, 1);
           g = __shfl(g, 0, 64);
           const int32_t j0 = g * 64;
-          if (j0 >= pre) break;
+          if (j0 >= pre1) break;
           const int32_t j = j0 + lane;
           int32_t cs = 0, ce = 0;
-          if (j < pre) {
+          if (j < pre1) {
             const int32_t k = base + j;
             const int32_t v = S.adj[k];
             const int32_t e = S.rev[k];
             cs = lo_w == 0 ? O.off[v] : cur_in[j];
             ce = hi_w >= range ? e : gallop_lower_bound(O.adj, cs, e, hi_w);
-            if (multi) cur_out[j] = ce;
+            if (multi && !seeded) cur_out[j] = ce;
           }
-          if (dense) {
-            wave_walk(O.adj, cs, ce - cs, mark, [&](int, int32_t, int32_t w) { dense_add(table, w - lo_w, half); });
+          if (wdense) {
+            wave_walk(O.adj, cs, ce - cs, mark, [&](int, int32_t, int32_t w) { dense_add(table, w - lo_w, whalf); });
           } else {
             wave_walk(O.adj, cs, ce - cs, mark,
                       [&](int, int32_t, int32_t w) { block_hash_add(table, cap, w, &s_fill, &s_over); });
@@ -415,7 +450,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
           }
         }
         __syncthreads();
-        if (dense || !s_over) break;
+        if (wdense || !s_over) break;
         // the window holds too many distinct ends for the table: halve it and redo
         for (int i = t; i < (int)(2 * cap); i += kHeavyNT) table[i] = 0;
         __syncthreads();
@@ -441,10 +476,10 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
             const int32_t k = base + j;
             v = S.adj[k];
             cs = lo_w == 0 ? O.off[v] : cur_in[j];
-            ce = multi ? cur_out[j] : S.rev[k];
+            ce = (multi && !seeded) ? cur_out[j] : S.rev[k];
           }
           wave_walk(O.adj, cs, ce - cs, mark, [&](int mid, int32_t slot, int32_t w) {
-            const int32_t c = dense ? dense_get(table, w - lo_w, half) : hash_get(table, table + cap, cap - 1, w);
+            const int32_t c = wdense ? dense_get(table, w - lo_w, whalf) : hash_get(table, table + cap, cap - 1, w);
             if (c > 1) {
               const unsigned long long d = (unsigned long long)(c - 1);
               if (mode == kEdge) atomicAdd(&acc_o[slot], d);
@@ -463,13 +498,13 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       }
       // ---- finalize the window: C(count,2) per end, then clear the table
       unsigned long long* vs = pick_ptr(p.vout, x);
-      if (dense) {
+      if (wdense) {
         const int32_t wn = hi_w - lo_w;
-        const int32_t words = half ? (wn + 1) >> 1 : wn;
+        const int32_t words = whalf ? (wn + 1) >> 1 : wn;
         for (int32_t i = t; i < words; i += kHeavyNT) {
           const uint32_t word = (uint32_t)table[i];
           if (word) {
-            if (half) {
+            if (whalf) {
               const int32_t c0 = (int32_t)(word & 0xFFFFu), c1 = (int32_t)(word >> 16);
               if (c0 > 1) {
                 const unsigned long long cc = choose2(c0);
@@ -505,7 +540,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         }
       }
       __syncthreads();
-      if (multi) {
+      if (multi && !seeded) {
         int32_t* tmp = cur_in;
         cur_in = cur_out;
         cur_out = tmp;
@@ -573,6 +608,7 @@ void zero_u64(void* p, int64_t n, hipStream_t s) {
 }
 
 void prepare_count(bfc_graph_s* g, hipStream_t s) {
+  prepare_dense(g, s);
   // two cursor arrays per heavy workgroup, then 256 bytes for the ticket
   const size_t need = (size_t)heavy_grid_for(g) * 2 * (size_t)cursor_stride_for(g) * sizeof(int32_t) + 256;
   if (g->scratch_bytes < need) {
@@ -623,12 +659,24 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     p.acc[0] = g->acc.as<unsigned long long>();
     p.acc[1] = g->acc.as<unsigned long long>() + g->m;
   }
+  const DenseBlock& d = g->dense;
+  p.dtop[0] = g->side[0].n - d.KU;
+  p.dtop[1] = g->side[1].n - d.KL;
+  if (d.KU > 0) {
+    p.dC[0] = d.CU();
+    p.dC[1] = d.CL();
+    p.dld[0] = d.PU;
+    p.dld[1] = d.PL;
+  }
   if (sc.n_heavy > 0) zero_u64(ticket, 1, s);
+  // events: [0] dense block [1] light [2] heavy [3] fold [4]
   bfc_graph_s::TimedCall tc{};
   if (g->timing) {
-    for (int i = 0; i < 4; ++i) BFC_HIP(hipEventCreate(&tc.ev[i]));
+    for (int i = 0; i < 5; ++i) BFC_HIP(hipEventCreate(&tc.ev[i]));
     BFC_HIP(hipEventRecord(tc.ev[0], s));
   }
+  dense_block(g, s);
+  if (g->timing) BFC_HIP(hipEventRecord(tc.ev[1], s));
   if (sc.n_light > 0) {
     p.list = g->sched.light.as<int32_t>();
     p.n_list = sc.n_light;
@@ -637,14 +685,14 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     light_kernel<<<(unsigned)grid, kLightNT, 0, s>>>(p);
     BFC_LAUNCH_CHECK();
   }
-  if (g->timing) BFC_HIP(hipEventRecord(tc.ev[1], s));
+  if (g->timing) BFC_HIP(hipEventRecord(tc.ev[2], s));
   if (sc.n_heavy > 0) {
     p.list = g->sched.heavy.as<int32_t>();
     p.n_list = sc.n_heavy;
     heavy_kernel<<<(unsigned)heavy_grid, kHeavyNT, 0, s>>>(p);
     BFC_LAUNCH_CHECK();
   }
-  if (g->timing) BFC_HIP(hipEventRecord(tc.ev[2], s));
+  if (g->timing) BFC_HIP(hipEventRecord(tc.ev[3], s));
   if (mode == kEdge && g->m > 0) {
     int64_t grid = (g->m + 255) / 256;
     if (grid > 65536) grid = 65536;
@@ -654,23 +702,24 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     BFC_LAUNCH_CHECK();
   }
   if (g->timing) {
-    BFC_HIP(hipEventRecord(tc.ev[3], s));
+    BFC_HIP(hipEventRecord(tc.ev[4], s));
     g->timed.push_back(tc);
   }
 }
 
 void collect_times(bfc_graph_s* g) {
   for (auto& tc : g->timed) {
-    BFC_HIP(hipEventSynchronize(tc.ev[3]));
-    float a = 0, b = 0, c = 0;
-    BFC_HIP(hipEventElapsedTime(&a, tc.ev[0], tc.ev[1]));
-    BFC_HIP(hipEventElapsedTime(&b, tc.ev[1], tc.ev[2]));
-    BFC_HIP(hipEventElapsedTime(&c, tc.ev[2], tc.ev[3]));
+    BFC_HIP(hipEventSynchronize(tc.ev[4]));
+    float dn = 0, a = 0, b = 0, c = 0;
+    BFC_HIP(hipEventElapsedTime(&dn, tc.ev[0], tc.ev[1]));
+    BFC_HIP(hipEventElapsedTime(&a, tc.ev[1], tc.ev[2]));
+    BFC_HIP(hipEventElapsedTime(&b, tc.ev[2], tc.ev[3]));
+    BFC_HIP(hipEventElapsedTime(&c, tc.ev[3], tc.ev[4]));
     g->light_ms += a;
     g->heavy_ms += b;
-    g->other_ms += c;
+    g->other_ms += c + dn;
     g->timed_calls += 1;
-    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(tc.ev[i]);
+    for (int i = 0; i < 5; ++i) (void)hipEventDestroy(tc.ev[i]);
   }
   g->timed.clear();
 }

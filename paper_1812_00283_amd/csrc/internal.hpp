@@ -121,6 +121,15 @@ struct Tuning {
   int32_t dense_block = 0;
 };
 
+// Dense block of top-priority vertices (int8 MFMA, see dense.hip).
+struct DenseBlock {
+  int32_t KU = 0, KL = 0;  // block sizes per layer (0: disabled)
+  int32_t PU = 0, PL = 0;  // padded to multiples of 32
+  DevBuf buf;              // XU, YU, XL, YL (int8) then CU [PU][PU], CL [PL][PL] (int32)
+  int32_t* CU() const { return reinterpret_cast<int32_t*>(buf.as<int8_t>() + 4 * (size_t)PU * (size_t)PL); }
+  int32_t* CL() const { return CU() + (size_t)PU * (size_t)PU; }
+};
+
 }  // namespace bfc
 
 struct bfc_graph_s {
@@ -137,6 +146,7 @@ struct bfc_graph_s {
   hipGraphExec_t cap_exec = nullptr;
   bfc::Schedule sched;
   bfc::Tuning tune;
+  bfc::DenseBlock dense;
   bfc::DevBuf scratch;    // per-workgroup cursors and the work ticket of the count kernels
   size_t scratch_bytes = 0;
   bfc::DevBuf acc;        // int64 [2m] per-arc accumulators of the per-edge count (allocated on first use)
@@ -148,7 +158,7 @@ struct bfc_graph_s {
   bool used = false;
   // optional kernel timing: events around the count kernels of each call
   bool timing = false;
-  struct TimedCall { hipEvent_t ev[4]; };
+  struct TimedCall { hipEvent_t ev[5]; };
   std::vector<TimedCall> timed;
   int64_t timed_calls = 0;
   double light_ms = 0, heavy_ms = 0, other_ms = 0;
@@ -191,6 +201,10 @@ void build_batch(bfc_graph_s* g, const int32_t* edges, const int64_t* eoff_host,
 void prepare_count(bfc_graph_s* g, hipStream_t s);
 // Sums the durations of timed count calls (waits for them).
 void collect_times(bfc_graph_s* g);
+// Dense block: sizes and buffers for the current tuning, and the MFMA
+// products for one count call.
+void prepare_dense(bfc_graph_s* g, hipStream_t s);
+void dense_block(bfc_graph_s* g, hipStream_t s);
 // Zero fill by kernel (safe inside captured graphs, unlike a memset node).
 void zero_u64(void* p, int64_t n, hipStream_t s);
 

@@ -100,6 +100,10 @@ TUNINGS = {
     "hash-tiny-windows": {"light_max_wedges": 1, "window_mode": 3, "hash_window_wedges": 64},
     "hash-overfull": {"light_max_wedges": 64, "window_mode": 3, "hash_window_wedges": 1 << 30},
     "dense-ratio-1": {"dense_min_ratio": 1},
+    "mfma-block-64": {"dense_block": 64},
+    "mfma-block-1024": {"dense_block": 1024, "light_max_wedges": 64},
+    "mfma-block-4096-hash": {"dense_block": 4096, "window_mode": 3, "hash_window_wedges": 512},
+    "mfma-block-32768": {"dense_block": 32768},
 }
 
 
@@ -111,6 +115,24 @@ def test_hub_graph_every_kernel_path(gpu_lib, hub_graph, hub_oracle, name):
     np.testing.assert_array_equal(up, o_up)
     np.testing.assert_array_equal(lo, o_lo)
     np.testing.assert_array_equal(be, o_be)
+
+
+def test_mfma_block_covers_whole_small_graphs(gpu_lib):
+    """Block sizes at or above the layer sizes: every start is in the block."""
+    for a, b in [(3, 5), (40, 60), (64, 64), (100, 37)]:
+        g = gg.complete_bipartite(a, b)
+        for k in (64, 128):
+            check_against_oracle(gpu_lib, g, {"dense_block": k})
+    rng = np.random.default_rng(3)
+    for i in range(30):
+        g = gg.random_small(4000 + i, int(rng.integers(2, 70)), int(rng.integers(2, 70)), float(rng.uniform(0.1, 0.9)))
+        check_against_oracle(gpu_lib, g, {"dense_block": 64, "light_max_wedges": 1 + i % 3})
+
+
+def test_mfma_block_planted_bicliques(gpu_lib):
+    g = gg.chung_lu(77, 20_000, 15_000, 300_000, 2.0, 2.3, 3000.0, blocks=8, block=96, density=0.9, name="planted")
+    for k in (0, 256, 2048):
+        check_against_oracle(gpu_lib, g, {"dense_block": k} if k else None)
 
 
 def test_repeat_and_async_and_streams(gpu_lib, hub_graph, hub_oracle):
