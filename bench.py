@@ -90,6 +90,130 @@ def cpu_baseline(g, wedges: int, target_s: float = 15.0) -> dict:
     }
 
 
+def bench_batch(args) -> int:
+    """Batched form: all graphs in one handle (one build, one set of count
+    launches replayed from a captured HIP graph) against a loop of
+    bfc_build + bfc_count_total, one graph per handle, on the same GPU."""
+    import torch
+
+    import graphgen as gg
+    from paper_1812_00283_amd import bfc
+
+    bfc.load()
+    t = time.perf_counter()
+    b = gg.batch_workload(count=args.graphs)
+    log(f"generated {b.count} graphs, {int(b.offsets[-1])} edges in {time.perf_counter() - t:.1f}s")
+    edges = torch.from_numpy(b.edges).cuda()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    totals = torch.zeros(b.count, dtype=torch.int64, device="cuda")
+    # batched: build + captured count
+    ref = None
+    times_build, times_count = [], []
+    for i in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = bfc.build_batch(edges, b.offsets, b.n_upper, b.n_lower, stream)
+        t1 = time.perf_counter()
+        h.capture_total(totals, stream)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        h.replay(stream)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        got = totals.cpu().numpy().copy()
+        ref = got if ref is None else ref
+        assert (got == ref).all()
+        if i >= args.warmup:
+            times_build.append(t1 - t0)
+            times_count.append(t3 - t2)
+        wed = h.batch_wedges()
+        h.close()
+        log(f"batched step {i}: build {1e3 * (t1 - t0):.1f} ms, replayed count {1e3 * (t3 - t2):.1f} ms")
+    batched_s = float(np.median(times_build)) + float(np.median(times_count))
+    # plain: one graph per handle
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = np.zeros(b.count, np.int64)
+    for g in range(b.count):
+        lo, hi = int(b.offsets[g]), int(b.offsets[g + 1])
+        if hi == lo:
+            continue
+        with bfc.Graph(edges[lo:hi], int(b.n_upper[g]), int(b.n_lower[g]), stream) as h:
+            plain[g] = h.count_total(stream)[0]
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    assert (plain == ref).all(), "batched and plain totals differ"
+    exact = None
+    gold = os.path.join(ROOT, "tests", "golden", "batch.json")
+    if os.path.exists(gold) and args.graphs == 4096:
+        with open(gold) as f:
+            rec = json.load(f)["batch-4096"]
+        exact = bool(rec["sha256"] == b.sha256() and (np.array(rec["totals"]) == ref).all())
+    print(json.dumps({
+        "metric": "batched graphs/s", "value": b.count / batched_s, "unit": "graphs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * batched_s, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"batch-{b.count}", "edges": int(b.offsets[-1]), "wedges": int(wed.sum()),
+                   "exact_vs_oracle": exact},
+        "batched_build_ms": 1e3 * float(np.median(times_build)),
+        "batched_count_ms": 1e3 * float(np.median(times_count)),
+        "plain_graphs_per_s": b.count / plain_s, "plain_ms": 1e3 * plain_s,
+        "speedup_vs_plain": plain_s / batched_s,
+    }), flush=True)
+    return 0
+
+
+def bench_serve(args) -> int:
+    """Served form: a prefix of the arrival trace replayed in real time against
+    the continuous-batching server, then against the plain FIFO server."""
+    import torch
+
+    import graphgen as gg
+    from paper_1812_00283_amd import bfc, serve
+
+    bfc.load()
+    reqs = gg.serve_schedule(duration_s=args.serve_seconds, m_hi=args.serve_max_edges)
+    roots = {r.index: r.graph for r in reqs if r.follow_up_of < 0}
+    t = time.perf_counter()
+    built = dict(zip(roots, gg.spec_graphs(list(roots.values()))))
+    offered_edges = sum(built[r.follow_up_of if r.follow_up_of >= 0 else r.index].m for r in reqs)
+    log(f"trace: {len(reqs)} requests over {args.serve_seconds}s, {len(roots)} graphs, "
+        f"{offered_edges} request edges; generated in {time.perf_counter() - t:.1f}s")
+    arrivals = [r.arrival_s for r in reqs]
+
+    def jobs():
+        return [serve.Job(r.index, r.kind, r.follow_up_of if r.follow_up_of >= 0 else r.index,
+                          built[r.follow_up_of if r.follow_up_of >= 0 else r.index].edges,
+                          r.graph.n_upper, r.graph.n_lower) for r in reqs]
+
+    free, total = torch.cuda.mem_get_info()
+    budget = int(args.serve_budget_gb * (1 << 30)) if args.serve_budget_gb else int(0.6 * free)
+    out = {}
+    for name, srv in (("batched", serve.Server(budget, slots=4)), ("plain", serve.Server(budget, plain=True))):
+        js = jobs()
+        wall = serve.replay(js, arrivals, srv)
+        st = serve.latency_stats(js)
+        st.update({"wall_s": wall, "requests_per_s": len(js) / wall, "edges_per_s": offered_edges / wall,
+                   "cache_hits": sum(j.cache_hit for j in js), "batched_requests": sum(j.batched for j in js),
+                   "peak_admitted_gb": srv.peak / (1 << 30)})
+        out[name] = (st, [j.result for j in js])
+        log(f"{name}: p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms, {st['requests_per_s']:.1f} req/s")
+    assert out["batched"][1] == out["plain"][1], "served results differ between the mix and the plain server"
+    bst, pst = out["batched"][0], out["plain"][0]
+    print(json.dumps({
+        "metric": "served p99 latency", "value": bst["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": 1e3 * bst["wall_s"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"serve-{args.serve_seconds}s", "requests": len(reqs),
+                   "offered_requests_per_s": len(reqs) / args.serve_seconds,
+                   "offered_edges_per_s": offered_edges / args.serve_seconds, "budget_gb": budget / (1 << 30),
+                   "max_edges_per_request": args.serve_max_edges},
+        "batched": bst, "plain": pst, "results_identical": True,
+    }), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,7 +223,15 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (calibrates HBM counters)")
+    ap.add_argument("--graphs", type=int, default=4096, help="graphs in the batched workload")
+    ap.add_argument("--serve-seconds", type=float, default=1.0, help="prefix of the arrival trace to serve")
+    ap.add_argument("--serve-max-edges", type=int, default=50_000_000)
+    ap.add_argument("--serve-budget-gb", type=float, default=0.0)
     args = ap.parse_args()
+    if args.workload == "batch" and args.gpus == 1:
+        return bench_batch(args)
+    if args.workload == "serve" and args.gpus == 1:
+        return bench_serve(args)
     if args.copy_probe:
         import torch
 
