@@ -223,6 +223,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (calibrates HBM counters)")
+    ap.add_argument("--tuning", default="", help='JSON dict of bfc_set_tuning fields, e.g. {"window_mode": 3}')
     ap.add_argument("--graphs", type=int, default=4096, help="graphs in the batched workload")
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="prefix of the arrival trace to serve")
     ap.add_argument("--serve-max-edges", type=int, default=50_000_000)
@@ -267,8 +268,12 @@ def main() -> int:
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
+    tuning = json.loads(args.tuning) if args.tuning else None
+
     def step(timing: bool):
         h = bfc.Graph(edges, g.n_upper, g.n_lower, stream)
+        if tuning:
+            h.set_tuning(**tuning)
         if timing:
             h.set_kernel_timing(True)
         tb = time.perf_counter()
@@ -296,6 +301,7 @@ def main() -> int:
         count_s.append(tc)
         heavy_ms.append(kt["heavy_ms"] / max(kt["calls"], 1))
         light_ms.append(kt["light_ms"] / max(kt["calls"], 1))
+        log(f"step {i}: count {1e3 * tc:.2f} ms (heavy kernel {heavy_ms[-1]:.2f} ms, light {light_ms[-1]:.2f} ms)")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     assert all(x == tot0 for x in totals), "totals differ between steps"
@@ -329,6 +335,7 @@ def main() -> int:
             "butterflies": tot0,
             "step": "bfc_build + bfc_count_total on device-resident edges",
             "exact_vs_oracle": bool(gold),
+            "tuning": tuning or "default",
         },
         "count_ms": count_ms,
         "build_ms": ms_step - count_ms,

@@ -176,8 +176,11 @@ bfc_status bfc_count_total(bfc_graph g, void* stream, int64_t* total_host, int64
       cs.finish();
     }
     int64_t v = 0;
+    int32_t st = 0;
     BFC_HIP(hipMemcpyAsync(&v, tot.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    BFC_HIP(hipMemcpyAsync(&st, count_status(h), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BFC_HIP(hipStreamSynchronize(s));
+    if (st) throw Error{BFC_ERR_DEVICE, "internal error: a counting window could not be sized"};
     *total_host = v;
     if (wedges_host) *wedges_host = h->sched.wedges;
   });

@@ -26,16 +26,33 @@ namespace bfc {
 
 namespace {
 
+// Degree histogram.  Each workgroup adds into one of kDegCopies private
+// copies (by workgroup index), so the many increments of a hub vertex are
+// spread over several addresses; reduce_copies_kernel then sums the copies.
+constexpr int kDegCopies = 8;
+
 __global__ void degree_kernel(const int32_t* __restrict__ edges, int64_t m, int32_t nU, int32_t nL,
                               int32_t* __restrict__ degU, int32_t* __restrict__ degL, int32_t* __restrict__ status) {
+  const int c = blockIdx.x % kDegCopies;
+  int32_t* du = degU + (int64_t)c * nU;
+  int32_t* dl = degL + (int64_t)c * nL;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
     const int2 e = reinterpret_cast<const int2*>(edges)[i];
     if (e.x < 0 || e.x >= nU || e.y < 0 || e.y >= nL) {
       atomicOr(&status[0], 1);
       continue;
     }
-    atomicAdd(&degU[e.x], 1);
-    atomicAdd(&degL[e.y], 1);
+    atomicAdd(&du[e.x], 1);
+    atomicAdd(&dl[e.y], 1);
+  }
+}
+
+__global__ void reduce_copies_kernel(const int32_t* __restrict__ copies, int32_t n, int32_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t s = 0;
+#pragma unroll
+    for (int c = 0; c < kDegCopies; ++c) s += copies[(int64_t)c * n + i];
+    out[i] = s;
   }
 }
 
@@ -63,40 +80,57 @@ __global__ void arc_keys_kernel(const int32_t* __restrict__ edges, int64_t m, in
 }
 
 __global__ void arc_unpack_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t m,
-                                  uint64_t mask_dst, int32_t* __restrict__ adj, int32_t* __restrict__ slot_of_edge,
-                                  int32_t* __restrict__ status) {
+                                  int bits_dst, int32_t* __restrict__ adj, int32_t* __restrict__ src,
+                                  int32_t* __restrict__ slot_of_edge, int32_t* __restrict__ status) {
+  const uint64_t mask = (1ull << bits_dst) - 1ull;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t key = keys[k];
-    adj[k] = (int32_t)(key & mask_dst);
+    adj[k] = (int32_t)(key & mask);
+    src[k] = (int32_t)(key >> bits_dst);
     slot_of_edge[vals[k]] = (int32_t)k;
     if (k > 0 && keys[k - 1] == key) atomicOr(&status[1], 1);
   }
 }
 
-__global__ void link_kernel(const int32_t* __restrict__ edges, int64_t m, const int32_t* __restrict__ slotU,
-                            const int32_t* __restrict__ slotL, const int32_t* __restrict__ rankU,
-                            const int32_t* __restrict__ rankL, const int32_t* __restrict__ degU,
-                            const int32_t* __restrict__ degL, const int32_t* __restrict__ offU,
-                            const int32_t* __restrict__ offL, int32_t* __restrict__ revU, int32_t* __restrict__ revL,
-                            int32_t* __restrict__ loU, int32_t* __restrict__ loL, unsigned long long* __restrict__ workU,
-                            unsigned long long* __restrict__ workL, int32_t* __restrict__ eslot) {
+__global__ void link_kernel(int64_t m, const int32_t* __restrict__ slotU, const int32_t* __restrict__ slotL,
+                            int32_t* __restrict__ revU, int32_t* __restrict__ revL, int32_t* __restrict__ eslot) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    const int2 e = reinterpret_cast<const int2*>(edges)[i];
     const int32_t su = slotU[i];
     const int32_t sl = slotL[i];
     revU[su] = sl;
     revL[sl] = su;
     eslot[i] = su;
-    const int32_t ru = rankU[e.x];
-    const int32_t rl = rankL[e.y];
-    if (degL[e.y] <= degU[e.x]) {
-      // v has lower priority: arc u->v is a middle arc of start u; ends = N(v) before u
-      atomicAdd(&loU[ru], 1);
-      atomicAdd(&workU[ru], (unsigned long long)(sl - offL[rl]));
-    } else {
-      atomicAdd(&loL[rl], 1);
-      atomicAdd(&workL[rl], (unsigned long long)(su - offU[ru]));
-    }
+  }
+}
+
+// Per arc k of side X (source rank src[k], neighbour rank adj[k]): is the
+// neighbour a middle of the source (lower priority), and if so how many
+// wedges it gives: the entries of N(neighbour) before the source, i.e.
+// rev[k] - off_other[neighbour].  With the global id putting every upper
+// vertex above every lower one, for an upper u and lower v:
+// p(v) < p(u)  <=>  deg(v) <= deg(u).
+__global__ void middle_kernel(int64_t m, int x, const int32_t* __restrict__ src, const int32_t* __restrict__ adj,
+                              const int32_t* __restrict__ rev, const int32_t* __restrict__ off_other,
+                              const int32_t* __restrict__ deg_self, const int32_t* __restrict__ deg_other,
+                              int32_t* __restrict__ mid_flag, int64_t* __restrict__ mid_work) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = src[k];
+    const int32_t v = adj[k];
+    const int32_t ds = deg_self[r], dv = deg_other[v];
+    const bool mid = x == 0 ? dv <= ds : dv < ds;
+    mid_flag[k] = mid ? 1 : 0;
+    mid_work[k] = mid ? (int64_t)(rev[k] - off_other[v]) : 0;
+  }
+}
+
+// lo[r] and work[r] from the prefix sums of the per-arc values over row r.
+__global__ void row_sums_kernel(int32_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ flag_scan,
+                                const int64_t* __restrict__ work_scan, int32_t* __restrict__ lo,
+                                int64_t* __restrict__ work) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = off[r], b = off[r + 1];
+    lo[r] = flag_scan[b] - flag_scan[a];
+    work[r] = work_scan[b] - work_scan[a];
   }
 }
 
@@ -116,14 +150,23 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
   status.alloc(4 * sizeof(int32_t), s);
   BFC_HIP(hipMemsetAsync(status.p, 0, 4 * sizeof(int32_t), s));
   TmpBuf deg[2];
-  for (int x = 0; x < 2; ++x) {
-    deg[x].alloc(sizeof(int32_t) * (size_t)(n[x] + 1), s);
-    BFC_HIP(hipMemsetAsync(deg[x].p, 0, sizeof(int32_t) * (size_t)(n[x] + 1), s));
-  }
-  if (m > 0) {
-    degree_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, n[0], n[1], deg[0].as<int32_t>(), deg[1].as<int32_t>(),
-                                              status.as<int32_t>());
-    BFC_LAUNCH_CHECK();
+  {
+    TmpBuf copies[2];
+    for (int x = 0; x < 2; ++x) {
+      deg[x].alloc(sizeof(int32_t) * (size_t)(n[x] + 1), s);
+      copies[x].alloc(sizeof(int32_t) * (size_t)kDegCopies * (size_t)n[x], s);
+      BFC_HIP(hipMemsetAsync(copies[x].p, 0, sizeof(int32_t) * (size_t)kDegCopies * (size_t)n[x], s));
+    }
+    if (m > 0) {
+      degree_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, n[0], n[1], copies[0].as<int32_t>(),
+                                                copies[1].as<int32_t>(), status.as<int32_t>());
+      BFC_LAUNCH_CHECK();
+    }
+    for (int x = 0; x < 2; ++x) {
+      if (n[x] == 0) continue;
+      reduce_copies_kernel<<<grid_1d(n[x]), 256, 0, s>>>(copies[x].as<int32_t>(), n[x], deg[x].as<int32_t>());
+      BFC_LAUNCH_CHECK();
+    }
   }
   int32_t st[4] = {0, 0, 0, 0};
   BFC_HIP(hipMemcpyAsync(st, status.p, sizeof(st), hipMemcpyDeviceToHost, s));
@@ -131,37 +174,37 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
   if (st[0]) throw Error{BFC_ERR_VERTEX_OUT_OF_RANGE, "an edge has an upper id outside [0,n_upper) or a lower id outside [0,n_lower)"};
 
   // ---- priorities: stable sort of each layer's ids by degree
-  TmpBuf rank_of[2];
+  TmpBuf rank_of[2], deg_rank[2];
   for (int x = 0; x < 2; ++x) {
     Side& sd = g->side[x];
     sd.n = n[x];
     const int64_t nx = n[x];
-    TmpBuf keys, ktmp, vtmp;
+    TmpBuf ktmp, vtmp;
     sd.id_of.alloc(sizeof(uint32_t) * (size_t)nx, s);
     DevBuf& vals = sd.id_of;
-    keys.alloc(sizeof(uint32_t) * (size_t)nx, s);
+    deg_rank[x].alloc(sizeof(uint32_t) * (size_t)nx, s);
     ktmp.alloc(sizeof(uint32_t) * (size_t)nx, s);
     vtmp.alloc(sizeof(uint32_t) * (size_t)nx, s);
     if (nx > 0) {
-      BFC_HIP(hipMemcpyAsync(keys.p, deg[x].p, sizeof(uint32_t) * (size_t)nx, hipMemcpyDeviceToDevice, s));
+      BFC_HIP(hipMemcpyAsync(deg_rank[x].p, deg[x].p, sizeof(uint32_t) * (size_t)nx, hipMemcpyDeviceToDevice, s));
       iota_kernel<<<grid_1d(nx), 256, 0, s>>>(vals.as<uint32_t>(), nx);
       BFC_LAUNCH_CHECK();
       const int64_t max_deg = m < n[1 - x] ? m : n[1 - x];
-      radix_sort_u32(keys.as<uint32_t>(), vals.as<uint32_t>(), ktmp.as<uint32_t>(), vtmp.as<uint32_t>(), nx,
+      radix_sort_u32(deg_rank[x].as<uint32_t>(), vals.as<uint32_t>(), ktmp.as<uint32_t>(), vtmp.as<uint32_t>(), nx,
                      bits_for((uint64_t)max_deg), s);
     }
-    // keys = degrees in rank order; vals = id_of
+    // deg_rank = degrees in rank order; id_of = ids in rank order
     rank_of[x].alloc(sizeof(int32_t) * (size_t)nx, s);
     if (nx > 0) {
       invert_kernel<<<grid_1d(nx), 256, 0, s>>>(sd.id_of.as<uint32_t>(), rank_of[x].as<int32_t>(), nx);
       BFC_LAUNCH_CHECK();
     }
     sd.off.alloc(sizeof(int32_t) * (size_t)(nx + 1), s);
-    exclusive_scan_i32(keys.as<int32_t>(), sd.off.as<int32_t>(), nx, sd.off.as<int32_t>() + nx, s);
+    exclusive_scan_i32(deg_rank[x].as<int32_t>(), sd.off.as<int32_t>(), nx, sd.off.as<int32_t>() + nx, s);
   }
 
   // ---- per-side CSR by sorting (rank, neighbour rank) keys
-  TmpBuf slot[2];
+  TmpBuf slot[2], src[2];
   const int bits[2] = {bits_for((uint64_t)(n[0] > 1 ? n[0] - 1 : 1)), bits_for((uint64_t)(n[1] > 1 ? n[1] - 1 : 1))};
   {
     TmpBuf keys, vals, ktmp, vtmp;
@@ -173,6 +216,7 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
       Side& sd = g->side[x];
       sd.adj.alloc(sizeof(int32_t) * (size_t)m, s);
       slot[x].alloc(sizeof(int32_t) * (size_t)m, s);
+      src[x].alloc(sizeof(int32_t) * (size_t)m, s);
       if (m == 0) continue;
       const int bd = bits[1 - x];
       arc_keys_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, x, rank_of[x].as<int32_t>(), rank_of[1 - x].as<int32_t>(),
@@ -180,31 +224,43 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
       BFC_LAUNCH_CHECK();
       radix_sort_u64(keys.as<uint64_t>(), vals.as<uint32_t>(), ktmp.as<uint64_t>(), vtmp.as<uint32_t>(), m,
                      bits[0] + bits[1], s);
-      arc_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(keys.as<uint64_t>(), vals.as<uint32_t>(), m,
-                                                     (1ull << bd) - 1ull, sd.adj.as<int32_t>(), slot[x].as<int32_t>(),
+      arc_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(keys.as<uint64_t>(), vals.as<uint32_t>(), m, bd,
+                                                     sd.adj.as<int32_t>(), src[x].as<int32_t>(), slot[x].as<int32_t>(),
                                                      status.as<int32_t>());
       BFC_LAUNCH_CHECK();
     }
   }
 
-  // ---- reverse slots, lower-priority prefix lengths, per-start work
-  for (int x = 0; x < 2; ++x) {
-    Side& sd = g->side[x];
-    sd.rev.alloc(sizeof(int32_t) * (size_t)m, s);
-    sd.lo.alloc(sizeof(int32_t) * (size_t)sd.n, s);
-    sd.work.alloc(sizeof(int64_t) * (size_t)sd.n, s);
-    BFC_HIP(hipMemsetAsync(sd.lo.p, 0, sizeof(int32_t) * (size_t)sd.n, s));
-    BFC_HIP(hipMemsetAsync(sd.work.p, 0, sizeof(int64_t) * (size_t)sd.n, s));
-  }
+  // ---- reverse slots, then per start: lower-priority prefix length and wedges
+  for (int x = 0; x < 2; ++x) g->side[x].rev.alloc(sizeof(int32_t) * (size_t)m, s);
   g->eslot.alloc(sizeof(int32_t) * (size_t)m, s);
   if (m > 0) {
-    link_kernel<<<grid_1d(m), 256, 0, s>>>(
-        edges, m, slot[0].as<int32_t>(), slot[1].as<int32_t>(), rank_of[0].as<int32_t>(), rank_of[1].as<int32_t>(),
-        deg[0].as<int32_t>(), deg[1].as<int32_t>(), g->side[0].off.as<int32_t>(), g->side[1].off.as<int32_t>(),
-        g->side[0].rev.as<int32_t>(), g->side[1].rev.as<int32_t>(), g->side[0].lo.as<int32_t>(),
-        g->side[1].lo.as<int32_t>(), g->side[0].work.as<unsigned long long>(),
-        g->side[1].work.as<unsigned long long>(), g->eslot.as<int32_t>());
+    link_kernel<<<grid_1d(m), 256, 0, s>>>(m, slot[0].as<int32_t>(), slot[1].as<int32_t>(),
+                                            g->side[0].rev.as<int32_t>(), g->side[1].rev.as<int32_t>(),
+                                            g->eslot.as<int32_t>());
     BFC_LAUNCH_CHECK();
+  }
+  for (int x = 0; x < 2; ++x) {
+    Side& sd = g->side[x];
+    sd.lo.alloc(sizeof(int32_t) * (size_t)sd.n, s);
+    sd.work.alloc(sizeof(int64_t) * (size_t)sd.n, s);
+    TmpBuf flag, work;
+    flag.alloc(sizeof(int32_t) * (size_t)(m + 1), s);
+    work.alloc(sizeof(int64_t) * (size_t)(m + 1), s);
+    if (m > 0) {
+      middle_kernel<<<grid_1d(m), 256, 0, s>>>(m, x, src[x].as<int32_t>(), sd.adj.as<int32_t>(), sd.rev.as<int32_t>(),
+                                                g->side[1 - x].off.as<int32_t>(), deg_rank[x].as<int32_t>(),
+                                                deg_rank[1 - x].as<int32_t>(), flag.as<int32_t>(),
+                                                work.as<int64_t>());
+      BFC_LAUNCH_CHECK();
+    }
+    exclusive_scan_i32(flag.as<int32_t>(), flag.as<int32_t>(), m, flag.as<int32_t>() + m, s);
+    exclusive_scan_i64(work.as<int64_t>(), work.as<int64_t>(), m, work.as<int64_t>() + m, s);
+    if (sd.n > 0) {
+      row_sums_kernel<<<grid_1d(sd.n), 256, 0, s>>>(sd.n, sd.off.as<int32_t>(), flag.as<int32_t>(),
+                                                     work.as<int64_t>(), sd.lo.as<int32_t>(), sd.work.as<int64_t>());
+      BFC_LAUNCH_CHECK();
+    }
   }
   BFC_HIP(hipMemcpyAsync(st, status.p, sizeof(st), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
@@ -255,8 +311,17 @@ __global__ void classify_kernel(const int64_t* __restrict__ work0, const int32_t
     if (s_lm) atomicAdd(&sums[4], s_lm);
     if (s_hm) atomicAdd(&sums[5], s_hm);
   }
-  if (max_pre) atomicMax(&sums[1], (unsigned long long)max_pre);
-  if (max_w) atomicMax(&sums[6], max_w);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const int32_t op = __shfl_xor(max_pre, d, 64);
+    const unsigned long long ow = __shfl_xor(max_w, d, 64);
+    max_pre = op > max_pre ? op : max_pre;
+    max_w = ow > max_w ? ow : max_w;
+  }
+  if (__lane_id() == 0) {
+    if (max_pre) atomicMax(&sums[1], (unsigned long long)max_pre);
+    if (max_w) atomicMax(&sums[6], max_w);
+  }
 }
 
 __global__ void compact_kernel(const int32_t* __restrict__ is_light, const int32_t* __restrict__ is_heavy,

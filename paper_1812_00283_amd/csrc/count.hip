@@ -51,6 +51,7 @@ struct CountParams {
   int32_t* cursor;
   int64_t cursor_stride;
   unsigned int* ticket;
+  int32_t* status;             // bit 0: a window could not be made to fit (internal error)
   int32_t dense_ratio;
   int32_t window_mode;
   int32_t hash_window_wedges;
@@ -108,61 +109,57 @@ __device__ __forceinline__ int32_t gallop_lower_bound(const int32_t* __restrict_
 }
 
 // ------------------------------------------------------------ wavefront walk
-// Up to this many end-id loads are in flight per lane.
-constexpr int kInFlight = 4;
+// Positions each lane takes per step of a walk (strided by 64, so one load
+// instruction reads 64 consecutive slots of one or a few middles).
+constexpr int kSteps = 8;
 
-template <typename T>
-__device__ __forceinline__ T wave_inclusive_max(T v) {
-  const int lane = __lane_id();
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const T o = __shfl_up(v, d, 64);
-    if (lane >= d && o > v) v = o;
-  }
-  return v;
-}
+// Per-wavefront LDS state of one walk: slice starts and exclusive offsets of
+// up to 64 middles (exc[64] holds the total).
+struct WalkLds {
+  int32_t cs[64];
+  int32_t exc[65];
+};
 
-// Visits every wedge of a group of up to 64 middles.  Lane l holds middle l's
-// end slice [cs, cs + len) in adj_other.  Wedges are numbered 0..tot-1 in
-// middle order and the wavefront takes 64 consecutive numbers per step, so
-// consecutive lanes load consecutive end ids.  The middle of position f is
-// found without a search: lanes mark the positions where a middle starts
-// (wavefront-private LDS `mark`), a running maximum over lanes spreads each
-// middle to its positions, and a ballot gives the middle already open at the
-// step's first position.  fn(middle lane, slot, end) is called per wedge.
+// Visits every wedge of a group of up to 64 middles.  Lane l holds middle
+// l's end slice [cs, cs + len) in adj_other.  Wedges are numbered 0..tot-1
+// in middle order; position f is taken by lane f mod 64, and each lane keeps
+// its current middle and advances it through the offsets in LDS (positions
+// only increase), so finding a wedge's middle costs about one LDS read.
+// Each lane issues kSteps end-id loads before using any of them.
+// fn(middle lane, slot, end) is called per wedge.
 template <typename Fn>
-__device__ __forceinline__ void wave_walk(const int32_t* __restrict__ oadj, int32_t cs, int32_t len,
-                                          int32_t* mark, Fn&& fn) {
+__device__ __forceinline__ void wave_walk(const int32_t* __restrict__ oadj, int32_t cs, int32_t len, WalkLds& L,
+                                          Fn&& fn) {
   const int lane = __lane_id();
   const int32_t inc = wave_inclusive_scan(len);
   const int32_t tot = __shfl(inc, 63, 64);
-  const int32_t exc = inc - len;
-  const bool open = len > 0;
-  for (int32_t f0 = 0; f0 < tot; f0 += 64 * kInFlight) {
-    int32_t slot[kInFlight];
-    int mid[kInFlight];
-    int32_t w[kInFlight];
+  __builtin_amdgcn_wave_barrier();
+  L.cs[lane] = cs;
+  L.exc[lane] = inc - len;
+  if (lane == 63) L.exc[64] = tot;
+  __builtin_amdgcn_wave_barrier();
+  int mid = 0;
+  for (int32_t f0 = 0; f0 < tot; f0 += 64 * kSteps) {
+    int32_t slot[kSteps], w[kSteps];
+    int midq[kSteps];
 #pragma unroll
-    for (int q = 0; q < kInFlight; ++q) {
-      const int32_t fb = f0 + 64 * q;
-      const uint64_t before = __ballot(open && exc <= fb);
-      const int first = before ? 63 - __clzll(before) : 0;
-      mark[lane] = -1;
-      __builtin_amdgcn_wave_barrier();
-      if (open && exc > fb && exc < fb + 64) mark[exc - fb] = lane;
-      __builtin_amdgcn_wave_barrier();
-      int mk = mark[lane];
-      __builtin_amdgcn_wave_barrier();
-      mk = wave_inclusive_max(mk > first ? mk : first);
-      mid[q] = mk;
-      slot[q] = __shfl(cs, mk, 64) + (fb + lane - __shfl(exc, mk, 64));
+    for (int q = 0; q < kSteps; ++q) {
+      const int32_t f = f0 + 64 * q + lane;
+      w[q] = -1;
+      slot[q] = 0;
+      midq[q] = 0;
+      if (f < tot) {
+        while (L.exc[mid + 1] <= f) ++mid;  // exc[64] = tot > f bounds the loop
+        slot[q] = L.cs[mid] + (f - L.exc[mid]);
+        midq[q] = mid;
+        w[q] = oadj[slot[q]];
+      }
     }
 #pragma unroll
-    for (int q = 0; q < kInFlight; ++q) w[q] = (f0 + 64 * q + lane < tot) ? oadj[slot[q]] : -1;
-#pragma unroll
-    for (int q = 0; q < kInFlight; ++q)
-      if (w[q] >= 0) fn(mid[q], slot[q], w[q]);
+    for (int q = 0; q < kSteps; ++q)
+      if (w[q] >= 0) fn(midq[q], slot[q], w[q]);
   }
+  __builtin_amdgcn_wave_barrier();
 }
 
 // ------------------------------------------------------------ hash tables
@@ -195,13 +192,13 @@ constexpr int kLightCap = 2048;  // table entries per wavefront; light_max <= kL
 __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
   __shared__ int32_t tkeys[kLightWaves][kLightCap];
   __shared__ int32_t tcnt[kLightWaves][kLightCap];
-  __shared__ int32_t tmark[kLightWaves][64];
+  __shared__ WalkLds twalk[kLightWaves];
   __shared__ unsigned long long tdelta[kLightWaves][64];
   const int lane = __lane_id();
   const int wv = threadIdx.x >> 6;
   int32_t* keys = tkeys[wv];
   int32_t* cnt = tcnt[wv];
-  int32_t* mark = tmark[wv];
+  WalkLds& L = twalk[wv];
   unsigned long long* dsum = tdelta[wv];
   for (int h = lane; h < kLightCap; h += 64) { keys[h] = 0; cnt[h] = 0; }
   dsum[lane] = 0;
@@ -228,7 +225,7 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
         cs = O.off[S.adj[k]];
         len = S.rev[k] - cs;
       }
-      wave_walk(O.adj, cs, len, mark, [&](int, int32_t, int32_t w) { wave_hash_add(keys, cnt, mask, w); });
+      wave_walk(O.adj, cs, len, L, [&](int, int32_t, int32_t w) { wave_hash_add(keys, cnt, mask, w); });
     }
     unsigned long long a = 0;
     if (mode == kVertex) {
@@ -268,7 +265,7 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
           cs = O.off[v];
           len = S.rev[k] - cs;
         }
-        wave_walk(O.adj, cs, len, mark, [&](int mid, int32_t slot, int32_t w) {
+        wave_walk(O.adj, cs, len, L, [&](int mid, int32_t slot, int32_t w) {
           const int32_t c = hash_get(keys, cnt, mask, w);
           if (c > 1) {
             const unsigned long long d = (unsigned long long)(c - 1);
@@ -276,13 +273,13 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
             atomicAdd(&dsum[mid], d);
           }
         });
-        __builtin_amdgcn_wave_barrier();
         const unsigned long long d = dsum[lane];
         if (d) {
           if (mode == kEdge) atomicAdd(&acc_s[base + j], d);
           else atomicAdd(&vmid[O.id_of[v]], d);
           dsum[lane] = 0;
         }
+        __builtin_amdgcn_wave_barrier();
       }
     }
     for (uint32_t h = lane; h < cap; h += 64) { keys[h] = 0; cnt[h] = 0; }
@@ -299,29 +296,34 @@ constexpr int kHeavyWaves = kHeavyNT / 64;
 constexpr int kTableWords = 32768;          // 128 KB of LDS
 constexpr int kHashCap = kTableWords / 2;   // keys | counts
 constexpr int kHashSingleMax = 8192;        // one hash window suffices below this many wedges
+constexpr int32_t kNone = 0x7FFFFFFF;       // "no further end" in a middle's cursor
 
-__device__ __forceinline__ void block_hash_add(int32_t* table, uint32_t cap, int32_t w, int32_t* s_fill,
-                                               int32_t* s_over) {
+// Inserts end w into the workgroup hash table (count 1, or bumps its count).
+// Returns 1 when w is a new key.  A probe sequence longer than kMaxProbe, or
+// a window already flagged as overfull, sets/keeps the flag and inserts
+// nothing more: the window is then halved and walked again, so an overfull
+// table never turns into long scans.
+constexpr uint32_t kMaxProbe = 64;
+
+__device__ __forceinline__ int block_hash_add(int32_t* table, uint32_t cap, int32_t w, int32_t* s_over) {
+  if (*(volatile int32_t*)s_over) return 0;
   int32_t* keys = table;
   int32_t* cnt = table + cap;
   const int32_t key = w + 1;
   const uint32_t mask = cap - 1;
   uint32_t h = mix32((uint32_t)w) & mask;
-  for (uint32_t probe = 0; probe < cap; ++probe) {
+  for (uint32_t probe = 0; probe < kMaxProbe; ++probe) {
     const int32_t cur = keys[h];
-    if (cur == key) { atomicAdd(&cnt[h], 1); return; }
+    if (cur == key) { atomicAdd(&cnt[h], 1); return 0; }
     if (cur == 0) {
       const int32_t old = atomicCAS(&keys[h], 0, key);
-      if (old == 0) {
-        atomicAdd(&cnt[h], 1);
-        if (atomicAdd(s_fill, 1) >= (int32_t)(cap - cap / 4)) *s_over = 1;
-        return;
-      }
-      if (old == key) { atomicAdd(&cnt[h], 1); return; }
+      if (old == 0) { atomicAdd(&cnt[h], 1); return 1; }
+      if (old == key) { atomicAdd(&cnt[h], 1); return 0; }
     }
     h = (h + 1) & mask;
   }
   *s_over = 1;
+  return 0;
 }
 
 // Dense window counters: 32-bit, or two 16-bit counters per word when every
@@ -336,9 +338,17 @@ __device__ __forceinline__ int32_t dense_get(const int32_t* table, int32_t i, bo
   return table[i];
 }
 
+// Takes the next group index of the workgroup's current pass (wave-uniform).
+__device__ __forceinline__ int32_t next_group(int32_t* s_next) {
+  int32_t g = 0;
+  if (__lane_id() == 0) g = atomicAdd(s_next, 1);
+  return __shfl(g, 0, 64);
+}
+
 __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
-  __shared__ int32_t table[kTableWords];
-  __shared__ int32_t tmark[kHeavyWaves][64];
+  __shared__ __align__(16) int32_t table[kTableWords];
+  __shared__ WalkLds twalk[kHeavyWaves];
+  __shared__ int32_t tqueue[kHeavyWaves][128];
   __shared__ unsigned long long tdelta[kHeavyWaves][64];
   __shared__ unsigned long long s_red64[kHeavyWaves + 1];
   __shared__ int32_t s_idx, s_fill, s_over, s_next;
@@ -347,10 +357,14 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
   const int lane = __lane_id();
   const int wv = t >> 6;
   const int mode = p.mode;
-  int32_t* mark = tmark[wv];
+  WalkLds& L = twalk[wv];
+  int32_t* queue = tqueue[wv];
   unsigned long long* dsum = tdelta[wv];
-  int32_t* cur_in = p.cursor + (int64_t)blockIdx.x * 2 * p.cursor_stride;
-  int32_t* cur_out = cur_in + p.cursor_stride;
+  // per-middle cursor state of multi-window starts: next slot, end id at
+  // that slot (kNone when exhausted), and the window's end slot
+  int32_t* pos = p.cursor + (int64_t)blockIdx.x * 3 * p.cursor_stride;
+  int32_t* nxt = pos + p.cursor_stride;
+  int32_t* cend = nxt + p.cursor_stride;
   for (int i = t; i < kTableWords; i += kHeavyNT) table[i] = 0;
   dsum[lane] = 0;
   unsigned long long acc_total = 0;
@@ -370,8 +384,9 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
     const int32_t pre = S.lo[r];
     const int64_t W = S.work[r];
     const int32_t range = r;
-    const bool dense = p.window_mode == 2 || (p.window_mode == 1 && W * (int64_t)p.dense_ratio >= (int64_t)range);
-    const bool half = dense && pre < 65536;
+    const bool dense = p.window_mode == 2 ||
+                       (p.window_mode == 1 && (W > kHashSingleMax || W * (int64_t)p.dense_ratio >= (int64_t)range));
+    const bool half = pre < 65536;
     int32_t width;
     uint32_t cap = kHashCap;
     if (dense) {
@@ -384,14 +399,13 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       const int64_t wd = (int64_t)range * p.hash_window_wedges / W;
       width = (int32_t)(wd < 256 ? 256 : (wd > range ? range : wd));
     }
-    unsigned long long start_acc = 0;
     // Starts in the dense block: the last window covers the block's end ranks
-    // [top, r); its counters start from the MFMA products and its pass 1 walks
-    // only middles outside the other layer's block.
+    // [top, r); its counters start from the MFMA products and its first pass
+    // walks only middles outside the other layer's block (a prefix).
     const int32_t top = x ? p.dtop[1] : p.dtop[0];
     const bool in_block = r > top;
     const int32_t sparse_end = in_block ? top : range;
-    int32_t pre_out = pre;  // middles outside the other layer's block (a prefix)
+    int32_t pre_out = pre;
     if (in_block) {
       const int32_t otop = x ? p.dtop[0] : p.dtop[1];
       int32_t a = 0, b = pre;
@@ -401,10 +415,22 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       }
       pre_out = a;
     }
+    // one window over [0, range) needs no cursors; otherwise every middle
+    // keeps its next slot and next end id in scratch
+    bool cursors = !(sparse_end == range && width >= range);
+    if (cursors) {
+      for (int32_t j = t; j < pre; j += kHeavyNT) {
+        const int32_t k = base + j;
+        const int32_t ps = O.off[S.adj[k]];
+        pos[j] = ps;
+        nxt[j] = ps < S.rev[k] ? O.adj[ps] : kNone;
+      }
+    }
+    unsigned long long start_acc = 0;
     int32_t lo_w = 0;
     for (;;) {
       int32_t hi_w;
-      bool wdense = dense, whalf = half;
+      bool wdense = dense, whalf = half && dense;
       const bool seeded = lo_w >= sparse_end;
       if (!seeded) {
         hi_w = (int64_t)lo_w + width >= sparse_end ? sparse_end : lo_w + width;
@@ -416,69 +442,125 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         break;
       }
       const int32_t pre1 = seeded ? pre_out : pre;
-      bool multi = !(lo_w == 0 && hi_w == range);
       if (seeded) {
         const int32_t* crow = (x ? p.dC[1] : p.dC[0]) + (int64_t)(r - top) * (x ? p.dld[1] : p.dld[0]);
         for (int32_t i = t; i < range - top; i += kHeavyNT) table[i] = crow[i];
       }
+      // cursors advance during pass 1 only for dense windows of a total count
+      // (a hash window may have to be redone; pass 2 needs the old cursors)
+      const bool advance_now = wdense && mode == kTotal;
       // ---- pass 1: count the wedges whose end lies in [lo_w, hi_w)
+      int32_t halvings = 0;
       for (;;) {
         if (t == 0) { s_fill = 0; s_over = 0; s_next = 0; }
         __syncthreads();
+        int32_t qn = 0;
         for (;;) {
-          int32_t g = 0;
-          if (lane == 0) g = atomicAdd(&s_next, 1);
-          g = __shfl(g, 0, 64);
-          const int32_t j0 = g * 64;
-          if (j0 >= pre1) break;
-          const int32_t j = j0 + lane;
-          int32_t cs = 0, ce = 0;
-          if (j < pre1) {
-            const int32_t k = base + j;
-            const int32_t v = S.adj[k];
-            const int32_t e = S.rev[k];
-            cs = lo_w == 0 ? O.off[v] : cur_in[j];
-            ce = hi_w >= range ? e : gallop_lower_bound(O.adj, cs, e, hi_w);
-            if (multi && !seeded) cur_out[j] = ce;
+          const int32_t g = next_group(&s_next);
+          const bool done = g * 64 >= pre1;
+          if (!cursors) {
+            if (done) break;
+            const int32_t j = g * 64 + lane;
+            int32_t cs = 0, ce = 0;
+            if (j < pre1) {
+              const int32_t k = base + j;
+              cs = O.off[S.adj[k]];
+              ce = S.rev[k];
+            }
+            if (wdense) {
+              wave_walk(O.adj, cs, ce - cs, L, [&](int, int32_t, int32_t w) { dense_add(table, w - lo_w, whalf); });
+            } else {
+              int32_t fresh = 0;
+              wave_walk(O.adj, cs, ce - cs, L,
+                        [&](int, int32_t, int32_t w) { fresh += block_hash_add(table, cap, w, &s_over); });
+              fresh = wave_sum(fresh);
+              if (lane == 0 && fresh && atomicAdd(&s_fill, fresh) + fresh > (int32_t)(cap / 8 * 5)) s_over = 1;
+              if (*(volatile int32_t*)&s_over) break;
+            }
+            continue;
           }
-          if (wdense) {
-            wave_walk(O.adj, cs, ce - cs, mark, [&](int, int32_t, int32_t w) { dense_add(table, w - lo_w, whalf); });
-          } else {
-            wave_walk(O.adj, cs, ce - cs, mark,
-                      [&](int, int32_t, int32_t w) { block_hash_add(table, cap, w, &s_fill, &s_over); });
-            if (*(volatile int32_t*)&s_over) break;
+          // compact the middles with an end in this window into full groups of 64
+          if (!done) {
+            const int32_t j = g * 64 + lane;
+            const bool act = j < pre1 && nxt[j] < hi_w;
+            const uint64_t am = __ballot(act);
+            if (act) queue[qn + __popcll(am & __lanemask_lt())] = j;
+            qn += __popcll(am);
+            __builtin_amdgcn_wave_barrier();
           }
+          while (qn >= 64 || (done && qn > 0)) {
+            const int32_t j = lane < qn ? queue[lane] : -1;
+            __builtin_amdgcn_wave_barrier();
+            if (qn > 64 && lane < qn - 64) queue[lane] = queue[64 + lane];
+            __builtin_amdgcn_wave_barrier();
+            qn = qn > 64 ? qn - 64 : 0;
+            int32_t cs = 0, ce = 0;
+            if (j >= 0) {
+              const int32_t k = base + j;
+              const int32_t e = S.rev[k];
+              cs = pos[j];  // O.adj[cs] = nxt[j] < hi_w
+              ce = hi_w >= range ? e : gallop_lower_bound(O.adj, cs + 1, e, hi_w);
+              if (advance_now) {
+                pos[j] = ce;
+                nxt[j] = ce < e ? O.adj[ce] : kNone;
+              } else {
+                cend[j] = ce;
+              }
+            }
+            if (wdense) {
+              wave_walk(O.adj, cs, ce - cs, L, [&](int, int32_t, int32_t w) { dense_add(table, w - lo_w, whalf); });
+            } else {
+              int32_t fresh = 0;
+              wave_walk(O.adj, cs, ce - cs, L,
+                        [&](int, int32_t, int32_t w) { fresh += block_hash_add(table, cap, w, &s_over); });
+              fresh = wave_sum(fresh);
+              if (lane == 0 && fresh && atomicAdd(&s_fill, fresh) + fresh > (int32_t)(cap / 8 * 5)) s_over = 1;
+            }
+          }
+          if (done) break;
+          if (!wdense && *(volatile int32_t*)&s_over) break;
         }
         __syncthreads();
         if (wdense || !s_over) break;
-        // the window holds too many distinct ends for the table: halve it and redo
+        // the window holds too many distinct ends for the table: halve it and
+        // redo.  A start walked without cursors (one window over its whole
+        // end range) switches to cursors first, so the smaller window applies.
         for (int i = t; i < (int)(2 * cap); i += kHeavyNT) table[i] = 0;
+        if (!cursors) {
+          for (int32_t j = t; j < pre; j += kHeavyNT) {
+            const int32_t k = base + j;
+            const int32_t ps = O.off[S.adj[k]];
+            pos[j] = ps;
+            nxt[j] = ps < S.rev[k] ? O.adj[ps] : kNone;
+          }
+          cursors = true;
+        }
         __syncthreads();
+        // a window of one end rank holds one distinct end, so this ends after
+        // at most 31 halvings; the cap only guards against a logic error
+        if (++halvings > 40) {
+          if (t == 0) atomicOr(p.status, 1);
+          break;
+        }
         hi_w = lo_w + ((hi_w - lo_w) > 1 ? (hi_w - lo_w) / 2 : 1);
-        multi = true;
       }
-      // ---- pass 2 (per-vertex / per-edge): count - 1 to both edges of every wedge
+      // ---- pass 2 (per-vertex / per-edge): count - 1 to both edges of every
+      // wedge; also advances the cursors past this window
       if (mode != kTotal) {
         unsigned long long* acc_s = pick_ptr(p.acc, x);
         unsigned long long* acc_o = pick_ptr(p.acc, 1 - x);
         unsigned long long* vmid = pick_ptr(p.vout, 1 - x);
-        if (t == 0) s_next = 0;
-        __syncthreads();
-        for (;;) {
-          int32_t g = 0;
-          if (lane == 0) g = atomicAdd(&s_next, 1);
-          g = __shfl(g, 0, 64);
-          const int32_t j0 = g * 64;
-          if (j0 >= pre) break;
-          const int32_t j = j0 + lane;
-          int32_t cs = 0, ce = 0, v = 0;
-          if (j < pre) {
-            const int32_t k = base + j;
+        // walks the middles of one group (lane's middle jl, or -1) and advances their cursors
+        auto walk2 = [&](int32_t jl) {
+          int32_t cs = 0, ce = 0, v = 0, e = 0;
+          if (jl >= 0) {
+            const int32_t k = base + jl;
             v = S.adj[k];
-            cs = lo_w == 0 ? O.off[v] : cur_in[j];
-            ce = (multi && !seeded) ? cur_out[j] : S.rev[k];
+            e = S.rev[k];
+            cs = cursors ? pos[jl] : O.off[v];
+            ce = (!cursors || hi_w >= range) ? e : cend[jl];
           }
-          wave_walk(O.adj, cs, ce - cs, mark, [&](int mid, int32_t slot, int32_t w) {
+          wave_walk(O.adj, cs, ce - cs, L, [&](int mid, int32_t slot, int32_t w) {
             const int32_t c = wdense ? dense_get(table, w - lo_w, whalf) : hash_get(table, table + cap, cap - 1, w);
             if (c > 1) {
               const unsigned long long d = (unsigned long long)(c - 1);
@@ -486,24 +568,76 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
               atomicAdd(&dsum[mid], d);
             }
           });
-          __builtin_amdgcn_wave_barrier();
           const unsigned long long d = dsum[lane];
-          if (d) {
-            if (mode == kEdge) atomicAdd(&acc_s[base + j], d);
-            else atomicAdd(&vmid[O.id_of[v]], d);
-            dsum[lane] = 0;
+          if (jl >= 0) {
+            if (d) {
+              if (mode == kEdge) atomicAdd(&acc_s[base + jl], d);
+              else atomicAdd(&vmid[O.id_of[v]], d);
+            }
+            if (cursors) {
+              pos[jl] = ce;
+              nxt[jl] = ce < e ? O.adj[ce] : kNone;
+            }
           }
+          dsum[lane] = 0;
+          __builtin_amdgcn_wave_barrier();
+        };
+        if (t == 0) s_next = 0;
+        __syncthreads();
+        int32_t qn = 0;
+        for (;;) {
+          const int32_t g = next_group(&s_next);
+          const bool done = g * 64 >= pre;
+          if (!cursors) {
+            if (done) break;
+            walk2(g * 64 + lane < pre ? g * 64 + lane : -1);
+            continue;
+          }
+          if (!done) {
+            const int32_t j = g * 64 + lane;
+            const bool act = j < pre && nxt[j] < hi_w;
+            const uint64_t am = __ballot(act);
+            if (act) queue[qn + __popcll(am & __lanemask_lt())] = j;
+            qn += __popcll(am);
+            __builtin_amdgcn_wave_barrier();
+          }
+          while (qn >= 64 || (done && qn > 0)) {
+            const int32_t jl = lane < qn ? queue[lane] : -1;
+            __builtin_amdgcn_wave_barrier();
+            if (qn > 64 && lane < qn - 64) queue[lane] = queue[64 + lane];
+            __builtin_amdgcn_wave_barrier();
+            qn = qn > 64 ? qn - 64 : 0;
+            walk2(jl);
+          }
+          if (done) break;
         }
         __syncthreads();
+      } else if (cursors && !advance_now) {
+        // hash window of a total count: advance the cursors now that the window is final
+        for (int32_t j = t; j < pre1; j += kHeavyNT) {
+          if (nxt[j] < hi_w) {
+            const int32_t ce = cend[j];
+            pos[j] = ce;
+            nxt[j] = ce < S.rev[base + j] ? O.adj[ce] : kNone;
+          }
+        }
       }
       // ---- finalize the window: C(count,2) per end, then clear the table
       unsigned long long* vs = pick_ptr(p.vout, x);
       if (wdense) {
         const int32_t wn = hi_w - lo_w;
         const int32_t words = whalf ? (wn + 1) >> 1 : wn;
-        for (int32_t i = t; i < words; i += kHeavyNT) {
-          const uint32_t word = (uint32_t)table[i];
-          if (word) {
+        const int32_t quads = (words + 3) >> 2;
+        uint4* t4 = reinterpret_cast<uint4*>(table);
+        for (int32_t i4 = t; i4 < quads; i4 += kHeavyNT) {
+          const uint4 q4 = t4[i4];
+          if ((q4.x | q4.y | q4.z | q4.w) == 0u) continue;
+          const uint32_t wd[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const uint32_t word = wd[c];
+            if (!word) continue;
+            const int32_t i = 4 * i4 + c;
             if (whalf) {
               const int32_t c0 = (int32_t)(word & 0xFFFFu), c1 = (int32_t)(word >> 16);
               if (c0 > 1) {
@@ -521,8 +655,8 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
               start_acc += cc;
               if (mode == kVertex) atomicAdd(&vs[S.id_of[lo_w + i]], cc);
             }
-            table[i] = 0;
           }
+          t4[i4] = make_uint4(0u, 0u, 0u, 0u);
         }
       } else {
         for (uint32_t h = t; h < cap; h += kHeavyNT) {
@@ -539,12 +673,15 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
           }
         }
       }
-      __syncthreads();
-      if (multi && !seeded) {
-        int32_t* tmp = cur_in;
-        cur_in = cur_out;
-        cur_out = tmp;
+      if (!wdense && cursors && !seeded) {
+        // size the next hash window from this one's distinct ends (aim: a quarter of the table)
+        const int64_t span = hi_w - lo_w;
+        const int64_t fill = s_fill;
+        int64_t next = fill > 0 ? span * (int64_t)(cap / 4) / fill : 2 * span;
+        next = next < 64 ? 64 : next;
+        width = (int32_t)(next > range ? range : next);
       }
+      __syncthreads();
       lo_w = hi_w;
     }
     if (mode == kVertex) {
@@ -607,10 +744,14 @@ void zero_u64(void* p, int64_t n, hipStream_t s) {
   BFC_LAUNCH_CHECK();
 }
 
+int32_t* count_status(bfc_graph_s* g) {
+  return reinterpret_cast<int32_t*>(g->scratch.as<char>() + g->scratch_bytes - 128);
+}
+
 void prepare_count(bfc_graph_s* g, hipStream_t s) {
   prepare_dense(g, s);
-  // two cursor arrays per heavy workgroup, then 256 bytes for the ticket
-  const size_t need = (size_t)heavy_grid_for(g) * 2 * (size_t)cursor_stride_for(g) * sizeof(int32_t) + 256;
+  // three cursor arrays per heavy workgroup, then 256 bytes for the ticket
+  const size_t need = (size_t)heavy_grid_for(g) * 3 * (size_t)cursor_stride_for(g) * sizeof(int32_t) + 256;
   if (g->scratch_bytes < need) {
     g->scratch.alloc(need, s);
     g->scratch_bytes = need;
@@ -625,6 +766,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   const int64_t stride = cursor_stride_for(g);
   int32_t* cursor = g->scratch.as<int32_t>();
   unsigned int* ticket = reinterpret_cast<unsigned int*>(g->scratch.as<char>() + g->scratch_bytes - 256);
+  int32_t* status = reinterpret_cast<int32_t*>(g->scratch.as<char>() + g->scratch_bytes - 128);
 
   CountParams p{};
   for (int x = 0; x < 2; ++x) {
@@ -640,6 +782,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   p.cursor = cursor;
   p.cursor_stride = stride;
   p.ticket = ticket;
+  p.status = status;
   p.dense_ratio = g->tune.dense_min_ratio;
   p.window_mode = g->tune.window_mode;
   p.hash_window_wedges = g->tune.hash_window_wedges;
@@ -668,7 +811,8 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     p.dld[0] = d.PU;
     p.dld[1] = d.PL;
   }
-  if (sc.n_heavy > 0) zero_u64(ticket, 1, s);
+  zero_u64(ticket, 1, s);      // ticket (4 bytes) and padding
+  zero_u64(status, 1, s);
   // events: [0] dense block [1] light [2] heavy [3] fold [4]
   bfc_graph_s::TimedCall tc{};
   if (g->timing) {

@@ -199,6 +199,8 @@ void build_batch(bfc_graph_s* g, const int32_t* edges, const int64_t* eoff_host,
 // Allocates the count kernels' scratch for the current schedule on stream s
 // (not capture-safe; called when a schedule is built).
 void prepare_count(bfc_graph_s* g, hipStream_t s);
+// Device status word of the count kernels (0 = fine), reset by every count call.
+int32_t* count_status(bfc_graph_s* g);
 // Sums the durations of timed count calls (waits for them).
 void collect_times(bfc_graph_s* g);
 // Dense block: sizes and buffers for the current tuning, and the MFMA
