@@ -164,6 +164,8 @@ bfc_status bfc_destroy(bfc_graph g);
  *                      hash windows.  Default 4.
  *   window_mode        1 = automatic (default), 2 = always dense windows,
  *                      3 = always hash windows.
+ *   dense_min_wedges   in automatic mode a start also uses dense windows when
+ *                      it has more than this many wedges.  Default 8192.
  *   hash_window_wedges wedges aimed at per hash window of a large start (the
  *                      window is halved when its distinct ends overfill the
  *                      table).  Default 4096.
@@ -176,6 +178,7 @@ typedef struct {
   int32_t window_mode;
   int32_t hash_window_wedges;
   int32_t dense_block;
+  int32_t dense_min_wedges;
 } bfc_tuning;
 
 bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t);

@@ -45,7 +45,7 @@ class BfcError(RuntimeError):
 class Tuning(ctypes.Structure):
     _fields_ = [("light_max_wedges", ctypes.c_int32), ("dense_min_ratio", ctypes.c_int32),
                 ("window_mode", ctypes.c_int32), ("hash_window_wedges", ctypes.c_int32),
-                ("dense_block", ctypes.c_int32)]
+                ("dense_block", ctypes.c_int32), ("dense_min_wedges", ctypes.c_int32)]
 
 
 class ScheduleInfo(ctypes.Structure):
@@ -212,10 +212,10 @@ class Graph:
         return {"m": m.value, "n_upper": nu.value, "n_lower": nl.value, "wedges": w.value, "device_bytes": b.value}
 
     def set_tuning(self, light_max_wedges: int = 0, dense_min_ratio: int = 0, window_mode: int = 0,
-                   hash_window_wedges: int = 0, dense_block: int = -1) -> None:
+                   hash_window_wedges: int = 0, dense_block: int = -1, dense_min_wedges: int = 0) -> None:
         """Changes which kernel path handles each start; no count changes.
         window_mode: 1 automatic, 2 dense windows only, 3 hash windows only."""
-        t = Tuning(light_max_wedges, dense_min_ratio, window_mode, hash_window_wedges, dense_block)
+        t = Tuning(light_max_wedges, dense_min_ratio, window_mode, hash_window_wedges, dense_block, dense_min_wedges)
         _check(load().bfc_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
@@ -223,7 +223,7 @@ class Graph:
         _check(load().bfc_get_tuning(self._h, ctypes.byref(t)))
         return {"light_max_wedges": t.light_max_wedges, "dense_min_ratio": t.dense_min_ratio,
                 "window_mode": t.window_mode, "hash_window_wedges": t.hash_window_wedges,
-                "dense_block": t.dense_block}
+                "dense_block": t.dense_block, "dense_min_wedges": t.dense_min_wedges}
 
     def schedule_info(self) -> dict:
         si = ScheduleInfo()

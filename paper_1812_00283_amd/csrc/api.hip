@@ -371,6 +371,7 @@ bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t) {
     if (t->window_mode > 0) nt.window_mode = t->window_mode;
     if (t->hash_window_wedges > 0) nt.hash_window_wedges = t->hash_window_wedges;
     if (t->dense_block >= 0) nt.dense_block = t->dense_block;
+    if (t->dense_min_wedges > 0) nt.dense_min_wedges = t->dense_min_wedges;
     const bool resched = nt.light_max_wedges != h->tune.light_max_wedges || nt.dense_block != h->tune.dense_block;
     h->tune = nt;
     if (resched) {
@@ -434,6 +435,7 @@ bfc_status bfc_get_tuning(bfc_graph g, bfc_tuning* t) {
     t->window_mode = h->tune.window_mode;
     t->hash_window_wedges = h->tune.hash_window_wedges;
     t->dense_block = h->tune.dense_block;
+    t->dense_min_wedges = h->tune.dense_min_wedges;
   });
 }
 

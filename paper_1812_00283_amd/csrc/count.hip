@@ -55,6 +55,7 @@ struct CountParams {
   int32_t dense_ratio;
   int32_t window_mode;
   int32_t hash_window_wedges;
+  int32_t dense_min_wedges;
   unsigned long long* gtotal;  // per-graph totals of a batch (kTotal), else null
   const int32_t* gid[2];       // graph index of every rank, per layer (null: one graph)
   int32_t dtop[2];             // first rank of the dense block per layer (n_X when disabled)
@@ -338,35 +339,98 @@ __device__ __forceinline__ int32_t dense_get(const int32_t* table, int32_t i, bo
   return table[i];
 }
 
-// Takes the next group index of the workgroup's current pass (wave-uniform).
-__device__ __forceinline__ int32_t next_group(int32_t* s_next) {
-  int32_t g = 0;
-  if (__lane_id() == 0) g = atomicAdd(s_next, 1);
-  return __shfl(g, 0, 64);
+// ------------------------------------------------------------ flattened walk
+// A batch of (middle, window) slices is held in LDS as a segment list:
+// se[i] = exclusive prefix of the slice lengths (strictly increasing, every
+// slice is non-empty; se[n] = total), sd[i] = slice start slot - se[i], so
+// the slot of flattened position f inside segment i is sd[i] + f.
+
+// Visits positions [F0, F1) of a segment list of n entries (n < 4096).
+// Lane l takes positions F0 + l, F0 + 64 + l, ...  Per step of 64 positions
+// the wavefront loads the next 64 segment starts; a start d positions into
+// the step marks lane d (ds_permute), and a lane's segment is the current
+// one plus the number of marks at or below it (ballot + popcount), so
+// locating segments costs O(1) per step however short they are.
+// fn(segment, slot, end) is called per wedge; stop() is polled (uniformly)
+// after every kSteps steps.
+template <typename Fn, typename Stop>
+__device__ __forceinline__ void seg_walk(const int32_t* __restrict__ oadj, const int32_t* se, const int32_t* sd,
+                                         int32_t n, int32_t F0, int32_t F1, Fn&& fn, Stop&& stop) {
+  if (F0 >= F1) return;
+  const int lane = __lane_id();
+  const uint64_t le_mask = __lanemask_lt() | (1ull << lane);
+  // segment holding F0: largest s with se[s] <= F0 (se[0] = 0), by two
+  // rounds of a 64-way search over se[0..n]
+  int32_t s0;
+  {
+    const int32_t n1 = n + 1;
+    const int32_t stride = (n1 + 63) >> 6;
+    int32_t i = lane * stride;
+    const int32_t c1 = __popcll(__ballot(i < n1 && se[i] <= F0)) - 1;
+    const int32_t lo = c1 * stride;
+    i = lo + lane;
+    s0 = lo + __popcll(__ballot(lane < stride && i < n1 && se[i] <= F0)) - 1;
+  }
+  int32_t sd0 = sd[s0];
+  for (int32_t f0 = F0; f0 < F1; f0 += 64 * kSteps) {
+    int32_t slot[kSteps], w[kSteps], sg[kSteps];
+#pragma unroll
+    for (int q = 0; q < kSteps; ++q) {
+      const int32_t f = f0 + 64 * q;
+      w[q] = -1;
+      slot[q] = 0;
+      sg[q] = 0;
+      if (f < F1) {
+        // invariant: se[s0] <= f < se[s0 + 1], so every loaded start is > f
+        const int32_t idx = s0 + 1 + lane;
+        const int32_t b = idx <= n ? se[idx] : 0x7FFFFFFF;
+        const int32_t g = idx < n ? sd[idx] : 0;
+        const int32_t d = b - f;
+        const int32_t mark = __builtin_amdgcn_ds_permute(d < 64 ? 4 * d : 0, d < 64 ? 1 : 0);
+        const int32_t c = __popcll(__ballot(mark != 0) & le_mask);
+        const int32_t gc = __shfl(g, c > 0 ? c - 1 : 0, 64);
+        const int32_t base = c > 0 ? gc : sd0;
+        if (f + lane < F1) {
+          slot[q] = base + f + lane;
+          sg[q] = s0 + c;
+          w[q] = oadj[slot[q]];
+        }
+        const int32_t cn = __popcll(__ballot(d <= 64));
+        if (cn > 0) {
+          sd0 = __builtin_amdgcn_readlane(g, cn - 1);
+          s0 += cn;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kSteps; ++q)
+      if (w[q] >= 0) fn(sg[q], slot[q], w[q]);
+    if (stop()) break;
+  }
 }
+
+// Segment list capacities: pass 1 keeps (se, sd); pass 2 also keeps the
+// middle index and a 64-bit delta sum per segment.
+constexpr int kSeg1 = 2048;
+constexpr int kSeg2 = 1024;
+constexpr int kSegWords = 5124;  // max(2 * kSeg1 + 1, 3 * kSeg2 + 2 + 2 * kSeg2), rounded up
 
 __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
   __shared__ __align__(16) int32_t table[kTableWords];
-  __shared__ WalkLds twalk[kHeavyWaves];
-  __shared__ int32_t tqueue[kHeavyWaves][128];
-  __shared__ unsigned long long tdelta[kHeavyWaves][64];
+  __shared__ __align__(16) int32_t segbuf[kSegWords];
   __shared__ unsigned long long s_red64[kHeavyWaves + 1];
-  __shared__ int32_t s_idx, s_fill, s_over, s_next;
+  __shared__ int32_t s_idx, s_fill, s_over, s_cut_j, s_cut_lex;
 
   const int t = threadIdx.x;
   const int lane = __lane_id();
   const int wv = t >> 6;
   const int mode = p.mode;
-  WalkLds& L = twalk[wv];
-  int32_t* queue = tqueue[wv];
-  unsigned long long* dsum = tdelta[wv];
   // per-middle cursor state of multi-window starts: next slot, end id at
   // that slot (kNone when exhausted), and the window's end slot
   int32_t* pos = p.cursor + (int64_t)blockIdx.x * 3 * p.cursor_stride;
   int32_t* nxt = pos + p.cursor_stride;
   int32_t* cend = nxt + p.cursor_stride;
   for (int i = t; i < kTableWords; i += kHeavyNT) table[i] = 0;
-  dsum[lane] = 0;
   unsigned long long acc_total = 0;
 
   for (;;) {
@@ -384,8 +448,8 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
     const int32_t pre = S.lo[r];
     const int64_t W = S.work[r];
     const int32_t range = r;
-    const bool dense = p.window_mode == 2 ||
-                       (p.window_mode == 1 && (W > kHashSingleMax || W * (int64_t)p.dense_ratio >= (int64_t)range));
+    const bool dense = p.window_mode == 2 || (p.window_mode == 1 && (W > p.dense_min_wedges ||
+                                                                     W * (int64_t)p.dense_ratio >= (int64_t)range));
     const bool half = pre < 65536;
     int32_t width;
     uint32_t cap = kHashCap;
@@ -449,79 +513,135 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       // cursors advance during pass 1 only for dense windows of a total count
       // (a hash window may have to be redone; pass 2 needs the old cursors)
       const bool advance_now = wdense && mode == kTotal;
+
+      // Fills the segment list with the non-empty slices [cs, ce) of window
+      // [lo_w, hi_w) of middles rj, rj+1, ... < npre, up to `segcap` of
+      // them, 2 * kHeavyNT middles per sweep in middle order (one packed
+      // workgroup scan of (active, length)).  Leaves rj at the first middle
+      // not taken and returns the segment count and total length; the cursors
+      // of taken middles advance (or record the window end, cend) here.
+      auto fill = [&](int32_t npre, int32_t segcap, bool second, int32_t* se, int32_t* sd, int32_t* sj,
+                      unsigned long long* sdel, int32_t& rj, int32_t& nseg, int32_t& T) {
+        nseg = 0;
+        T = 0;
+        while (nseg < segcap && rj < npre) {
+          int32_t jv[2], csv[2], cev[2], ev[2];
+          bool actv[2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int32_t j = rj + 2 * t + h;
+            jv[h] = j;
+            actv[h] = false;
+            csv[h] = cev[h] = ev[h] = 0;
+            if (j < npre) {
+              const int32_t k = base + j;
+              const int32_t e = S.rev[k];
+              ev[h] = e;
+              if (!cursors) {
+                const int32_t cs = O.off[S.adj[k]];
+                csv[h] = cs;
+                cev[h] = e;
+                actv[h] = e > cs;
+              } else if (nxt[j] < hi_w) {
+                const int32_t cs = pos[j];  // O.adj[cs] = nxt[j] < hi_w
+                actv[h] = true;
+                csv[h] = cs;
+                cev[h] = hi_w >= range ? e : (second ? cend[j] : gallop_lower_bound(O.adj, cs + 1, e, hi_w));
+              }
+            }
+          }
+          const int32_t l0 = actv[0] ? cev[0] - csv[0] : 0;
+          const int32_t l1 = actv[1] ? cev[1] - csv[1] : 0;
+          const unsigned long long packed =
+              ((unsigned long long)((int)actv[0] + (int)actv[1]) << 32) | (uint32_t)(l0 + l1);
+          unsigned long long tot;
+          const unsigned long long ex = block_exclusive_scan<unsigned long long, kHeavyNT>(packed, s_red64, &tot);
+          const int32_t room = segcap - nseg;
+          const int32_t nact = (int32_t)(tot >> 32);
+          int32_t ia = (int32_t)(ex >> 32);
+          int32_t lex = (int32_t)(uint32_t)ex;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            if (!actv[h]) continue;
+            if (ia < room) {
+              const int32_t ps = nseg + ia;
+              se[ps] = T + lex;
+              sd[ps] = csv[h] - (T + lex);
+              if (second) {
+                sj[ps] = jv[h];
+                sdel[ps] = 0ull;
+              }
+              if (cursors) {
+                if (second || advance_now) {
+                  pos[jv[h]] = cev[h];
+                  nxt[jv[h]] = cev[h] < ev[h] ? O.adj[cev[h]] : kNone;
+                } else {
+                  cend[jv[h]] = cev[h];
+                }
+              }
+            } else if (ia == room) {
+              s_cut_j = jv[h];
+              s_cut_lex = lex;
+            }
+            ++ia;
+            lex += cev[h] - csv[h];
+          }
+          if (nact <= room) {
+            nseg += nact;
+            T += (int32_t)(uint32_t)tot;
+            rj = npre - rj > 2 * kHeavyNT ? rj + 2 * kHeavyNT : npre;
+          } else {
+            __syncthreads();
+            rj = s_cut_j;
+            T += s_cut_lex;
+            nseg = segcap;
+          }
+        }
+        if (t == 0) se[nseg] = T;
+        __syncthreads();
+      };
+      // this wavefront's share of the batch's positions
+      auto share = [&](int32_t T, int32_t& F0, int32_t& F1) {
+        F0 = (int32_t)((int64_t)T * wv / kHeavyWaves);
+        F1 = (int32_t)((int64_t)T * (wv + 1) / kHeavyWaves);
+      };
+
       // ---- pass 1: count the wedges whose end lies in [lo_w, hi_w)
       int32_t halvings = 0;
       for (;;) {
-        if (t == 0) { s_fill = 0; s_over = 0; s_next = 0; }
+        if (t == 0) { s_fill = 0; s_over = 0; }
         __syncthreads();
-        int32_t qn = 0;
-        for (;;) {
-          const int32_t g = next_group(&s_next);
-          const bool done = g * 64 >= pre1;
-          if (!cursors) {
-            if (done) break;
-            const int32_t j = g * 64 + lane;
-            int32_t cs = 0, ce = 0;
-            if (j < pre1) {
-              const int32_t k = base + j;
-              cs = O.off[S.adj[k]];
-              ce = S.rev[k];
-            }
-            if (wdense) {
-              wave_walk(O.adj, cs, ce - cs, L, [&](int, int32_t, int32_t w) { dense_add(table, w - lo_w, whalf); });
-            } else {
-              int32_t fresh = 0;
-              wave_walk(O.adj, cs, ce - cs, L,
-                        [&](int, int32_t, int32_t w) { fresh += block_hash_add(table, cap, w, &s_over); });
-              fresh = wave_sum(fresh);
-              if (lane == 0 && fresh && atomicAdd(&s_fill, fresh) + fresh > (int32_t)(cap / 8 * 5)) s_over = 1;
-              if (*(volatile int32_t*)&s_over) break;
-            }
-            continue;
+        int32_t* se = segbuf;
+        int32_t* sd = segbuf + kSeg1 + 1;
+        int32_t rj = 0;
+        bool over = false;
+        while (rj < pre1) {
+          int32_t nseg, T;
+          fill(pre1, kSeg1, false, se, sd, nullptr, nullptr, rj, nseg, T);
+          int32_t F0, F1;
+          share(T, F0, F1);
+          if (wdense) {
+            seg_walk(O.adj, se, sd, nseg, F0, F1,
+                     [&](int32_t, int32_t, int32_t w) { dense_add(table, w - lo_w, whalf); },
+                     [] { return false; });
+          } else {
+            int32_t fresh = 0;
+            seg_walk(O.adj, se, sd, nseg, F0, F1,
+                     [&](int32_t, int32_t, int32_t w) { fresh += block_hash_add(table, cap, w, &s_over); },
+                     [&] {
+                       const int32_t fw = wave_sum(fresh);
+                       fresh = 0;
+                       if (lane == 0 && fw && atomicAdd(&s_fill, fw) + fw > (int32_t)(cap / 8 * 5)) s_over = 1;
+                       return __builtin_amdgcn_readfirstlane(*(volatile int32_t*)&s_over) != 0;
+                     });
           }
-          // compact the middles with an end in this window into full groups of 64
-          if (!done) {
-            const int32_t j = g * 64 + lane;
-            const bool act = j < pre1 && nxt[j] < hi_w;
-            const uint64_t am = __ballot(act);
-            if (act) queue[qn + __popcll(am & __lanemask_lt())] = j;
-            qn += __popcll(am);
-            __builtin_amdgcn_wave_barrier();
+          __syncthreads();
+          if (!wdense && s_over) {
+            over = true;
+            break;
           }
-          while (qn >= 64 || (done && qn > 0)) {
-            const int32_t j = lane < qn ? queue[lane] : -1;
-            __builtin_amdgcn_wave_barrier();
-            if (qn > 64 && lane < qn - 64) queue[lane] = queue[64 + lane];
-            __builtin_amdgcn_wave_barrier();
-            qn = qn > 64 ? qn - 64 : 0;
-            int32_t cs = 0, ce = 0;
-            if (j >= 0) {
-              const int32_t k = base + j;
-              const int32_t e = S.rev[k];
-              cs = pos[j];  // O.adj[cs] = nxt[j] < hi_w
-              ce = hi_w >= range ? e : gallop_lower_bound(O.adj, cs + 1, e, hi_w);
-              if (advance_now) {
-                pos[j] = ce;
-                nxt[j] = ce < e ? O.adj[ce] : kNone;
-              } else {
-                cend[j] = ce;
-              }
-            }
-            if (wdense) {
-              wave_walk(O.adj, cs, ce - cs, L, [&](int, int32_t, int32_t w) { dense_add(table, w - lo_w, whalf); });
-            } else {
-              int32_t fresh = 0;
-              wave_walk(O.adj, cs, ce - cs, L,
-                        [&](int, int32_t, int32_t w) { fresh += block_hash_add(table, cap, w, &s_over); });
-              fresh = wave_sum(fresh);
-              if (lane == 0 && fresh && atomicAdd(&s_fill, fresh) + fresh > (int32_t)(cap / 8 * 5)) s_over = 1;
-            }
-          }
-          if (done) break;
-          if (!wdense && *(volatile int32_t*)&s_over) break;
         }
-        __syncthreads();
-        if (wdense || !s_over) break;
+        if (!over) break;
         // the window holds too many distinct ends for the table: halve it and
         // redo.  A start walked without cursors (one window over its whole
         // end range) switches to cursors first, so the smaller window applies.
@@ -550,68 +670,48 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         unsigned long long* acc_s = pick_ptr(p.acc, x);
         unsigned long long* acc_o = pick_ptr(p.acc, 1 - x);
         unsigned long long* vmid = pick_ptr(p.vout, 1 - x);
-        // walks the middles of one group (lane's middle jl, or -1) and advances their cursors
-        auto walk2 = [&](int32_t jl) {
-          int32_t cs = 0, ce = 0, v = 0, e = 0;
-          if (jl >= 0) {
-            const int32_t k = base + jl;
-            v = S.adj[k];
-            e = S.rev[k];
-            cs = cursors ? pos[jl] : O.off[v];
-            ce = (!cursors || hi_w >= range) ? e : cend[jl];
-          }
-          wave_walk(O.adj, cs, ce - cs, L, [&](int mid, int32_t slot, int32_t w) {
-            const int32_t c = wdense ? dense_get(table, w - lo_w, whalf) : hash_get(table, table + cap, cap - 1, w);
-            if (c > 1) {
-              const unsigned long long d = (unsigned long long)(c - 1);
-              if (mode == kEdge) atomicAdd(&acc_o[slot], d);
-              atomicAdd(&dsum[mid], d);
-            }
-          });
-          const unsigned long long d = dsum[lane];
-          if (jl >= 0) {
+        int32_t* se = segbuf;
+        int32_t* sd = segbuf + kSeg2 + 1;
+        int32_t* sj = sd + kSeg2;
+        unsigned long long* sdel = reinterpret_cast<unsigned long long*>(segbuf + 3 * kSeg2 + 2);
+        int32_t rj = 0;
+        while (rj < pre) {
+          int32_t nseg, T;
+          fill(pre, kSeg2, true, se, sd, sj, sdel, rj, nseg, T);
+          int32_t F0, F1;
+          share(T, F0, F1);
+          // a lane's segments only increase along its positions: sum its
+          // deltas per segment in a register and add them to LDS on a change
+          int32_t cur = -1;
+          unsigned long long run = 0;
+          seg_walk(O.adj, se, sd, nseg, F0, F1,
+                   [&](int32_t sg, int32_t slot, int32_t w) {
+                     const int32_t c = wdense ? dense_get(table, w - lo_w, whalf)
+                                              : hash_get(table, table + cap, cap - 1, w);
+                     if (c > 1) {
+                       const unsigned long long d = (unsigned long long)(c - 1);
+                       if (mode == kEdge) atomicAdd(&acc_o[slot], d);
+                       if (sg != cur) {
+                         if (run) atomicAdd(&sdel[cur], run);
+                         cur = sg;
+                         run = 0;
+                       }
+                       run += d;
+                     }
+                   },
+                   [] { return false; });
+          if (run) atomicAdd(&sdel[cur], run);
+          __syncthreads();
+          for (int32_t i = t; i < nseg; i += kHeavyNT) {
+            const unsigned long long d = sdel[i];
             if (d) {
-              if (mode == kEdge) atomicAdd(&acc_s[base + jl], d);
-              else atomicAdd(&vmid[O.id_of[v]], d);
-            }
-            if (cursors) {
-              pos[jl] = ce;
-              nxt[jl] = ce < e ? O.adj[ce] : kNone;
+              const int32_t k = base + sj[i];
+              if (mode == kEdge) atomicAdd(&acc_s[k], d);
+              else atomicAdd(&vmid[O.id_of[S.adj[k]]], d);
             }
           }
-          dsum[lane] = 0;
-          __builtin_amdgcn_wave_barrier();
-        };
-        if (t == 0) s_next = 0;
-        __syncthreads();
-        int32_t qn = 0;
-        for (;;) {
-          const int32_t g = next_group(&s_next);
-          const bool done = g * 64 >= pre;
-          if (!cursors) {
-            if (done) break;
-            walk2(g * 64 + lane < pre ? g * 64 + lane : -1);
-            continue;
-          }
-          if (!done) {
-            const int32_t j = g * 64 + lane;
-            const bool act = j < pre && nxt[j] < hi_w;
-            const uint64_t am = __ballot(act);
-            if (act) queue[qn + __popcll(am & __lanemask_lt())] = j;
-            qn += __popcll(am);
-            __builtin_amdgcn_wave_barrier();
-          }
-          while (qn >= 64 || (done && qn > 0)) {
-            const int32_t jl = lane < qn ? queue[lane] : -1;
-            __builtin_amdgcn_wave_barrier();
-            if (qn > 64 && lane < qn - 64) queue[lane] = queue[64 + lane];
-            __builtin_amdgcn_wave_barrier();
-            qn = qn > 64 ? qn - 64 : 0;
-            walk2(jl);
-          }
-          if (done) break;
+          __syncthreads();
         }
-        __syncthreads();
       } else if (cursors && !advance_now) {
         // hash window of a total count: advance the cursors now that the window is final
         for (int32_t j = t; j < pre1; j += kHeavyNT) {
@@ -676,8 +776,8 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       if (!wdense && cursors && !seeded) {
         // size the next hash window from this one's distinct ends (aim: a quarter of the table)
         const int64_t span = hi_w - lo_w;
-        const int64_t fill = s_fill;
-        int64_t next = fill > 0 ? span * (int64_t)(cap / 4) / fill : 2 * span;
+        const int64_t fill_n = s_fill;
+        int64_t next = fill_n > 0 ? span * (int64_t)(cap / 4) / fill_n : 2 * span;
         next = next < 64 ? 64 : next;
         width = (int32_t)(next > range ? range : next);
       }
@@ -786,6 +886,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   p.dense_ratio = g->tune.dense_min_ratio;
   p.window_mode = g->tune.window_mode;
   p.hash_window_wedges = g->tune.hash_window_wedges;
+  p.dense_min_wedges = g->tune.dense_min_wedges;
   if (gtotals) {
     p.total = nullptr;
     p.gtotal = reinterpret_cast<unsigned long long*>(gtotals);

@@ -119,6 +119,7 @@ struct Tuning {
   int32_t window_mode = 1;  // 1 auto, 2 dense only, 3 hash only
   int32_t hash_window_wedges = 4096;
   int32_t dense_block = 0;
+  int32_t dense_min_wedges = 8192;
 };
 
 // Dense block of top-priority vertices (int8 MFMA, see dense.hip).
