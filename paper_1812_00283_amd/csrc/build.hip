@@ -140,6 +140,39 @@ unsigned grid_1d(int64_t n) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
+// ---- window-boundary tables
+// Degrees do not decrease with rank, so the vertices of degree >= D are the
+// ranks from the first such one up.
+__global__ void first_rank_kernel(const int32_t* __restrict__ off, int32_t n, int32_t D, int32_t* __restrict__ out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (off[mid + 1] - off[mid] >= D) hi = mid; else lo = mid + 1;
+  }
+  *out = lo;
+}
+
+// Row of rank v (v >= first): entry w = first slot of N(v) with end rank
+// >= w << kWinShift (a binary search over the ascending list).
+__global__ void window_table_kernel(const int32_t* __restrict__ off, const int32_t* __restrict__ adj, int32_t n,
+                                    int32_t R, int64_t rows_max, const int32_t* __restrict__ first_p,
+                                    int32_t* __restrict__ tab) {
+  int32_t first = *first_p;
+  if ((int64_t)n - first > rows_max) first = (int32_t)(n - rows_max);
+  const int64_t total = ((int64_t)n - first) * R;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = first + (int32_t)(i / R);
+    const int32_t key = (int32_t)(i % R) << kWinShift;
+    int32_t a = off[v], b = off[v + 1];
+    while (a < b) {
+      const int32_t mid = (a + b) >> 1;
+      if (adj[mid] < key) a = mid + 1; else b = mid;
+    }
+    tab[i] = a;
+  }
+}
+
 }  // namespace
 
 void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
@@ -262,9 +295,32 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
       BFC_LAUNCH_CHECK();
     }
   }
+  // window-boundary tables of both middle layers (first row rank -> status[2 + o])
+  int64_t rows_max[2] = {0, 0};
+  for (int o = 0; o < 2; ++o) {
+    const int32_t no = n[o];
+    const int32_t R = (n[1 - o] >> kWinShift) + 2;
+    const int32_t D = 2 * R > kWinMinDegree ? 2 * R : kWinMinDegree;
+    rows_max[o] = m / D < no ? m / D : no;
+    g->wt_row[o] = R;
+    g->wt_first[o] = no;
+    if (rows_max[o] <= 0) continue;
+    g->wt[o].alloc(sizeof(int32_t) * (size_t)rows_max[o] * (size_t)R, s);
+    first_rank_kernel<<<1, 64, 0, s>>>(g->side[o].off.as<int32_t>(), no, D, status.as<int32_t>() + 2 + o);
+    BFC_LAUNCH_CHECK();
+    window_table_kernel<<<grid_1d(rows_max[o] * R), 256, 0, s>>>(
+        g->side[o].off.as<int32_t>(), g->side[o].adj.as<int32_t>(), no, R, rows_max[o],
+        status.as<int32_t>() + 2 + o, g->wt[o].as<int32_t>());
+    BFC_LAUNCH_CHECK();
+  }
   BFC_HIP(hipMemcpyAsync(st, status.p, sizeof(st), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
   if (st[1]) throw Error{BFC_ERR_DUPLICATE_EDGE, "the edge list repeats an (upper, lower) pair"};
+  for (int o = 0; o < 2; ++o) {
+    if (rows_max[o] <= 0) continue;
+    const int32_t lo = (int32_t)(n[o] - rows_max[o]);
+    g->wt_first[o] = st[2 + o] > lo ? st[2 + o] : lo;
+  }
 }
 
 // ---------------------------------------------------------------- schedule

@@ -61,6 +61,9 @@ struct CountParams {
   int32_t dtop[2];             // first rank of the dense block per layer (n_X when disabled)
   const int32_t* dC[2];        // MFMA products CU, CL (row-major)
   int32_t dld[2];              // their row strides
+  const int32_t* wt[2];        // window-boundary tables per middle layer (rows for ranks >= wt_first)
+  int32_t wt_first[2];
+  int32_t wt_row[2];
 };
 
 __device__ __forceinline__ int32_t graph_index(const CountParams& p, int x, int32_t r) {
@@ -107,6 +110,17 @@ __device__ __forceinline__ int32_t gallop_lower_bound(const int32_t* __restrict_
     if (a[mid] < key) l = mid + 1; else h = mid;
   }
   return l;
+}
+
+// First slot of a table middle's list (row `rowp` of the window-boundary
+// table) whose end rank is >= key: the table entry of key's 2^kWinShift
+// block, then a gallop inside that block when key is not a block start.
+__device__ __forceinline__ int32_t table_lb(const int32_t* __restrict__ oadj, const int32_t* __restrict__ rowp,
+                                            int32_t key) {
+  const int32_t w = key >> kWinShift;
+  const int32_t a = rowp[w];
+  if ((key & ((1 << kWinShift) - 1)) == 0) return a;
+  return gallop_lower_bound(oadj, a, rowp[w + 1], key);
 }
 
 // ------------------------------------------------------------ wavefront walk
@@ -414,6 +428,10 @@ __device__ __forceinline__ void seg_walk(const int32_t* __restrict__ oadj, const
 constexpr int kSeg1 = 2048;
 constexpr int kSeg2 = 1024;
 constexpr int kSegWords = 5124;  // max(2 * kSeg1 + 1, 3 * kSeg2 + 2 + 2 * kSeg2), rounded up
+// A dense window of a total count whose wedges fit one batch and number
+// fewer than this is finalized by walking its wedges again (each end's
+// counter read and cleared once) instead of scanning every counter.
+constexpr int32_t kRewalkMax = 8192;
 
 __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
   __shared__ __align__(16) int32_t table[kTableWords];
@@ -448,6 +466,11 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
     const int32_t pre = S.lo[r];
     const int64_t W = S.work[r];
     const int32_t range = r;
+    // middles of rank >= tfirst find their window slices in the table and
+    // keep no cursor
+    const int32_t* tab = x ? p.wt[0] : p.wt[1];
+    const int32_t tfirst = tab ? (x ? p.wt_first[0] : p.wt_first[1]) : 0x7FFFFFFF;
+    const int32_t trow = x ? p.wt_row[0] : p.wt_row[1];
     const bool dense = p.window_mode == 2 || (p.window_mode == 1 && (W > p.dense_min_wedges ||
                                                                      W * (int64_t)p.dense_ratio >= (int64_t)range));
     const bool half = pre < 65536;
@@ -480,16 +503,19 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       pre_out = a;
     }
     // one window over [0, range) needs no cursors; otherwise every middle
-    // keeps its next slot and next end id in scratch
-    bool cursors = !(sparse_end == range && width >= range);
-    if (cursors) {
+    // below tfirst keeps its next slot and next end id in scratch
+    auto init_cursors = [&] {
       for (int32_t j = t; j < pre; j += kHeavyNT) {
         const int32_t k = base + j;
-        const int32_t ps = O.off[S.adj[k]];
+        const int32_t v = S.adj[k];
+        if (v >= tfirst) continue;
+        const int32_t ps = O.off[v];
         pos[j] = ps;
         nxt[j] = ps < S.rev[k] ? O.adj[ps] : kNone;
       }
-    }
+    };
+    bool cursors = !(sparse_end == range && width >= range);
+    if (cursors) init_cursors();
     unsigned long long start_acc = 0;
     int32_t lo_w = 0;
     for (;;) {
@@ -525,23 +551,36 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         nseg = 0;
         T = 0;
         while (nseg < segcap && rj < npre) {
-          int32_t jv[2], csv[2], cev[2], ev[2];
+          int32_t jv[2], csv[2], cev[2], ev[2], vv[2];
           bool actv[2];
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const int32_t j = rj + 2 * t + h;
             jv[h] = j;
             actv[h] = false;
-            csv[h] = cev[h] = ev[h] = 0;
+            csv[h] = cev[h] = ev[h] = vv[h] = 0;
             if (j < npre) {
               const int32_t k = base + j;
               const int32_t e = S.rev[k];
+              const int32_t v = S.adj[k];
               ev[h] = e;
+              vv[h] = v;
               if (!cursors) {
-                const int32_t cs = O.off[S.adj[k]];
+                const int32_t cs = O.off[v];
                 csv[h] = cs;
                 cev[h] = e;
                 actv[h] = e > cs;
+              } else if (v >= tfirst) {
+                const int32_t* rowp = tab + (int64_t)(v - tfirst) * trow;
+                const int32_t cs = table_lb(O.adj, rowp, lo_w);
+                int32_t ce = e;
+                if (hi_w < range) {
+                  const int32_t c2 = table_lb(O.adj, rowp, hi_w);
+                  ce = c2 < e ? c2 : e;
+                }
+                csv[h] = cs;
+                cev[h] = ce;
+                actv[h] = ce > cs;
               } else if (nxt[j] < hi_w) {
                 const int32_t cs = pos[j];  // O.adj[cs] = nxt[j] < hi_w
                 actv[h] = true;
@@ -571,7 +610,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
                 sj[ps] = jv[h];
                 sdel[ps] = 0ull;
               }
-              if (cursors) {
+              if (cursors && vv[h] < tfirst) {
                 if (second || advance_now) {
                   pos[jv[h]] = cev[h];
                   nxt[jv[h]] = cev[h] < ev[h] ? O.adj[cev[h]] : kNone;
@@ -608,6 +647,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
 
       // ---- pass 1: count the wedges whose end lies in [lo_w, hi_w)
       int32_t halvings = 0;
+      int32_t batches = 0, last_n = 0, last_t = 0;
       for (;;) {
         if (t == 0) { s_fill = 0; s_over = 0; }
         __syncthreads();
@@ -615,9 +655,13 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         int32_t* sd = segbuf + kSeg1 + 1;
         int32_t rj = 0;
         bool over = false;
+        batches = 0;
         while (rj < pre1) {
           int32_t nseg, T;
           fill(pre1, kSeg1, false, se, sd, nullptr, nullptr, rj, nseg, T);
+          ++batches;
+          last_n = nseg;
+          last_t = T;
           int32_t F0, F1;
           share(T, F0, F1);
           if (wdense) {
@@ -647,12 +691,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         // end range) switches to cursors first, so the smaller window applies.
         for (int i = t; i < (int)(2 * cap); i += kHeavyNT) table[i] = 0;
         if (!cursors) {
-          for (int32_t j = t; j < pre; j += kHeavyNT) {
-            const int32_t k = base + j;
-            const int32_t ps = O.off[S.adj[k]];
-            pos[j] = ps;
-            nxt[j] = ps < S.rev[k] ? O.adj[ps] : kNone;
-          }
+          init_cursors();
           cursors = true;
         }
         __syncthreads();
@@ -715,7 +754,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       } else if (cursors && !advance_now) {
         // hash window of a total count: advance the cursors now that the window is final
         for (int32_t j = t; j < pre1; j += kHeavyNT) {
-          if (nxt[j] < hi_w) {
+          if (S.adj[base + j] < tfirst && nxt[j] < hi_w) {
             const int32_t ce = cend[j];
             pos[j] = ce;
             nxt[j] = ce < S.rev[base + j] ? O.adj[ce] : kNone;
@@ -724,7 +763,25 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       }
       // ---- finalize the window: C(count,2) per end, then clear the table
       unsigned long long* vs = pick_ptr(p.vout, x);
-      if (wdense) {
+      if (mode == kTotal && wdense && !seeded && batches == 1 && last_t < kRewalkMax) {
+        // the window's segment list is still in LDS: visit its wedges again
+        int32_t F0, F1;
+        share(last_t, F0, F1);
+        seg_walk(O.adj, segbuf, segbuf + kSeg1 + 1, last_n, F0, F1,
+                 [&](int32_t, int32_t, int32_t w) {
+                   const int32_t i = w - lo_w;
+                   int32_t c;
+                   if (whalf) {
+                     const uint32_t sh = (uint32_t)(i & 1) << 4;
+                     const uint32_t old = atomicAnd(reinterpret_cast<uint32_t*>(&table[i >> 1]), ~(0xFFFFu << sh));
+                     c = (int32_t)((old >> sh) & 0xFFFFu);
+                   } else {
+                     c = atomicExch(&table[i], 0);
+                   }
+                   if (c > 1) start_acc += choose2(c);
+                 },
+                 [] { return false; });
+      } else if (wdense) {
         const int32_t wn = hi_w - lo_w;
         const int32_t words = whalf ? (wn + 1) >> 1 : wn;
         const int32_t quads = (words + 3) >> 2;
@@ -887,6 +944,11 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   p.window_mode = g->tune.window_mode;
   p.hash_window_wedges = g->tune.hash_window_wedges;
   p.dense_min_wedges = g->tune.dense_min_wedges;
+  for (int o = 0; o < 2; ++o) {
+    p.wt[o] = g->wt[o].bytes ? g->wt[o].as<int32_t>() : nullptr;
+    p.wt_first[o] = g->wt_first[o];
+    p.wt_row[o] = g->wt_row[o];
+  }
   if (gtotals) {
     p.total = nullptr;
     p.gtotal = reinterpret_cast<unsigned long long*>(gtotals);

@@ -13,6 +13,10 @@
 namespace bfc {
 
 constexpr int kWave = 64;
+// Window-boundary tables: entries every 2^kWinShift end ranks, rows for the
+// middles of degree >= max(2 x row length, kWinMinDegree).
+constexpr int kWinShift = 15;
+constexpr int32_t kWinMinDegree = 64;
 
 // ------------------------------------------------------------ errors
 struct Error {
@@ -138,6 +142,13 @@ struct bfc_graph_s {
   int32_t n_upper = 0, n_lower = 0;
   bfc::Side side[2];      // 0 = upper layer, 1 = lower layer
   bfc::DevBuf eslot;      // int32 [m] slot of edge i in side[0].adj
+  // window-boundary tables, one per middle layer o: for the ranks
+  // v >= wt_first[o] (the vertices of degree >= wt_min_degree), row v holds
+  // wt_row[o] slots; entry w is the first slot of N(v) whose end rank is
+  // >= w * 2^15 (end ranks are ranks of the other layer)
+  bfc::DevBuf wt[2];
+  int32_t wt_first[2] = {0, 0};
+  int32_t wt_row[2] = {0, 0};
   // batches: graph index of every rank (per layer) and per-graph |W|
   int32_t n_graphs = 1;
   bfc::DevBuf gid[2];
