@@ -166,9 +166,12 @@ bfc_status bfc_destroy(bfc_graph g);
  *                      3 = always hash windows.
  *   dense_min_wedges   in automatic mode a start also uses dense windows when
  *                      it has more than this many wedges.  Default 8192.
- *   hash_window_wedges wedges aimed at per hash window of a large start (the
- *                      window is halved when its distinct ends overfill the
- *                      table).  Default 4096.
+ *   hash_window_wedges wedges aimed at per hash window (the window is halved
+ *                      when its distinct ends overfill the table).  In
+ *                      automatic mode a dense start's low end ranks, up to
+ *                      the longest multiple of the dense width expected to
+ *                      hold this many wedges, form one hash window.  Default
+ *                      8192.
  *   dense_block        vertices per layer in the top-priority block counted
  *                      with int8 MFMA (0 disables it; multiple of 64).
  */

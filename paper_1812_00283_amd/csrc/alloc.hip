@@ -1,0 +1,143 @@
+// Caching device allocator for the library's buffers.
+//
+// A build allocates and frees some eighty buffers and a count a few more;
+// through the stream-ordered pool each call costs tens to hundreds of
+// microseconds of host time, enough to leave the GPU idle between kernels.
+// Here a freed block goes to a per-device free list together with the stream
+// it was freed on and an event recorded there.  A later request of the same
+// size class takes it when it comes from that stream (stream order puts the
+// new work after the old) or once the event has completed; otherwise the
+// block stays cached and a new one is allocated.  Memory is returned to the
+// driver only when an allocation fails (blocks whose events have completed
+// are freed and the allocation is retried).
+#include "internal.hpp"
+
+#include <map>
+#include <unordered_map>
+
+namespace bfc {
+
+namespace {
+
+struct Block {
+  size_t size = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  bool pending = false;  // ev marks the end of the work queued before the free
+};
+
+std::mutex g_mu;
+std::unordered_map<void*, Block> g_live;
+std::multimap<std::pair<int, size_t>, std::pair<void*, Block>> g_free;  // (device, size) -> block
+
+// Rounds to 8 classes per power of two (at most 12.5% slack), 256 B minimum.
+size_t size_class(size_t n) {
+  if (n <= 256) return 256;
+  int lg = 63 - __builtin_clzll((unsigned long long)(n - 1));  // n - 1 < 2^(lg + 1)
+  const size_t step = lg >= 3 ? (size_t)1 << (lg - 2) : 1;
+  return (n + step - 1) / step * step;
+}
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+// Frees cached blocks of `device` whose work has completed (caller holds g_mu).
+void trim_locked(int device) {
+  for (auto it = g_free.begin(); it != g_free.end();) {
+    Block& b = it->second.second;
+    if (b.device == device && (!b.pending || hipEventQuery(b.ev) == hipSuccess)) {
+      if (b.ev) (void)hipEventDestroy(b.ev);
+      (void)hipFree(it->second.first);
+      it = g_free.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+}  // namespace
+
+void* cache_alloc(size_t bytes, hipStream_t s) {
+  if (capturing(s)) throw Error{BFC_ERR_INVALID_ARGUMENT, "device allocation while the stream is being captured"};
+  int device = 0;
+  BFC_HIP(hipGetDevice(&device));
+  const size_t size = size_class(bytes);
+  {
+    std::lock_guard<std::mutex> hold(g_mu);
+    auto range = g_free.equal_range({device, size});
+    for (auto it = range.first; it != range.second; ++it) {
+      Block& b = it->second.second;
+      if (b.pending && b.stream != s && hipEventQuery(b.ev) != hipSuccess) continue;
+      void* p = it->second.first;
+      Block nb = b;
+      nb.pending = false;
+      g_free.erase(it);
+      g_live[p] = nb;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, size);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> hold(g_mu);
+      trim_locked(device);
+    }
+    e = hipMalloc(&p, size);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{BFC_ERR_OUT_OF_MEMORY, std::string("device allocation failed: ") + hipGetErrorString(e)};
+    }
+  }
+  std::lock_guard<std::mutex> hold(g_mu);
+  Block b;
+  b.size = size;
+  b.device = device;
+  g_live[p] = b;
+  return p;
+}
+
+void cache_free(void* p, hipStream_t s) {
+  if (!p) return;
+  std::lock_guard<std::mutex> hold(g_mu);
+  auto it = g_live.find(p);
+  if (it == g_live.end()) return;
+  Block b = it->second;
+  g_live.erase(it);
+  // a block freed inside a stream capture is never reused: the captured work
+  // that uses it runs at replay time
+  if (capturing(s)) return;
+  b.stream = s;
+  b.pending = false;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur == b.device) {
+    if (!b.ev) (void)hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+    b.pending = b.ev && hipEventRecord(b.ev, s) == hipSuccess;
+  }
+  if (!b.pending) {
+    // no event on the block's device: wait for that device's work instead
+    (void)hipSetDevice(b.device);
+    (void)hipDeviceSynchronize();
+    (void)hipSetDevice(cur);
+  }
+  g_free.emplace(std::make_pair(b.device, b.size), std::make_pair(p, b));
+}
+
+void cache_free_idle(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> hold(g_mu);
+  auto it = g_live.find(p);
+  if (it == g_live.end()) return;
+  Block b = it->second;
+  g_live.erase(it);
+  b.stream = nullptr;
+  b.pending = false;
+  g_free.emplace(std::make_pair(b.device, b.size), std::make_pair(p, b));
+}
+
+}  // namespace bfc

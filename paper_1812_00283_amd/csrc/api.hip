@@ -48,22 +48,6 @@ struct DeviceScope {
 
 void zero_i64(int64_t* p, int64_t n, hipStream_t s) { zero_u64(p, n, s); }
 
-std::mutex g_pool_mu;
-bool g_pool_warm[64] = {};
-
-}  // namespace
-
-void keep_pool_warm(int device) {
-  std::lock_guard<std::mutex> hold(g_pool_mu);
-  if (device < 0 || device >= 64 || g_pool_warm[device]) return;
-  hipMemPool_t pool = nullptr;
-  BFC_HIP(hipDeviceGetDefaultMemPool(&pool, device));
-  uint64_t threshold = UINT64_MAX;
-  BFC_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold));
-  g_pool_warm[device] = true;
-}
-
-namespace {
 
 bfc_graph_s* checked(bfc_graph g) {
   if (!g) throw Error{BFC_ERR_INVALID_ARGUMENT, "null graph handle"};
@@ -148,12 +132,14 @@ bfc_status bfc_build(const int32_t* edges_dev, int64_t m, int32_t n_upper, int32
       g->m = m;
       g->n_upper = n_upper;
       g->n_lower = n_lower;
-      keep_pool_warm(g->device);
       build_graph(g, edges_dev, s);
       build_schedule(g, s);
       prepare_count(g, s);
       BFC_HIP(hipStreamSynchronize(s));
     } catch (...) {
+      // let queued build work finish before its buffers return to the cache
+      (void)hipStreamSynchronize(s);
+      (void)hipGetLastError();
       if (g->done) (void)hipEventDestroy(g->done);
       delete g;
       throw;
@@ -203,12 +189,14 @@ bfc_status bfc_build_batch(const int32_t* edges_dev, const int64_t* edge_offsets
     try {
       BFC_HIP(hipGetDevice(&g->device));
       BFC_HIP(hipEventCreateWithFlags(&g->done, hipEventDisableTiming));
-      keep_pool_warm(g->device);
       build_batch(g, edges_dev, edge_offsets_host, n_upper_host, n_lower_host, G, s);
       build_schedule(g, s);
       prepare_count(g, s);
       BFC_HIP(hipStreamSynchronize(s));
     } catch (...) {
+      // let queued build work finish before its buffers return to the cache
+      (void)hipStreamSynchronize(s);
+      (void)hipGetLastError();
       if (g->done) (void)hipEventDestroy(g->done);
       delete g;
       throw;

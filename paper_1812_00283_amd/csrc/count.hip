@@ -112,6 +112,23 @@ __device__ __forceinline__ int32_t gallop_lower_bound(const int32_t* __restrict_
   return l;
 }
 
+// First index in [lo, hi) with a[index] >= key when the answer is usually
+// within a few entries of lo: four independent loads, then a gallop.
+__device__ __forceinline__ int32_t near_lower_bound(const int32_t* __restrict__ a, int32_t lo, int32_t hi,
+                                                    int32_t key) {
+  const int32_t n = hi - lo;
+  if (n <= 0) return lo;
+  const int32_t a0 = a[lo];
+  const int32_t a1 = n > 1 ? a[lo + 1] : key;
+  const int32_t a2 = n > 2 ? a[lo + 2] : key;
+  const int32_t a3 = n > 3 ? a[lo + 3] : key;
+  if (a0 >= key) return lo;
+  if (a1 >= key) return lo + 1;
+  if (a2 >= key) return lo + 2;
+  if (a3 >= key) return lo + 3;
+  return gallop_lower_bound(a, lo + 4, hi, key);
+}
+
 // First slot of a table middle's list (row `rowp` of the window-boundary
 // table) whose end rank is >= key: the table entry of key's 2^kWinShift
 // block, then a gallop inside that block when key is not a block start.
@@ -474,24 +491,45 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
     const bool dense = p.window_mode == 2 || (p.window_mode == 1 && (W > p.dense_min_wedges ||
                                                                      W * (int64_t)p.dense_ratio >= (int64_t)range));
     const bool half = pre < 65536;
-    int32_t width;
-    uint32_t cap = kHashCap;
-    if (dense) {
-      width = half ? 2 * kTableWords : kTableWords;
-    } else if (W <= kHashSingleMax) {
-      width = range;
-      cap = 512;
-      while ((int64_t)cap < 2 * W) cap <<= 1;
-    } else {
-      const int64_t wd = (int64_t)range * p.hash_window_wedges / W;
-      width = (int32_t)(wd < 256 ? 256 : (wd > range ? range : wd));
-    }
     // Starts in the dense block: the last window covers the block's end ranks
     // [top, r); its counters start from the MFMA products and its first pass
     // walks only middles outside the other layer's block (a prefix).
     const int32_t top = x ? p.dtop[1] : p.dtop[0];
     const bool in_block = r > top;
     const int32_t sparse_end = in_block ? top : range;
+    // Windows: hash windows over [0, hash_end) (width hwidth, adapted as they
+    // go), then dense windows of `width` ranks up to sparse_end.
+    int32_t width = half ? 2 * kTableWords : kTableWords;
+    int32_t hwidth = 0, hash_end = 0;
+    uint32_t cap = kHashCap;
+    if (dense) {
+      if (p.window_mode == 1 && base > 0) {
+        // Sparse prefix of a dense start: the ends of its wedges are
+        // neighbours of its middles, which in a degree-driven graph fall on
+        // the start layer's vertices in proportion to their degree, so about
+        // W * off_X[x] / off_X[r] wedges end below rank x.  The prefix is the
+        // longest multiple of the dense width expected to hold at most
+        // hash_window_wedges of them (one 64-lane probe of off_X); a wrong
+        // guess costs time only (an overfull hash window is split).
+        const int32_t step0 = (sparse_end + 63) / 64;
+        const int32_t step = (step0 + 2 * kTableWords - 1) / (2 * kTableWords) * (2 * kTableWords);
+        const int64_t xl = (int64_t)(lane + 1) * step;
+        const bool ok = xl < sparse_end &&
+                        (double)W * (double)S.off[xl] <= (double)p.hash_window_wedges * (double)base;
+        hash_end = __popcll(__ballot(ok)) * step;
+        hwidth = hash_end;
+      }
+    } else {
+      hash_end = sparse_end;
+      if (W <= kHashSingleMax) {
+        hwidth = range;
+        cap = 512;
+        while ((int64_t)cap < 2 * W) cap <<= 1;
+      } else {
+        const int64_t wd = (int64_t)range * p.hash_window_wedges / W;
+        hwidth = (int32_t)(wd < 256 ? 256 : (wd > range ? range : wd));
+      }
+    }
     int32_t pre_out = pre;
     if (in_block) {
       const int32_t otop = x ? p.dtop[0] : p.dtop[1];
@@ -514,16 +552,18 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         nxt[j] = ps < S.rev[k] ? O.adj[ps] : kNone;
       }
     };
-    bool cursors = !(sparse_end == range && width >= range);
+    bool cursors = !(sparse_end == range && (hash_end >= range ? hwidth >= range : (hash_end == 0 && width >= range)));
     if (cursors) init_cursors();
     unsigned long long start_acc = 0;
     int32_t lo_w = 0;
     for (;;) {
       int32_t hi_w;
-      bool wdense = dense, whalf = half && dense;
+      bool wdense = lo_w >= hash_end;
+      bool whalf = half && wdense;
       const bool seeded = lo_w >= sparse_end;
       if (!seeded) {
-        hi_w = (int64_t)lo_w + width >= sparse_end ? sparse_end : lo_w + width;
+        if (wdense) hi_w = (int64_t)lo_w + width >= sparse_end ? sparse_end : lo_w + width;
+        else hi_w = (int64_t)lo_w + hwidth >= hash_end ? hash_end : lo_w + hwidth;
       } else if (in_block && lo_w < range) {
         hi_w = range;
         wdense = true;
@@ -563,6 +603,8 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
               const int32_t k = base + j;
               const int32_t e = S.rev[k];
               const int32_t v = S.adj[k];
+              const int32_t pj = cursors ? pos[j] : 0;  // cursor state (meaningful below tfirst)
+              const int32_t nj = cursors ? nxt[j] : kNone;
               ev[h] = e;
               vv[h] = v;
               if (!cursors) {
@@ -581,11 +623,11 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
                 csv[h] = cs;
                 cev[h] = ce;
                 actv[h] = ce > cs;
-              } else if (nxt[j] < hi_w) {
-                const int32_t cs = pos[j];  // O.adj[cs] = nxt[j] < hi_w
+              } else if (nj < hi_w) {
+                const int32_t cs = pj;  // O.adj[cs] = nj < hi_w
                 actv[h] = true;
                 csv[h] = cs;
-                cev[h] = hi_w >= range ? e : (second ? cend[j] : gallop_lower_bound(O.adj, cs + 1, e, hi_w));
+                cev[h] = hi_w >= range ? e : (second ? cend[j] : near_lower_bound(O.adj, cs + 1, e, hi_w));
               }
             }
           }
@@ -836,7 +878,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         const int64_t fill_n = s_fill;
         int64_t next = fill_n > 0 ? span * (int64_t)(cap / 4) / fill_n : 2 * span;
         next = next < 64 ? 64 : next;
-        width = (int32_t)(next > range ? range : next);
+        hwidth = (int32_t)(next > range ? range : next);
       }
       __syncthreads();
       lo_w = hi_w;

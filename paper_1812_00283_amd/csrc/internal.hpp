@@ -37,33 +37,39 @@ void set_error(bfc_status s, const std::string& what);
 #define BFC_LAUNCH_CHECK() BFC_HIP(hipGetLastError())
 
 // ------------------------------------------------------------ memory
-// A device buffer owned by a graph handle.  Allocated in stream order from
-// the device's default memory pool (kept warm, so rebuilding a graph does not
-// go back to the driver); freed when the handle is destroyed, after all work
-// that uses it has completed.
+// Caching device allocator (alloc.hip).  cache_alloc returns a block of at
+// least `bytes` on the current device, usable by work queued on `s` from now
+// on.  cache_free hands it back once the work queued on `s` so far no longer
+// needs it (the block is reused by `s` at once and by other streams after
+// that work completes); cache_free_idle when no queued work uses it.  None
+// may be called for a stream that is being captured.
+void* cache_alloc(size_t bytes, hipStream_t s);
+void cache_free(void* p, hipStream_t s);
+void cache_free_idle(void* p);
+
+// A device buffer owned by a graph handle.  Work on a handle is ordered
+// (each count call waits for the previous one), so a buffer replaced by a
+// call on stream s is freed in order on s; the handle's destructor runs
+// after all its work has completed.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  ~DevBuf() { release(); }
-  void alloc(size_t n, hipStream_t s) {
-    release();
-    if (n == 0) n = 256;
-    BFC_HIP(hipMallocAsync(&p, n, s));
-    bytes = n;
+  ~DevBuf() {
+    if (p) cache_free_idle(p);
   }
-  void release() {
-    if (p) (void)hipFreeAsync(p, nullptr);
+  void alloc(size_t n, hipStream_t s) {
+    if (p) cache_free(p, s);
     p = nullptr;
     bytes = 0;
+    if (n == 0) n = 256;
+    p = cache_alloc(n, s);
+    bytes = n;
   }
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
-
-// Keeps freed pool memory cached on the device (called once per device).
-void keep_pool_warm(int device);
 
 // A stream-ordered temporary: allocated and freed in order on one stream,
 // so it may go out of scope while kernels that use it are still queued.
@@ -79,11 +85,11 @@ struct TmpBuf {
     release();
     if (n == 0) n = 256;
     s = stream;
-    BFC_HIP(hipMallocAsync(&p, n, s));
+    p = cache_alloc(n, s);
     bytes = n;
   }
   void release() {
-    if (p) (void)hipFreeAsync(p, s);
+    if (p) cache_free(p, s);
     p = nullptr;
     bytes = 0;
   }
@@ -121,7 +127,7 @@ struct Tuning {
   int32_t light_max_wedges = 1024;
   int32_t dense_min_ratio = 4;
   int32_t window_mode = 1;  // 1 auto, 2 dense only, 3 hash only
-  int32_t hash_window_wedges = 4096;
+  int32_t hash_window_wedges = 8192;
   int32_t dense_block = 0;
   int32_t dense_min_wedges = 8192;
 };

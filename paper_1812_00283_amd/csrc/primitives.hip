@@ -88,13 +88,13 @@ void exclusive_scan_impl(const T* in, T* out, int64_t n, T* total, hipStream_t s
     return;
   }
   T* partials = nullptr;
-  BFC_HIP(hipMallocAsync((void**)&partials, sizeof(T) * (size_t)tiles, s));
+  partials = static_cast<T*>(cache_alloc(sizeof(T) * (size_t)tiles, s));
   scan_reduce_kernel<T><<<(unsigned)tiles, kScanNT, 0, s>>>(in, n, partials);
   BFC_LAUNCH_CHECK();
   exclusive_scan_impl<T>(partials, partials, tiles, nullptr, s);
   scan_tile_kernel<T><<<(unsigned)tiles, kScanNT, 0, s>>>(in, out, n, partials, total);
   BFC_LAUNCH_CHECK();
-  BFC_HIP(hipFreeAsync(partials, s));
+  cache_free(partials, s);
 }
 
 // ------------------------------------------------------------------ sort
@@ -205,7 +205,7 @@ void radix_sort_impl(K* keys, uint32_t* vals, K* ktmp, uint32_t* vtmp, int64_t n
   if (n <= 1 || bits <= 0) return;
   const int64_t tiles = (n + kSortTile - 1) / kSortTile;
   uint32_t* counts = nullptr;
-  BFC_HIP(hipMallocAsync((void**)&counts, sizeof(uint32_t) * 256 * (size_t)tiles, s));
+  counts = static_cast<uint32_t*>(cache_alloc(sizeof(uint32_t) * 256 * (size_t)tiles, s));
   K* ks = keys;
   K* kd = ktmp;
   uint32_t* vs = vals;
@@ -223,7 +223,7 @@ void radix_sort_impl(K* keys, uint32_t* vals, K* ktmp, uint32_t* vtmp, int64_t n
     BFC_HIP(hipMemcpyAsync(keys, ks, sizeof(K) * (size_t)n, hipMemcpyDeviceToDevice, s));
     BFC_HIP(hipMemcpyAsync(vals, vs, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
   }
-  BFC_HIP(hipFreeAsync(counts, s));
+  cache_free(counts, s);
 }
 
 }  // namespace

@@ -104,6 +104,10 @@ TUNINGS = {
     "mfma-block-1024": {"dense_block": 1024, "light_max_wedges": 64},
     "mfma-block-4096-hash": {"dense_block": 4096, "window_mode": 3, "hash_window_wedges": 512},
     "mfma-block-32768": {"dense_block": 32768},
+    # dense starts with a hash window over their low end ranks: a prefix
+    # sized for far too many wedges (split by halving), and small prefixes
+    "auto-prefix-overfull": {"light_max_wedges": 64, "hash_window_wedges": 1 << 30},
+    "auto-prefix-small": {"light_max_wedges": 64, "dense_min_wedges": 256, "hash_window_wedges": 2048},
 }
 
 
