@@ -26,33 +26,49 @@ namespace bfc {
 
 namespace {
 
-// Degree histogram.  Each workgroup adds into one of kDegCopies private
-// copies (by workgroup index), so the many increments of a hub vertex are
-// spread over several addresses; reduce_copies_kernel then sums the copies.
-constexpr int kDegCopies = 8;
+// Degree histogram.  Each workgroup first counts in a small LDS table of
+// hashed slots, each claimed by the first id that lands in it, so the many
+// increments of a hub vertex reach global memory about once per workgroup
+// (same-address global atomics serialise); an id whose slot another id holds
+// is counted in global memory directly.
+constexpr int kDegNT = 256;
+constexpr int kDegSlotBits = 11;
+constexpr int kDegSlots = 1 << kDegSlotBits;
 
-__global__ void degree_kernel(const int32_t* __restrict__ edges, int64_t m, int32_t nU, int32_t nL,
-                              int32_t* __restrict__ degU, int32_t* __restrict__ degL, int32_t* __restrict__ status) {
-  const int c = blockIdx.x % kDegCopies;
-  int32_t* du = degU + (int64_t)c * nU;
-  int32_t* dl = degL + (int64_t)c * nL;
+__device__ __forceinline__ void degree_add(int32_t* key, int32_t* cnt, int32_t* deg, int32_t v) {
+  const uint32_t h = ((uint32_t)v * 0x9E3779B1u) >> (32 - kDegSlotBits);
+  int32_t k = key[h];
+  if (k == -1) {
+    k = atomicCAS(&key[h], -1, v);
+    if (k == -1) k = v;
+  }
+  if (k == v) atomicAdd(&cnt[h], 1);
+  else atomicAdd(&deg[v], 1);
+}
+
+__global__ __launch_bounds__(kDegNT) void degree_kernel(const int32_t* __restrict__ edges, int64_t m, int32_t nU,
+                                                        int32_t nL, int32_t* __restrict__ degU,
+                                                        int32_t* __restrict__ degL, int32_t* __restrict__ status) {
+  __shared__ int32_t skey[2][kDegSlots];
+  __shared__ int32_t scnt[2][kDegSlots];
+  for (int i = threadIdx.x; i < kDegSlots; i += kDegNT) {
+    skey[0][i] = skey[1][i] = -1;
+    scnt[0][i] = scnt[1][i] = 0;
+  }
+  __syncthreads();
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
     const int2 e = reinterpret_cast<const int2*>(edges)[i];
     if (e.x < 0 || e.x >= nU || e.y < 0 || e.y >= nL) {
       atomicOr(&status[0], 1);
       continue;
     }
-    atomicAdd(&du[e.x], 1);
-    atomicAdd(&dl[e.y], 1);
+    degree_add(skey[0], scnt[0], degU, e.x);
+    degree_add(skey[1], scnt[1], degL, e.y);
   }
-}
-
-__global__ void reduce_copies_kernel(const int32_t* __restrict__ copies, int32_t n, int32_t* __restrict__ out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    int32_t s = 0;
-#pragma unroll
-    for (int c = 0; c < kDegCopies; ++c) s += copies[(int64_t)c * n + i];
-    out[i] = s;
+  __syncthreads();
+  for (int i = threadIdx.x; i < kDegSlots; i += kDegNT) {
+    if (scnt[0][i]) atomicAdd(&degU[skey[0][i]], scnt[0][i]);
+    if (scnt[1][i]) atomicAdd(&degL[skey[1][i]], scnt[1][i]);
   }
 }
 
@@ -87,19 +103,19 @@ __global__ void arc_unpack_kernel(const uint64_t* __restrict__ keys, const uint3
     const uint64_t key = keys[k];
     adj[k] = (int32_t)(key & mask);
     src[k] = (int32_t)(key >> bits_dst);
-    slot_of_edge[vals[k]] = (int32_t)k;
+    if (slot_of_edge) slot_of_edge[vals[k]] = (int32_t)k;
     if (k > 0 && keys[k - 1] == key) atomicOr(&status[1], 1);
   }
 }
 
-__global__ void link_kernel(int64_t m, const int32_t* __restrict__ slotU, const int32_t* __restrict__ slotL,
-                            int32_t* __restrict__ revU, int32_t* __restrict__ revL, int32_t* __restrict__ eslot) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t su = slotU[i];
-    const int32_t sl = slotL[i];
-    revU[su] = sl;
-    revL[sl] = su;
-    eslot[i] = su;
+// Reverse slots from side 1's sorted order: slot k of side 1 holds edge
+// perm1[k], whose side-0 slot is eslot[perm1[k]].
+__global__ void link_kernel(int64_t m, const uint32_t* __restrict__ perm1, const int32_t* __restrict__ eslot,
+                            int32_t* __restrict__ rev0, int32_t* __restrict__ rev1) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s0 = eslot[perm1[k]];
+    rev1[k] = s0;
+    rev0[s0] = (int32_t)k;
   }
 }
 
@@ -183,23 +199,16 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
   status.alloc(4 * sizeof(int32_t), s);
   BFC_HIP(hipMemsetAsync(status.p, 0, 4 * sizeof(int32_t), s));
   TmpBuf deg[2];
-  {
-    TmpBuf copies[2];
-    for (int x = 0; x < 2; ++x) {
-      deg[x].alloc(sizeof(int32_t) * (size_t)(n[x] + 1), s);
-      copies[x].alloc(sizeof(int32_t) * (size_t)kDegCopies * (size_t)n[x], s);
-      BFC_HIP(hipMemsetAsync(copies[x].p, 0, sizeof(int32_t) * (size_t)kDegCopies * (size_t)n[x], s));
-    }
-    if (m > 0) {
-      degree_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, n[0], n[1], copies[0].as<int32_t>(),
-                                                copies[1].as<int32_t>(), status.as<int32_t>());
-      BFC_LAUNCH_CHECK();
-    }
-    for (int x = 0; x < 2; ++x) {
-      if (n[x] == 0) continue;
-      reduce_copies_kernel<<<grid_1d(n[x]), 256, 0, s>>>(copies[x].as<int32_t>(), n[x], deg[x].as<int32_t>());
-      BFC_LAUNCH_CHECK();
-    }
+  for (int x = 0; x < 2; ++x) {
+    deg[x].alloc(sizeof(int32_t) * (size_t)(n[x] + 1), s);
+    BFC_HIP(hipMemsetAsync(deg[x].p, 0, sizeof(int32_t) * (size_t)(n[x] + 1), s));
+  }
+  if (m > 0) {
+    int64_t grid = (m + kDegNT - 1) / kDegNT;
+    if (grid > 2048) grid = 2048;
+    degree_kernel<<<(unsigned)grid, kDegNT, 0, s>>>(edges, m, n[0], n[1], deg[0].as<int32_t>(), deg[1].as<int32_t>(),
+                                                   status.as<int32_t>());
+    BFC_LAUNCH_CHECK();
   }
   int32_t st[4] = {0, 0, 0, 0};
   BFC_HIP(hipMemcpyAsync(st, status.p, sizeof(st), hipMemcpyDeviceToHost, s));
@@ -236,8 +245,11 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
     exclusive_scan_i32(deg_rank[x].as<int32_t>(), sd.off.as<int32_t>(), nx, sd.off.as<int32_t>() + nx, s);
   }
 
-  // ---- per-side CSR by sorting (rank, neighbour rank) keys
-  TmpBuf slot[2], src[2];
+  // ---- per-side CSR by sorting (rank, neighbour rank) keys; side 0's
+  // order gives eslot (edge -> side-0 slot), side 1's the reverse slots
+  TmpBuf src[2];
+  for (int x = 0; x < 2; ++x) g->side[x].rev.alloc(sizeof(int32_t) * (size_t)m, s);
+  g->eslot.alloc(sizeof(int32_t) * (size_t)m, s);
   const int bits[2] = {bits_for((uint64_t)(n[0] > 1 ? n[0] - 1 : 1)), bits_for((uint64_t)(n[1] > 1 ? n[1] - 1 : 1))};
   {
     TmpBuf keys, vals, ktmp, vtmp;
@@ -248,7 +260,6 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
     for (int x = 0; x < 2; ++x) {
       Side& sd = g->side[x];
       sd.adj.alloc(sizeof(int32_t) * (size_t)m, s);
-      slot[x].alloc(sizeof(int32_t) * (size_t)m, s);
       src[x].alloc(sizeof(int32_t) * (size_t)m, s);
       if (m == 0) continue;
       const int bd = bits[1 - x];
@@ -258,21 +269,18 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
       radix_sort_u64(keys.as<uint64_t>(), vals.as<uint32_t>(), ktmp.as<uint64_t>(), vtmp.as<uint32_t>(), m,
                      bits[0] + bits[1], s);
       arc_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(keys.as<uint64_t>(), vals.as<uint32_t>(), m, bd,
-                                                     sd.adj.as<int32_t>(), src[x].as<int32_t>(), slot[x].as<int32_t>(),
-                                                     status.as<int32_t>());
+                                                     sd.adj.as<int32_t>(), src[x].as<int32_t>(),
+                                                     x == 0 ? g->eslot.as<int32_t>() : nullptr, status.as<int32_t>());
       BFC_LAUNCH_CHECK();
+      if (x == 1) {
+        link_kernel<<<grid_1d(m), 256, 0, s>>>(m, vals.as<uint32_t>(), g->eslot.as<int32_t>(),
+                                                g->side[0].rev.as<int32_t>(), g->side[1].rev.as<int32_t>());
+        BFC_LAUNCH_CHECK();
+      }
     }
   }
 
-  // ---- reverse slots, then per start: lower-priority prefix length and wedges
-  for (int x = 0; x < 2; ++x) g->side[x].rev.alloc(sizeof(int32_t) * (size_t)m, s);
-  g->eslot.alloc(sizeof(int32_t) * (size_t)m, s);
-  if (m > 0) {
-    link_kernel<<<grid_1d(m), 256, 0, s>>>(m, slot[0].as<int32_t>(), slot[1].as<int32_t>(),
-                                            g->side[0].rev.as<int32_t>(), g->side[1].rev.as<int32_t>(),
-                                            g->eslot.as<int32_t>());
-    BFC_LAUNCH_CHECK();
-  }
+  // ---- per start: lower-priority prefix length and wedges
   for (int x = 0; x < 2; ++x) {
     Side& sd = g->side[x];
     sd.lo.alloc(sizeof(int32_t) * (size_t)sd.n, s);
@@ -331,7 +339,9 @@ namespace {
 // [3] heavy wedges, [4] light middles, [5] heavy middles, [6] max start wedges
 // Starts in the dense block (the top KU / KL ranks) always go to the
 // workgroup kernel, which seeds them with the block's MFMA products.
-__global__ void classify_kernel(const int64_t* __restrict__ work0, const int32_t* __restrict__ lo0, int32_t n0,
+constexpr int kClassifyNT = 256;
+
+__global__ __launch_bounds__(kClassifyNT) void classify_kernel(const int64_t* __restrict__ work0, const int32_t* __restrict__ lo0, int32_t n0,
                                 const int64_t* __restrict__ work1, const int32_t* __restrict__ lo1, int32_t n1,
                                 int64_t light_max, int32_t KU, int32_t KL, int32_t* __restrict__ is_light,
                                 int32_t* __restrict__ is_heavy, unsigned long long* __restrict__ sums) {
@@ -355,18 +365,14 @@ __global__ void classify_kernel(const int64_t* __restrict__ work0, const int32_t
     }
     max_w = (unsigned long long)w > max_w ? (unsigned long long)w : max_w;
   }
+  // workgroup totals, then one atomic per workgroup
+  __shared__ unsigned long long red[5][kClassifyNT / 64];
+  __shared__ unsigned long long rmax[2][kClassifyNT / 64];
   s_all = wave_sum(s_all);
   s_lw = wave_sum(s_lw);
   s_hw = wave_sum(s_hw);
   s_lm = wave_sum(s_lm);
   s_hm = wave_sum(s_hm);
-  if (__lane_id() == 0) {
-    if (s_all) atomicAdd(&sums[0], s_all);
-    if (s_lw) atomicAdd(&sums[2], s_lw);
-    if (s_hw) atomicAdd(&sums[3], s_hw);
-    if (s_lm) atomicAdd(&sums[4], s_lm);
-    if (s_hm) atomicAdd(&sums[5], s_hm);
-  }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     const int32_t op = __shfl_xor(max_pre, d, 64);
@@ -374,9 +380,29 @@ __global__ void classify_kernel(const int64_t* __restrict__ work0, const int32_t
     max_pre = op > max_pre ? op : max_pre;
     max_w = ow > max_w ? ow : max_w;
   }
+  const int wv = threadIdx.x >> 6;
   if (__lane_id() == 0) {
-    if (max_pre) atomicMax(&sums[1], (unsigned long long)max_pre);
-    if (max_w) atomicMax(&sums[6], max_w);
+    red[0][wv] = s_all;
+    red[1][wv] = s_lw;
+    red[2][wv] = s_hw;
+    red[3][wv] = s_lm;
+    red[4][wv] = s_hm;
+    rmax[0][wv] = (unsigned long long)max_pre;
+    rmax[1][wv] = max_w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t[5] = {0, 0, 0, 0, 0}, mp = 0, mw = 0;
+    for (int w = 0; w < kClassifyNT / 64; ++w) {
+      for (int q = 0; q < 5; ++q) t[q] += red[q][w];
+      mp = rmax[0][w] > mp ? rmax[0][w] : mp;
+      mw = rmax[1][w] > mw ? rmax[1][w] : mw;
+    }
+    const int slot[5] = {0, 2, 3, 4, 5};
+    for (int q = 0; q < 5; ++q)
+      if (t[q]) atomicAdd(&sums[slot[q]], t[q]);
+    if (mp) atomicMax(&sums[1], mp);
+    if (mw) atomicMax(&sums[6], mw);
   }
 }
 
@@ -416,7 +442,7 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   int32_t KL = K > 0 ? (K < n1 ? K : n1) : 0;
   if (KU == 0 || KL == 0) KU = KL = 0;
   if (n > 0) {
-    classify_kernel<<<grid_1d(n), 256, 0, s>>>(g->side[0].work.as<int64_t>(), g->side[0].lo.as<int32_t>(), n0,
+    classify_kernel<<<grid_1d(n) < 1024 ? grid_1d(n) : 1024, kClassifyNT, 0, s>>>(g->side[0].work.as<int64_t>(), g->side[0].lo.as<int32_t>(), n0,
                                                 g->side[1].work.as<int64_t>(), g->side[1].lo.as<int32_t>(), n1,
                                                 light_max, KU, KL, flags_l.as<int32_t>(), flags_h.as<int32_t>(),
                                                 sums.as<unsigned long long>());
