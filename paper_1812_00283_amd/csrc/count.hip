@@ -377,19 +377,33 @@ __device__ __forceinline__ int32_t dense_get(const int32_t* table, int32_t i, bo
 // the slot of flattened position f inside segment i is sd[i] + f.
 
 // Visits positions [F0, F1) of a segment list of n entries (n < 4096).
-// Lane l takes positions F0 + l, F0 + 64 + l, ...  Per step of 64 positions
-// the wavefront loads the next 64 segment starts; a start d positions into
-// the step marks lane d (ds_permute), and a lane's segment is the current
-// one plus the number of marks at or below it (ballot + popcount), so
-// locating segments costs O(1) per step however short they are.
-// fn(segment, slot, end) is called per wedge; stop() is polled (uniformly)
-// after every kSteps steps.
+// Lane l takes positions F0 + l, F0 + 64 + l, ...; an iteration covers
+// kSegSteps steps of 64 positions.  The wavefront loads the next 64 segment
+// starts; a start d positions into a step marks lane d (ds_permute), and a
+// lane's segment is the current one plus the starts at or below its
+// position (ballot + mbcnt).  When the 64 loaded starts reach past the
+// iteration (segments averaging 8 positions or more) every step is located
+// from them independently and without branches; otherwise the starts are
+// reloaded per step.  End ids of the next iteration are loaded before this
+// one's are used.  fn(segment, slot, end) is called per wedge; stop() is
+// polled (uniformly) once per iteration.
+constexpr int kSegSteps = 8;
+
+// end id at slot (a 32-bit byte offset from a wavefront-uniform base)
+__device__ __forceinline__ int32_t load_end(const int32_t* __restrict__ oadj, int32_t slot) {
+  return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(oadj) + ((uint32_t)slot << 2));
+}
+
+// number of set bits of m in lanes below this one, plus add
+__device__ __forceinline__ int32_t mbcnt(uint64_t m, int32_t add) {
+  return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)add));
+}
+
 template <typename Fn, typename Stop>
 __device__ __forceinline__ void seg_walk(const int32_t* __restrict__ oadj, const int32_t* se, const int32_t* sd,
                                          int32_t n, int32_t F0, int32_t F1, Fn&& fn, Stop&& stop) {
   if (F0 >= F1) return;
   const int lane = __lane_id();
-  const uint64_t le_mask = __lanemask_lt() | (1ull << lane);
   // segment holding F0: largest s with se[s] <= F0 (se[0] = 0), by two
   // rounds of a 64-way search over se[0..n]
   int32_t s0;
@@ -403,28 +417,59 @@ __device__ __forceinline__ void seg_walk(const int32_t* __restrict__ oadj, const
     s0 = lo + __popcll(__ballot(lane < stride && i < n1 && se[i] <= F0)) - 1;
   }
   int32_t sd0 = sd[s0];
-  for (int32_t f0 = F0; f0 < F1; f0 += 64 * kSteps) {
-    int32_t slot[kSteps], w[kSteps], sg[kSteps];
+  // Positions f0 + 64 q + lane (q < kSegSteps): slot, segment and end id
+  // (-1: position >= F1).  Returns true when every position is < F1.
+  auto gen = [&](int32_t f0, int32_t* slot, int32_t* sg, int32_t* w) -> bool {
+    const int32_t fend = f0 + 64 * kSegSteps;
+    int32_t idx = s0 + 1 + lane;
+    int32_t b = idx <= n ? se[idx] : 0x7FFFFFFF;
+    int32_t g = idx < n ? sd[idx] : 0;
+    const bool full = fend <= F1;
+    if (full && __shfl(b, 63, 64) >= fend) {
+      // every segment start below fend is among b (ascending over lanes):
+      // the steps are independent
+      const int32_t e0 = b - f0 - 1;  // start offset - 1 relative to step 0
+      const int32_t pos0 = f0 + lane;
 #pragma unroll
-    for (int q = 0; q < kSteps; ++q) {
+      for (int q = 0; q < kSegSteps; ++q) {
+        const int32_t e = e0 - 64 * q;
+        const bool mk = (uint32_t)e < 63u;  // start inside (f, f + 64)
+        const int32_t mark = __builtin_amdgcn_ds_permute(mk ? (e + 1) << 2 : 0, mk ? 1 : 0);
+        const int32_t cb = __popcll(__ballot(e < 0));  // starts at or before f
+        const int32_t c = mbcnt(__ballot(mark != 0), mark + cb);
+        const int32_t gc = __builtin_amdgcn_ds_bpermute((c << 2) - 4, g);
+        slot[q] = (c == 0 ? sd0 : gc) + pos0 + 64 * q;
+        sg[q] = s0 + c;
+        w[q] = load_end(oadj, slot[q]);
+      }
+      const int32_t cn = __popcll(__ballot(b <= fend));
+      if (cn > 0) {
+        sd0 = __builtin_amdgcn_readlane(g, cn - 1);
+        s0 += cn;
+      }
+      return true;
+    }
+#pragma unroll
+    for (int q = 0; q < kSegSteps; ++q) {
       const int32_t f = f0 + 64 * q;
       w[q] = -1;
       slot[q] = 0;
       sg[q] = 0;
       if (f < F1) {
         // invariant: se[s0] <= f < se[s0 + 1], so every loaded start is > f
-        const int32_t idx = s0 + 1 + lane;
-        const int32_t b = idx <= n ? se[idx] : 0x7FFFFFFF;
-        const int32_t g = idx < n ? sd[idx] : 0;
+        if (q > 0) {
+          idx = s0 + 1 + lane;
+          b = idx <= n ? se[idx] : 0x7FFFFFFF;
+          g = idx < n ? sd[idx] : 0;
+        }
         const int32_t d = b - f;
         const int32_t mark = __builtin_amdgcn_ds_permute(d < 64 ? 4 * d : 0, d < 64 ? 1 : 0);
-        const int32_t c = __popcll(__ballot(mark != 0) & le_mask);
-        const int32_t gc = __shfl(g, c > 0 ? c - 1 : 0, 64);
-        const int32_t base = c > 0 ? gc : sd0;
+        const int32_t c = mbcnt(__ballot(mark != 0), mark);
+        const int32_t gc = __builtin_amdgcn_ds_bpermute((c << 2) - 4, g);
         if (f + lane < F1) {
-          slot[q] = base + f + lane;
+          slot[q] = (c == 0 ? sd0 : gc) + f + lane;
           sg[q] = s0 + c;
-          w[q] = oadj[slot[q]];
+          w[q] = load_end(oadj, slot[q]);
         }
         const int32_t cn = __popcll(__ballot(d <= 64));
         if (cn > 0) {
@@ -433,10 +478,31 @@ __device__ __forceinline__ void seg_walk(const int32_t* __restrict__ oadj, const
         }
       }
     }
+    return full;
+  };
+  int32_t slot_a[kSegSteps], sg_a[kSegSteps], w_a[kSegSteps];
+  bool full_a = gen(F0, slot_a, sg_a, w_a);
+  for (int32_t f0 = F0; f0 < F1; f0 += 64 * kSegSteps) {
+    int32_t slot_b[kSegSteps], sg_b[kSegSteps], w_b[kSegSteps];
+    const bool more = f0 + 64 * kSegSteps < F1;
+    bool full_b = false;
+    if (more) full_b = gen(f0 + 64 * kSegSteps, slot_b, sg_b, w_b);
+    if (full_a) {
 #pragma unroll
-    for (int q = 0; q < kSteps; ++q)
-      if (w[q] >= 0) fn(sg[q], slot[q], w[q]);
-    if (stop()) break;
+      for (int q = 0; q < kSegSteps; ++q) fn(sg_a[q], slot_a[q], w_a[q]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < kSegSteps; ++q)
+        if (w_a[q] >= 0) fn(sg_a[q], slot_a[q], w_a[q]);
+    }
+    if (!more || stop()) break;
+    full_a = full_b;
+#pragma unroll
+    for (int q = 0; q < kSegSteps; ++q) {
+      slot_a[q] = slot_b[q];
+      sg_a[q] = sg_b[q];
+      w_a[q] = w_b[q];
+    }
   }
 }
 
@@ -450,6 +516,8 @@ constexpr int kSegWords = 5124;  // max(2 * kSeg1 + 1, 3 * kSeg2 + 2 + 2 * kSeg2
 // counter read and cleared once) instead of scanning every counter.
 constexpr int32_t kRewalkMax = 8192;
 
+// One instantiation per count mode: the total count carries no second pass.
+template <int kMode>
 __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
   __shared__ __align__(16) int32_t table[kTableWords];
   __shared__ __align__(16) int32_t segbuf[kSegWords];
@@ -459,7 +527,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
   const int t = threadIdx.x;
   const int lane = __lane_id();
   const int wv = t >> 6;
-  const int mode = p.mode;
+  constexpr int mode = kMode;
   // per-middle cursor state of multi-window starts: next slot, end id at
   // that slot (kNone when exhausted), and the window's end slot
   int32_t* pos = p.cursor + (int64_t)blockIdx.x * 3 * p.cursor_stride;
@@ -706,9 +774,15 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
           last_t = T;
           int32_t F0, F1;
           share(T, F0, F1);
-          if (wdense) {
+          if (wdense && whalf) {
+            // lo_w is even: counter pair (w >> 1) - (lo_w >> 1), half (w & 1)
+            uint32_t* tw = reinterpret_cast<uint32_t*>(table) - (lo_w >> 1);
             seg_walk(O.adj, se, sd, nseg, F0, F1,
-                     [&](int32_t, int32_t, int32_t w) { dense_add(table, w - lo_w, whalf); },
+                     [&](int32_t, int32_t, int32_t w) { atomicAdd(&tw[w >> 1], (uint32_t)(w & 1) * 65535u + 1u); },
+                     [] { return false; });
+          } else if (wdense) {
+            int32_t* tw = table - lo_w;
+            seg_walk(O.adj, se, sd, nseg, F0, F1, [&](int32_t, int32_t, int32_t w) { atomicAdd(&tw[w], 1); },
                      [] { return false; });
           } else {
             int32_t fresh = 0;
@@ -1038,7 +1112,9 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   if (sc.n_heavy > 0) {
     p.list = g->sched.heavy.as<int32_t>();
     p.n_list = sc.n_heavy;
-    heavy_kernel<<<(unsigned)heavy_grid, kHeavyNT, 0, s>>>(p);
+    if (mode == kTotal) heavy_kernel<kTotal><<<(unsigned)heavy_grid, kHeavyNT, 0, s>>>(p);
+    else if (mode == kVertex) heavy_kernel<kVertex><<<(unsigned)heavy_grid, kHeavyNT, 0, s>>>(p);
+    else heavy_kernel<kEdge><<<(unsigned)heavy_grid, kHeavyNT, 0, s>>>(p);
     BFC_LAUNCH_CHECK();
   }
   if (g->timing) BFC_HIP(hipEventRecord(tc.ev[3], s));
