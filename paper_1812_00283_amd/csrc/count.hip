@@ -112,6 +112,8 @@ __device__ __forceinline__ int32_t gallop_lower_bound(const int32_t* __restrict_
   return l;
 }
 
+constexpr int32_t kNoEnd = 0x7FFFFFFF;  // "no further end" (no rank reaches it)
+
 // First index in [lo, hi) with a[index] >= key when the answer is usually
 // within a few entries of lo: four independent loads, then a gallop.
 __device__ __forceinline__ int32_t near_lower_bound(const int32_t* __restrict__ a, int32_t lo, int32_t hi,
@@ -127,6 +129,25 @@ __device__ __forceinline__ int32_t near_lower_bound(const int32_t* __restrict__ 
   if (a2 >= key) return lo + 2;
   if (a3 >= key) return lo + 3;
   return gallop_lower_bound(a, lo + 4, hi, key);
+}
+
+// near_lower_bound that also returns a[index] (kNoEnd when index == hi).
+__device__ __forceinline__ int32_t near_lower_bound_v(const int32_t* __restrict__ a, int32_t lo, int32_t hi,
+                                                      int32_t key, int32_t& val) {
+  const int32_t n = hi - lo;
+  val = kNoEnd;
+  if (n <= 0) return lo;
+  const int32_t a0 = a[lo];
+  const int32_t a1 = n > 1 ? a[lo + 1] : kNoEnd;
+  const int32_t a2 = n > 2 ? a[lo + 2] : kNoEnd;
+  const int32_t a3 = n > 3 ? a[lo + 3] : kNoEnd;
+  if (a0 >= key) { val = a0; return lo; }
+  if (a1 >= key) { val = a1; return lo + 1; }
+  if (a2 >= key) { val = a2; return lo + 2; }
+  if (a3 >= key) { val = a3; return lo + 3; }
+  const int32_t i = gallop_lower_bound(a, lo + 4, hi, key);
+  if (i < hi) val = a[i];
+  return i;
 }
 
 // First slot of a table middle's list (row `rowp` of the window-boundary
@@ -621,7 +642,33 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       }
     };
     bool cursors = !(sparse_end == range && (hash_end >= range ? hwidth >= range : (hash_end == 0 && width >= range)));
-    if (cursors) init_cursors();
+    // Resident mode: a multi-window start with at most 2 * kHeavyNT middles
+    // keeps middle 2t + h's slice state in thread t's registers: the end of
+    // its list below r (re), the start of its current slice (rcs), and raux
+    // = the middle's table row offset (>= 0) or -1 - (end id at rcs).  A
+    // window's slice ends (rce, and rnv = end id there) are computed from
+    // these, and committed once the window is final.
+    const bool resident = cursors && pre <= 2 * kHeavyNT;
+    int32_t re[2], rcs[2], raux[2], rce[2], rnv[2];
+    if (resident) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int32_t j = 2 * t + h;
+        re[h] = rcs[h] = rce[h] = 0;
+        raux[h] = rnv[h] = -1 - kNoEnd;
+        if (j < pre) {
+          const int32_t k = base + j;
+          const int32_t v = S.adj[k];
+          const int32_t e = S.rev[k];
+          const int32_t cs = O.off[v];
+          re[h] = e;
+          rcs[h] = rce[h] = cs;
+          raux[h] = v >= tfirst ? (v - tfirst) * trow : -1 - (cs < e ? O.adj[cs] : kNoEnd);
+        }
+      }
+    } else if (cursors) {
+      init_cursors();
+    }
     unsigned long long start_acc = 0;
     int32_t lo_w = 0;
     for (;;) {
@@ -755,6 +802,100 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         F1 = (int32_t)((int64_t)T * (wv + 1) / kHeavyWaves);
       };
 
+      // Resident mode: slice ends of window [lo_w, hi_w) for the thread's middles.
+      auto res_slices = [&] {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int32_t e = re[h], cs = rcs[h];
+          int32_t ce = cs, nv = -1 - raux[h];
+          if (cs < e) {
+            if (raux[h] >= 0) {
+              if (hi_w >= range) {
+                ce = e;
+              } else {
+                const int32_t c2 = table_lb(O.adj, tab + raux[h], hi_w);
+                ce = c2 < e ? c2 : e;
+              }
+            } else if (nv < hi_w) {
+              if (hi_w >= range) {
+                ce = e;
+                nv = kNoEnd;
+              } else {
+                ce = near_lower_bound_v(O.adj, cs + 1, e, hi_w, nv);
+              }
+            }
+          }
+          rce[h] = ce;
+          rnv[h] = nv;
+        }
+      };
+      // Resident mode: writes the non-empty slices of middles j < lim whose
+      // rank among them (in middle order) lies in [b0, b0 + segcap) to the
+      // segment list; returns the segment count, their total length and the
+      // number of non-empty slices among j < lim.
+      auto res_emit = [&](int32_t lim, int32_t b0, int32_t segcap, bool second, int32_t* se, int32_t* sd,
+                          int32_t* sj, unsigned long long* sdel, int32_t& nseg, int32_t& T, int32_t& nact) {
+        bool actv[2];
+        int32_t len[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          actv[h] = 2 * t + h < lim && rce[h] > rcs[h];
+          len[h] = actv[h] ? rce[h] - rcs[h] : 0;
+        }
+        const unsigned long long packed =
+            ((unsigned long long)((int)actv[0] + (int)actv[1]) << 32) | (uint32_t)(len[0] + len[1]);
+        unsigned long long tot;
+        const unsigned long long ex = block_exclusive_scan<unsigned long long, kHeavyNT>(packed, s_red64, &tot);
+        nact = (int32_t)(tot >> 32);
+        int32_t ia = (int32_t)(ex >> 32);
+        int32_t lex = (int32_t)(uint32_t)ex;
+        if (b0 > 0) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            if (actv[h] && ia == b0) s_cut_lex = lex;
+            if (actv[h]) { ++ia; lex += len[h]; }
+          }
+          __syncthreads();
+          ia = (int32_t)(ex >> 32);
+          lex = (int32_t)(uint32_t)ex;
+        }
+        const int32_t lex0 = b0 > 0 ? s_cut_lex : 0;
+        const int32_t hi_idx = nact < b0 + segcap ? nact : b0 + segcap;
+        nseg = hi_idx - b0;
+        T = (hi_idx == nact ? (int32_t)(uint32_t)tot : 0) - lex0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (!actv[h]) continue;
+          if (ia >= b0 && ia < b0 + segcap) {
+            const int32_t ps = ia - b0;
+            se[ps] = lex - lex0;
+            sd[ps] = rcs[h] - (lex - lex0);
+            if (second) {
+              sj[ps] = 2 * t + h;
+              sdel[ps] = 0ull;
+            }
+          } else if (ia == b0 + segcap) {
+            s_cut_j = lex;  // total length of the batch's slices + lex0
+          }
+          ++ia;
+          lex += len[h];
+        }
+        if (hi_idx < nact) {
+          __syncthreads();
+          T = s_cut_j - lex0;
+        }
+        if (t == 0) se[nseg] = T;
+        __syncthreads();
+      };
+      // Resident mode: the window is final; its slice ends become the next starts.
+      auto res_commit = [&] {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (raux[h] < 0) raux[h] = -1 - rnv[h];
+          rcs[h] = rce[h];
+        }
+      };
+
       // ---- pass 1: count the wedges whose end lies in [lo_w, hi_w)
       int32_t halvings = 0;
       int32_t batches = 0, last_n = 0, last_t = 0;
@@ -766,9 +907,16 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         int32_t rj = 0;
         bool over = false;
         batches = 0;
+        if (resident) res_slices();
         while (rj < pre1) {
           int32_t nseg, T;
-          fill(pre1, kSeg1, false, se, sd, nullptr, nullptr, rj, nseg, T);
+          if (resident) {
+            int32_t nact;
+            res_emit(pre1, 0, kSeg1, false, se, sd, nullptr, nullptr, nseg, T, nact);
+            rj = pre1;  // one batch holds every slice (pre <= kSeg1)
+          } else {
+            fill(pre1, kSeg1, false, se, sd, nullptr, nullptr, rj, nseg, T);
+          }
           ++batches;
           last_n = nseg;
           last_t = T;
@@ -829,10 +977,17 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         int32_t* sd = segbuf + kSeg2 + 1;
         int32_t* sj = sd + kSeg2;
         unsigned long long* sdel = reinterpret_cast<unsigned long long*>(segbuf + 3 * kSeg2 + 2);
-        int32_t rj = 0;
+        int32_t rj = 0, b0 = 0;
         while (rj < pre) {
           int32_t nseg, T;
-          fill(pre, kSeg2, true, se, sd, sj, sdel, rj, nseg, T);
+          if (resident) {
+            int32_t nact;
+            res_emit(pre, b0, kSeg2, true, se, sd, sj, sdel, nseg, T, nact);
+            b0 += kSeg2;
+            if (b0 >= nact) rj = pre;
+          } else {
+            fill(pre, kSeg2, true, se, sd, sj, sdel, rj, nseg, T);
+          }
           int32_t F0, F1;
           share(T, F0, F1);
           // a lane's segments only increase along its positions: sum its
@@ -867,7 +1022,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
           }
           __syncthreads();
         }
-      } else if (cursors && !advance_now) {
+      } else if (cursors && !advance_now && !resident) {
         // hash window of a total count: advance the cursors now that the window is final
         for (int32_t j = t; j < pre1; j += kHeavyNT) {
           if (S.adj[base + j] < tfirst && nxt[j] < hi_w) {
@@ -877,6 +1032,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
           }
         }
       }
+      if (resident) res_commit();
       // ---- finalize the window: C(count,2) per end, then clear the table
       unsigned long long* vs = pick_ptr(p.vout, x);
       if (mode == kTotal && wdense && !seeded && batches == 1 && last_t < kRewalkMax) {
