@@ -72,6 +72,92 @@ __global__ __launch_bounds__(kDegNT) void degree_kernel(const int32_t* __restric
   }
 }
 
+// Degrees by partition (no global atomics per endpoint): ids are grouped
+// into buckets of 2^kBucketShift consecutive ids -- bucket totals per tile,
+// a scatter of each id into its bucket's region (order inside a bucket is
+// irrelevant), then one workgroup per bucket counts its ids in LDS.  Both
+// layers at once; used while each layer has at most kMaxBuckets buckets.
+constexpr int kPartNT = 512;
+constexpr int64_t kPartTile = 16384;  // edges per workgroup
+constexpr int kBucketShift = 13;
+constexpr int kBucketIds = 1 << kBucketShift;
+constexpr int kMaxBuckets = 4096;
+
+__global__ __launch_bounds__(kPartNT) void part_count_kernel(const int32_t* __restrict__ edges, int64_t m,
+                                                             int32_t nU, int32_t nL, int32_t BU, int32_t BL,
+                                                             uint32_t* __restrict__ cnt,
+                                                             int32_t* __restrict__ status) {
+  __shared__ uint32_t h[2 * kMaxBuckets];
+  const int nb = BU + BL;
+  for (int i = threadIdx.x; i < nb; i += kPartNT) h[i] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * kPartTile;
+  const int64_t e1 = e0 + kPartTile < m ? e0 + kPartTile : m;
+  for (int64_t i = e0 + threadIdx.x; i < e1; i += kPartNT) {
+    const int2 e = reinterpret_cast<const int2*>(edges)[i];
+    if (e.x < 0 || e.x >= nU || e.y < 0 || e.y >= nL) {
+      atomicOr(&status[0], 1);
+      continue;
+    }
+    atomicAdd(&h[e.x >> kBucketShift], 1u);
+    atomicAdd(&h[BU + (e.y >> kBucketShift)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += kPartNT)
+    if (h[i]) atomicAdd(&cnt[i], h[i]);
+}
+
+__global__ __launch_bounds__(kPartNT) void part_scatter_kernel(const int32_t* __restrict__ edges, int64_t m,
+                                                               int32_t nU, int32_t nL, int32_t BU, int32_t BL,
+                                                               const uint32_t* __restrict__ off,
+                                                               uint32_t* __restrict__ fill,
+                                                               int32_t* __restrict__ part) {
+  __shared__ uint32_t h[2 * kMaxBuckets];
+  __shared__ uint32_t base[2 * kMaxBuckets];
+  const int nb = BU + BL;
+  for (int i = threadIdx.x; i < nb; i += kPartNT) h[i] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * kPartTile;
+  const int64_t e1 = e0 + kPartTile < m ? e0 + kPartTile : m;
+  for (int64_t i = e0 + threadIdx.x; i < e1; i += kPartNT) {
+    const int2 e = reinterpret_cast<const int2*>(edges)[i];
+    if (e.x < 0 || e.x >= nU || e.y < 0 || e.y >= nL) continue;
+    atomicAdd(&h[e.x >> kBucketShift], 1u);
+    atomicAdd(&h[BU + (e.y >> kBucketShift)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += kPartNT) {
+    base[i] = h[i] ? off[i] + atomicAdd(&fill[i], h[i]) : 0u;
+    h[i] = 0;
+  }
+  __syncthreads();
+  for (int64_t i = e0 + threadIdx.x; i < e1; i += kPartNT) {
+    const int2 e = reinterpret_cast<const int2*>(edges)[i];
+    if (e.x < 0 || e.x >= nU || e.y < 0 || e.y >= nL) continue;
+    const int bu = e.x >> kBucketShift, bl = BU + (e.y >> kBucketShift);
+    part[base[bu] + atomicAdd(&h[bu], 1u)] = e.x;
+    part[base[bl] + atomicAdd(&h[bl], 1u)] = e.y;
+  }
+}
+
+__global__ __launch_bounds__(kPartNT) void part_degree_kernel(const int32_t* __restrict__ part,
+                                                              const uint32_t* __restrict__ off, int32_t BU,
+                                                              int32_t nU, int32_t nL, int32_t* __restrict__ degU,
+                                                              int32_t* __restrict__ degL) {
+  __shared__ uint32_t h[kBucketIds];
+  const int b = blockIdx.x;
+  const bool lower = b >= BU;
+  const int32_t id0 = (lower ? b - BU : b) << kBucketShift;
+  const int32_t n = lower ? nL : nU;
+  const int32_t w = n - id0 < kBucketIds ? n - id0 : kBucketIds;
+  for (int i = threadIdx.x; i < w; i += kPartNT) h[i] = 0;
+  __syncthreads();
+  for (uint32_t i = off[b] + threadIdx.x; i < off[b + 1]; i += kPartNT) atomicAdd(&h[part[i] - id0], 1u);
+  __syncthreads();
+  int32_t* deg = lower ? degL : degU;
+  for (int i = threadIdx.x; i < w; i += kPartNT) deg[id0 + i] = (int32_t)h[i];
+}
+
 __global__ void iota_kernel(uint32_t* __restrict__ a, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = (uint32_t)i;
@@ -203,7 +289,29 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
     deg[x].alloc(sizeof(int32_t) * (size_t)(n[x] + 1), s);
     BFC_HIP(hipMemsetAsync(deg[x].p, 0, sizeof(int32_t) * (size_t)(n[x] + 1), s));
   }
-  if (m > 0) {
+  const int32_t BU = (n[0] + kBucketIds - 1) >> kBucketShift, BL = (n[1] + kBucketIds - 1) >> kBucketShift;
+  if (m > 0 && BU <= kMaxBuckets && BL <= kMaxBuckets) {
+    const int nb = BU + BL;
+    TmpBuf cnt, fill, part;
+    cnt.alloc(sizeof(uint32_t) * (size_t)(nb + 1), s);
+    fill.alloc(sizeof(uint32_t) * (size_t)nb, s);
+    part.alloc(sizeof(int32_t) * 2 * (size_t)m, s);
+    BFC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * (size_t)(nb + 1), s));
+    BFC_HIP(hipMemsetAsync(fill.p, 0, sizeof(uint32_t) * (size_t)nb, s));
+    const unsigned tiles = (unsigned)((m + kPartTile - 1) / kPartTile);
+    part_count_kernel<<<tiles, kPartNT, 0, s>>>(edges, m, n[0], n[1], BU, BL, cnt.as<uint32_t>(),
+                                                status.as<int32_t>());
+    BFC_LAUNCH_CHECK();
+    exclusive_scan_u32(cnt.as<uint32_t>(), cnt.as<uint32_t>(), nb + 1, s);
+    part_scatter_kernel<<<tiles, kPartNT, 0, s>>>(edges, m, n[0], n[1], BU, BL, cnt.as<uint32_t>(),
+                                                  fill.as<uint32_t>(), part.as<int32_t>());
+    BFC_LAUNCH_CHECK();
+    if (nb > 0) {
+      part_degree_kernel<<<(unsigned)nb, kPartNT, 0, s>>>(part.as<int32_t>(), cnt.as<uint32_t>(), BU, n[0], n[1],
+                                                          deg[0].as<int32_t>(), deg[1].as<int32_t>());
+      BFC_LAUNCH_CHECK();
+    }
+  } else if (m > 0) {
     int64_t grid = (m + kDegNT - 1) / kDegNT;
     if (grid > 2048) grid = 2048;
     degree_kernel<<<(unsigned)grid, kDegNT, 0, s>>>(edges, m, n[0], n[1], deg[0].as<int32_t>(), deg[1].as<int32_t>(),
