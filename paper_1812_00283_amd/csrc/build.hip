@@ -374,14 +374,16 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
       arc_keys_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, x, rank_of[x].as<int32_t>(), rank_of[1 - x].as<int32_t>(),
                                                    bd, keys.as<uint64_t>(), vals.as<uint32_t>());
       BFC_LAUNCH_CHECK();
-      radix_sort_u64(keys.as<uint64_t>(), vals.as<uint32_t>(), ktmp.as<uint64_t>(), vtmp.as<uint32_t>(), m,
-                     bits[0] + bits[1], s);
-      arc_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(keys.as<uint64_t>(), vals.as<uint32_t>(), m, bd,
+      const bool in_tmp = radix_sort_u64_any(keys.as<uint64_t>(), vals.as<uint32_t>(), ktmp.as<uint64_t>(),
+                                             vtmp.as<uint32_t>(), m, bits[0] + bits[1], s);
+      const uint64_t* sk = in_tmp ? ktmp.as<uint64_t>() : keys.as<uint64_t>();
+      const uint32_t* sv = in_tmp ? vtmp.as<uint32_t>() : vals.as<uint32_t>();
+      arc_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(sk, sv, m, bd,
                                                      sd.adj.as<int32_t>(), src[x].as<int32_t>(),
                                                      x == 0 ? g->eslot.as<int32_t>() : nullptr, status.as<int32_t>());
       BFC_LAUNCH_CHECK();
       if (x == 1) {
-        link_kernel<<<grid_1d(m), 256, 0, s>>>(m, vals.as<uint32_t>(), g->eslot.as<int32_t>(),
+        link_kernel<<<grid_1d(m), 256, 0, s>>>(m, sv, g->eslot.as<int32_t>(),
                                                 g->side[0].rev.as<int32_t>(), g->side[1].rev.as<int32_t>());
         BFC_LAUNCH_CHECK();
       }

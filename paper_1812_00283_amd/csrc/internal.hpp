@@ -198,6 +198,10 @@ void radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t
                     hipStream_t s);
 void radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, int64_t n, int bits,
                     hipStream_t s);
+// As radix_sort_u64, but leaves the result where the last pass wrote it:
+// returns true when that is (keys_tmp, vals_tmp).
+bool radix_sort_u64_any(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, int64_t n, int bits,
+                        hipStream_t s);
 
 // ------------------------------------------------------------ build and count
 void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s);

@@ -98,9 +98,11 @@ void exclusive_scan_impl(const T* in, T* out, int64_t n, T* total, hipStream_t s
 }
 
 // ------------------------------------------------------------------ sort
-constexpr int kSortNT = 256;
+// 8192 keys per workgroup (512 threads): each tile writes 256 digit runs
+// of 32 keys on average, long enough to keep the scatter's writes coalesced.
+constexpr int kSortNT = 512;
 constexpr int kSortVT = 16;
-constexpr int kSortTile = kSortNT * kSortVT;   // 4096 keys per workgroup
+constexpr int kSortTile = kSortNT * kSortVT;   // 8192 keys per workgroup
 constexpr int kSortWaves = kSortNT / 64;
 constexpr int kPerWave = kSortTile / kSortWaves;  // 1024
 
@@ -108,7 +110,7 @@ template <typename K>
 __global__ __launch_bounds__(kSortNT) void sort_hist_kernel(const K* __restrict__ keys, int64_t n, int shift,
                                                             uint32_t* __restrict__ counts, int64_t tiles) {
   __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  if (threadIdx.x < 256) h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(kSortNT) void sort_hist_kernel(const K* __restrict_
     if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  counts[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+  if (threadIdx.x < 256) counts[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
 }
 
 template <typename K>
@@ -166,16 +168,21 @@ __global__ __launch_bounds__(kSortNT) void sort_scatter_kernel(const K* __restri
   }
   __syncthreads();
   {
-    uint32_t c[kSortWaves];
+    // thread t < 256 handles digit t
     uint32_t tot = 0;
+    if (t < 256) {
+      uint32_t c[kSortWaves];
 #pragma unroll
-    for (int q = 0; q < kSortWaves; ++q) { c[q] = wcnt[q][t]; }
+      for (int q = 0; q < kSortWaves; ++q) { c[q] = wcnt[q][t]; }
 #pragma unroll
-    for (int q = 0; q < kSortWaves; ++q) { wcnt[q][t] = tot; tot += c[q]; }
+      for (int q = 0; q < kSortWaves; ++q) { wcnt[q][t] = tot; tot += c[q]; }
+    }
     uint32_t all;
     const uint32_t ds = block_exclusive_scan<uint32_t, kSortNT>(tot, red, &all);
-    dstart[t] = ds;
-    goff[t] = offs[(int64_t)t * tiles + blockIdx.x];
+    if (t < 256) {
+      dstart[t] = ds;
+      goff[t] = offs[(int64_t)t * tiles + blockIdx.x];
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -200,9 +207,11 @@ __global__ __launch_bounds__(kSortNT) void sort_scatter_kernel(const K* __restri
   }
 }
 
+// Returns true when the sorted data ends in (ktmp, vtmp) (copy_back false).
 template <typename K>
-void radix_sort_impl(K* keys, uint32_t* vals, K* ktmp, uint32_t* vtmp, int64_t n, int bits, hipStream_t s) {
-  if (n <= 1 || bits <= 0) return;
+bool radix_sort_impl(K* keys, uint32_t* vals, K* ktmp, uint32_t* vtmp, int64_t n, int bits, hipStream_t s,
+                     bool copy_back = true) {
+  if (n <= 1 || bits <= 0) return false;
   const int64_t tiles = (n + kSortTile - 1) / kSortTile;
   uint32_t* counts = nullptr;
   counts = static_cast<uint32_t*>(cache_alloc(sizeof(uint32_t) * 256 * (size_t)tiles, s));
@@ -219,11 +228,13 @@ void radix_sort_impl(K* keys, uint32_t* vals, K* ktmp, uint32_t* vtmp, int64_t n
     K* tk = ks; ks = kd; kd = tk;
     uint32_t* tv = vs; vs = vd; vd = tv;
   }
-  if (ks != keys) {
+  const bool in_tmp = ks != keys;
+  if (in_tmp && copy_back) {
     BFC_HIP(hipMemcpyAsync(keys, ks, sizeof(K) * (size_t)n, hipMemcpyDeviceToDevice, s));
     BFC_HIP(hipMemcpyAsync(vals, vs, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
   }
   cache_free(counts, s);
+  return in_tmp && !copy_back;
 }
 
 }  // namespace
@@ -244,6 +255,10 @@ void radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vt
 void radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
                     hipStream_t s) {
   radix_sort_impl<uint64_t>(keys, vals, ktmp, vtmp, n, bits, s);
+}
+bool radix_sort_u64_any(uint64_t* keys, uint32_t* vals, uint64_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
+                        hipStream_t s) {
+  return radix_sort_impl<uint64_t>(keys, vals, ktmp, vtmp, n, bits, s, false);
 }
 
 }  // namespace bfc
