@@ -527,6 +527,28 @@ __device__ __forceinline__ void seg_walk(const int32_t* __restrict__ oadj, const
   }
 }
 
+// Walks all T positions of a segment list, the workgroup's wavefronts
+// taking chunks of whole iterations from an LDS ticket (0 on entry), so a
+// wavefront that meets a slow stretch (short segments) takes fewer chunks.
+template <typename Fn, typename Stop>
+__device__ __forceinline__ void chunk_walk(const int32_t* __restrict__ oadj, const int32_t* se, const int32_t* sd,
+                                           int32_t n, int32_t T, int32_t* ticket, Fn&& fn, Stop&& stop) {
+  // about four chunks per wavefront
+  int32_t chunk = (T / 64 + 511) & ~511;
+  chunk = chunk < 512 ? 512 : (chunk > 8192 ? 8192 : chunk);
+  bool stopped = false;
+  for (;;) {
+    int32_t c = 0;
+    if (__lane_id() == 0) c = atomicAdd(ticket, 1);
+    c = __shfl(c, 0, 64);
+    const int64_t F0 = (int64_t)c * chunk;
+    if (F0 >= T) break;
+    const int32_t F1 = F0 + chunk < T ? (int32_t)F0 + chunk : T;
+    seg_walk(oadj, se, sd, n, (int32_t)F0, F1, fn, [&] { stopped = stop(); return stopped; });
+    if (stopped) break;
+  }
+}
+
 // Segment list capacities: pass 1 keeps (se, sd); pass 2 also keeps the
 // middle index and a 64-bit delta sum per segment.
 constexpr int kSeg1 = 2048;
@@ -544,6 +566,8 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
   __shared__ __align__(16) int32_t segbuf[kSegWords];
   __shared__ unsigned long long s_red64[kHeavyWaves + 1];
   __shared__ int32_t s_idx, s_fill, s_over, s_cut_j, s_cut_lex;
+  __shared__ int32_t s_ticket;  // chunk ticket of the dense walk
+  __shared__ unsigned long long s_emit;  // resident emission: count << 32 | total length
 
   const int t = threadIdx.x;
   const int lane = __lane_id();
@@ -793,7 +817,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
             nseg = segcap;
           }
         }
-        if (t == 0) se[nseg] = T;
+        if (t == 0) { se[nseg] = T; s_ticket = 0; }
         __syncthreads();
       };
       // this wavefront's share of the batch's positions
@@ -884,7 +908,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
           __syncthreads();
           T = s_cut_j - lex0;
         }
-        if (t == 0) se[nseg] = T;
+        if (t == 0) { se[nseg] = T; s_ticket = 0; }
         __syncthreads();
       };
       // Resident mode: the window is final; its slice ends become the next starts.
@@ -900,7 +924,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       int32_t halvings = 0;
       int32_t batches = 0, last_n = 0, last_t = 0;
       for (;;) {
-        if (t == 0) { s_fill = 0; s_over = 0; }
+        if (t == 0) { s_fill = 0; s_over = 0; s_emit = 0ull; }
         __syncthreads();
         int32_t* se = segbuf;
         int32_t* sd = segbuf + kSeg1 + 1;
@@ -911,8 +935,41 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         while (rj < pre1) {
           int32_t nseg, T;
           if (resident) {
-            int32_t nact;
-            res_emit(pre1, 0, kSeg1, false, se, sd, nullptr, nullptr, nseg, T, nact);
+            {
+              // every slice fits one batch, in any order: each wavefront
+              // reserves its entries and positions with one LDS atomic
+              const bool a0 = 2 * t < pre1 && rce[0] > rcs[0];
+              const bool a1 = 2 * t + 1 < pre1 && rce[1] > rcs[1];
+              const uint32_t l0 = a0 ? (uint32_t)(rce[0] - rcs[0]) : 0u;
+              const uint32_t l1 = a1 ? (uint32_t)(rce[1] - rcs[1]) : 0u;
+              const unsigned long long v = ((unsigned long long)((int)a0 + (int)a1) << 32) | (l0 + l1);
+              const unsigned long long inc = wave_inclusive_scan(v);
+              const unsigned long long wt = __shfl(inc, 63, 64);
+              unsigned long long wb = 0;
+              if (lane == 63 && wt) wb = atomicAdd(&s_emit, wt);
+              wb = __shfl(wb, 63, 64);
+              unsigned long long at = wb + inc - v;
+              if (a0) {
+                const int32_t ps = (int32_t)(at >> 32), L = (int32_t)(uint32_t)at;
+                se[ps] = L;
+                sd[ps] = rcs[0] - L;
+                at += (1ull << 32) | l0;
+              }
+              if (a1) {
+                const int32_t ps = (int32_t)(at >> 32), L = (int32_t)(uint32_t)at;
+                se[ps] = L;
+                sd[ps] = rcs[1] - L;
+              }
+              __syncthreads();
+              const unsigned long long all = s_emit;
+              nseg = (int32_t)(all >> 32);
+              T = (int32_t)(uint32_t)all;
+              if (t == 0) {
+                se[nseg] = T;
+                s_ticket = 0;
+              }
+              __syncthreads();
+            }
             rj = pre1;  // one batch holds every slice (pre <= kSeg1)
           } else {
             fill(pre1, kSeg1, false, se, sd, nullptr, nullptr, rj, nseg, T);
@@ -925,7 +982,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
           if (wdense && whalf) {
             // lo_w is even: counter pair (w >> 1) - (lo_w >> 1), half (w & 1)
             uint32_t* tw = reinterpret_cast<uint32_t*>(table) - (lo_w >> 1);
-            seg_walk(O.adj, se, sd, nseg, F0, F1,
+            chunk_walk(O.adj, se, sd, nseg, T, &s_ticket,
                      [&](int32_t, int32_t, int32_t w) { atomicAdd(&tw[w >> 1], (uint32_t)(w & 1) * 65535u + 1u); },
                      [] { return false; });
           } else if (wdense) {
