@@ -151,7 +151,7 @@ def bench_batch(args) -> int:
     b = gg.batch_workload(count=args.graphs)
     log(f"generated {b.count} graphs, {int(b.offsets[-1])} edges in {time.perf_counter() - t:.1f}s")
     edges = torch.from_numpy(b.edges).cuda()
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # capture needs a created stream
     torch.cuda.synchronize()
     totals = torch.zeros(b.count, dtype=torch.int64, device="cuda")
     # batched: build + captured count

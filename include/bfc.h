@@ -132,7 +132,8 @@ bfc_status bfc_batch_wedges(bfc_graph g, int64_t* wedges_host);
  * totals_dev) into a HIP graph owned by the handle (replacing an earlier
  * one); bfc_graph_replay launches it on `stream`.  The captured work
  * allocates nothing and records no memset nodes.  totals_dev must stay valid
- * while the capture is in use.
+ * while the capture is in use.  `stream` must be a created stream (the
+ * default stream cannot be captured): BFC_ERR_INVALID_ARGUMENT otherwise.
  */
 bfc_status bfc_graph_capture_total(bfc_graph g, void* stream, int64_t* totals_dev);
 bfc_status bfc_graph_replay(bfc_graph g, void* stream);

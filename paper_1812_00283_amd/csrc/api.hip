@@ -239,6 +239,7 @@ bfc_status bfc_graph_capture_total(bfc_graph g, void* stream, int64_t* totals_de
   return guard([&] {
     bfc_graph_s* h = checked(g);
     if (!totals_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "totals_dev is null"};
+    if (!stream) throw Error{BFC_ERR_INVALID_ARGUMENT, "capture needs a created stream (the default stream cannot be captured)"};
     DeviceScope ds(h->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> hold(h->mu);

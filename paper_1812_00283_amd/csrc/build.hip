@@ -242,6 +242,32 @@ unsigned grid_1d(int64_t n) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
+// largest g in [0, G) with off[g] <= x (off non-decreasing, off[0] <= x)
+template <typename T>
+__device__ __forceinline__ int32_t graph_of(const T* __restrict__ off, int32_t G, T x) {
+  int32_t lo = 0, hi = G;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Batch priority keys: (graph << db) | degree, so a stable sort by key
+// ranks each graph's vertices contiguously, in Definition 3's order inside
+// the graph (ids of one graph are consecutive, ties keep id order).
+__global__ void group_key_kernel(const int32_t* __restrict__ deg, int64_t n, const int32_t* __restrict__ goff,
+                                 int32_t G, int db, uint64_t* __restrict__ key) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    key[i] = ((uint64_t)graph_of<int32_t>(goff, G, (int32_t)i) << db) | (uint32_t)deg[i];
+}
+
+__global__ void low_bits_kernel(const uint64_t* __restrict__ key, int64_t n, int db, uint32_t* __restrict__ out) {
+  const uint64_t mask = (1ull << db) - 1ull;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (uint32_t)(key[i] & mask);
+}
+
 // ---- window-boundary tables
 // Degrees do not decrease with rank, so the vertices of degree >= D are the
 // ranks from the first such one up.
@@ -277,7 +303,7 @@ __global__ void window_table_kernel(const int32_t* __restrict__ off, const int32
 
 }  // namespace
 
-void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
+void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int32_t* const* groups, int32_t G) {
   const int64_t m = g->m;
   const int32_t n[2] = {g->n_upper, g->n_lower};
 
@@ -336,12 +362,26 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s) {
     ktmp.alloc(sizeof(uint32_t) * (size_t)nx, s);
     vtmp.alloc(sizeof(uint32_t) * (size_t)nx, s);
     if (nx > 0) {
-      BFC_HIP(hipMemcpyAsync(deg_rank[x].p, deg[x].p, sizeof(uint32_t) * (size_t)nx, hipMemcpyDeviceToDevice, s));
       iota_kernel<<<grid_1d(nx), 256, 0, s>>>(vals.as<uint32_t>(), nx);
       BFC_LAUNCH_CHECK();
       const int64_t max_deg = m < n[1 - x] ? m : n[1 - x];
-      radix_sort_u32(deg_rank[x].as<uint32_t>(), vals.as<uint32_t>(), ktmp.as<uint32_t>(), vtmp.as<uint32_t>(), nx,
-                     bits_for((uint64_t)max_deg), s);
+      const int db = bits_for((uint64_t)max_deg);
+      if (groups && G > 1) {
+        // batch: sort by (graph, degree); the degrees in rank order are the keys' low bits
+        TmpBuf key, key_tmp;
+        key.alloc(sizeof(uint64_t) * (size_t)nx, s);
+        key_tmp.alloc(sizeof(uint64_t) * (size_t)nx, s);
+        group_key_kernel<<<grid_1d(nx), 256, 0, s>>>(deg[x].as<int32_t>(), nx, groups[x], G, db, key.as<uint64_t>());
+        BFC_LAUNCH_CHECK();
+        radix_sort_u64(key.as<uint64_t>(), vals.as<uint32_t>(), key_tmp.as<uint64_t>(), vtmp.as<uint32_t>(), nx,
+                       db + bits_for((uint64_t)(G - 1)), s);
+        low_bits_kernel<<<grid_1d(nx), 256, 0, s>>>(key.as<uint64_t>(), nx, db, deg_rank[x].as<uint32_t>());
+        BFC_LAUNCH_CHECK();
+      } else {
+        BFC_HIP(hipMemcpyAsync(deg_rank[x].p, deg[x].p, sizeof(uint32_t) * (size_t)nx, hipMemcpyDeviceToDevice, s));
+        radix_sort_u32(deg_rank[x].as<uint32_t>(), vals.as<uint32_t>(), ktmp.as<uint32_t>(), vtmp.as<uint32_t>(), nx,
+                       db, s);
+      }
     }
     // deg_rank = degrees in rank order; id_of = ids in rank order
     rank_of[x].alloc(sizeof(int32_t) * (size_t)nx, s);
@@ -599,17 +639,6 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
 // ---------------------------------------------------------------- batches
 namespace {
 
-// largest g in [0, G) with off[g] <= x (off non-decreasing, off[0] <= x)
-template <typename T>
-__device__ __forceinline__ int32_t graph_of(const T* __restrict__ off, int32_t G, T x) {
-  int32_t lo = 0, hi = G;
-  while (hi - lo > 1) {
-    const int32_t mid = (lo + hi) >> 1;
-    if (off[mid] <= x) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 __global__ void shift_kernel(const int32_t* __restrict__ edges, int64_t m, const int64_t* __restrict__ eoff,
                              int32_t G, const int32_t* __restrict__ uoff, const int32_t* __restrict__ loff,
                              int32_t* __restrict__ out, int32_t* __restrict__ status) {
@@ -683,7 +712,13 @@ void build_batch(bfc_graph_s* g, const int32_t* edges, const int64_t* eoff_host,
   BFC_HIP(hipMemcpyAsync(st, status.p, sizeof(st), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
   if (st[0]) throw Error{BFC_ERR_VERTEX_OUT_OF_RANGE, "a batch edge has an id outside its graph's layers"};
-  build_graph(g, shifted.as<int32_t>(), s);
+  const int32_t* groups[2] = {d_uoff.as<int32_t>(), d_loff.as<int32_t>()};
+  build_graph(g, shifted.as<int32_t>(), s, groups, G);
+  // graph i's vertices of layer x hold ranks [off_x[i], off_x[i+1]) of that layer
+  for (int x = 0; x < 2; ++x) {
+    g->grank[x].alloc(sizeof(int32_t) * (size_t)(G + 1), s);
+    BFC_HIP(hipMemcpyAsync(g->grank[x].p, groups[x], sizeof(int32_t) * (size_t)(G + 1), hipMemcpyDeviceToDevice, s));
+  }
   TmpBuf gw;
   gw.alloc(sizeof(int64_t) * (size_t)G, s);
   BFC_HIP(hipMemsetAsync(gw.p, 0, sizeof(int64_t) * (size_t)G, s));

@@ -58,6 +58,7 @@ struct CountParams {
   int32_t dense_min_wedges;
   unsigned long long* gtotal;  // per-graph totals of a batch (kTotal), else null
   const int32_t* gid[2];       // graph index of every rank, per layer (null: one graph)
+  const int32_t* grank[2];     // first rank of each graph, per layer (null: one graph)
   int32_t dtop[2];             // first rank of the dense block per layer (n_X when disabled)
   const int32_t* dC[2];        // MFMA products CU, CL (row-major)
   int32_t dld[2];              // their row strides
@@ -596,13 +597,19 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
     const int32_t pre = S.lo[r];
     const int64_t W = S.work[r];
     const int32_t range = r;
+    // ends lie in [rlo, r): a batch ranks each graph's vertices contiguously
+    // (rlo = the graph's first rank, rounded down to even because dense
+    // counters pair ranks; one graph: 0)
+    const int32_t* grank = x ? p.grank[1] : p.grank[0];
+    const int32_t rlo = grank ? (grank[graph_index(p, x, r)] & ~1) : 0;
+    const int32_t span = range - rlo;
     // middles of rank >= tfirst find their window slices in the table and
     // keep no cursor
     const int32_t* tab = x ? p.wt[0] : p.wt[1];
     const int32_t tfirst = tab ? (x ? p.wt_first[0] : p.wt_first[1]) : 0x7FFFFFFF;
     const int32_t trow = x ? p.wt_row[0] : p.wt_row[1];
     const bool dense = p.window_mode == 2 || (p.window_mode == 1 && (W > p.dense_min_wedges ||
-                                                                     W * (int64_t)p.dense_ratio >= (int64_t)range));
+                                                                     W * (int64_t)p.dense_ratio >= (int64_t)span));
     const bool half = pre < 65536;
     // Starts in the dense block: the last window covers the block's end ranks
     // [top, r); its counters start from the MFMA products and its first pass
@@ -616,31 +623,34 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
     int32_t hwidth = 0, hash_end = 0;
     uint32_t cap = kHashCap;
     if (dense) {
-      if (p.window_mode == 1 && base > 0) {
+      const int32_t base_lo = S.off[rlo];
+      hash_end = rlo;
+      if (p.window_mode == 1 && base > base_lo) {
         // Sparse prefix of a dense start: the ends of its wedges are
         // neighbours of its middles, which in a degree-driven graph fall on
         // the start layer's vertices in proportion to their degree, so about
-        // W * off_X[x] / off_X[r] wedges end below rank x.  The prefix is the
+        // W * (off_X[x] - off_X[rlo]) / (off_X[r] - off_X[rlo]) wedges end
+        // below rank x.  The prefix is the
         // longest multiple of the dense width expected to hold at most
         // hash_window_wedges of them (one 64-lane probe of off_X); a wrong
         // guess costs time only (an overfull hash window is split).
-        const int32_t step0 = (sparse_end + 63) / 64;
+        const int32_t step0 = (sparse_end - rlo + 63) / 64;
         const int32_t step = (step0 + 2 * kTableWords - 1) / (2 * kTableWords) * (2 * kTableWords);
-        const int64_t xl = (int64_t)(lane + 1) * step;
-        const bool ok = xl < sparse_end &&
-                        (double)W * (double)S.off[xl] <= (double)p.hash_window_wedges * (double)base;
-        hash_end = __popcll(__ballot(ok)) * step;
-        hwidth = hash_end;
+        const int64_t xl = rlo + (int64_t)(lane + 1) * step;
+        const bool ok = xl < sparse_end && (double)W * (double)(S.off[xl] - base_lo) <=
+                                               (double)p.hash_window_wedges * (double)(base - base_lo);
+        hash_end = rlo + __popcll(__ballot(ok)) * step;
+        hwidth = hash_end - rlo;
       }
     } else {
       hash_end = sparse_end;
       if (W <= kHashSingleMax) {
-        hwidth = range;
+        hwidth = span;
         cap = 512;
         while ((int64_t)cap < 2 * W) cap <<= 1;
       } else {
-        const int64_t wd = (int64_t)range * p.hash_window_wedges / W;
-        hwidth = (int32_t)(wd < 256 ? 256 : (wd > range ? range : wd));
+        const int64_t wd = (int64_t)span * p.hash_window_wedges / W;
+        hwidth = (int32_t)(wd < 256 ? 256 : (wd > span ? span : wd));
       }
     }
     int32_t pre_out = pre;
@@ -665,7 +675,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         nxt[j] = ps < S.rev[k] ? O.adj[ps] : kNone;
       }
     };
-    bool cursors = !(sparse_end == range && (hash_end >= range ? hwidth >= range : (hash_end == 0 && width >= range)));
+    bool cursors = !(sparse_end == range && (hash_end >= range ? hwidth >= span : (hash_end == rlo && width >= span)));
     // Resident mode: a multi-window start with at most 2 * kHeavyNT middles
     // keeps middle 2t + h's slice state in thread t's registers: the end of
     // its list below r (re), the start of its current slice (rcs), and raux
@@ -694,7 +704,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       init_cursors();
     }
     unsigned long long start_acc = 0;
-    int32_t lo_w = 0;
+    int32_t lo_w = rlo;
     for (;;) {
       int32_t hi_w;
       bool wdense = lo_w >= hash_end;
@@ -1165,7 +1175,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         const int64_t fill_n = s_fill;
         int64_t next = fill_n > 0 ? span * (int64_t)(cap / 4) / fill_n : 2 * span;
         next = next < 64 ? 64 : next;
-        hwidth = (int32_t)(next > range ? range : next);
+        hwidth = (int32_t)(next > span ? span : next);
       }
       __syncthreads();
       lo_w = hi_w;
@@ -1277,6 +1287,13 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     p.wt[o] = g->wt[o].bytes ? g->wt[o].as<int32_t>() : nullptr;
     p.wt_first[o] = g->wt_first[o];
     p.wt_row[o] = g->wt_row[o];
+  }
+  if (g->grank[0].bytes && g->grank[1].bytes) {
+    // a batch: each start's ends lie in its graph's rank range
+    p.gid[0] = g->gid[0].as<int32_t>();
+    p.gid[1] = g->gid[1].as<int32_t>();
+    p.grank[0] = g->grank[0].as<int32_t>();
+    p.grank[1] = g->grank[1].as<int32_t>();
   }
   if (gtotals) {
     p.total = nullptr;

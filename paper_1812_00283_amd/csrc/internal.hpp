@@ -158,6 +158,7 @@ struct bfc_graph_s {
   // batches: graph index of every rank (per layer) and per-graph |W|
   int32_t n_graphs = 1;
   bfc::DevBuf gid[2];
+  bfc::DevBuf grank[2];   // per layer: first rank of each graph (G + 1), batches only
   std::vector<int64_t> graph_wedges;
   // captured total count
   hipGraph_t cap_graph = nullptr;
@@ -204,7 +205,11 @@ bool radix_sort_u64_any(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint
                         hipStream_t s);
 
 // ------------------------------------------------------------ build and count
-void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s);
+// groups (batches): per layer, G + 1 device offsets of each graph's ids;
+// vertices are then ranked by (graph, degree, id) so each graph's ranks are
+// contiguous.
+void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int32_t* const* groups = nullptr,
+                 int32_t G = 0);
 void build_schedule(bfc_graph_s* g, hipStream_t s);
 
 enum CountMode { kTotal = 0, kVertex = 1, kEdge = 2 };

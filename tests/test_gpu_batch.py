@@ -78,6 +78,9 @@ def test_capture_and_replay(gpu_lib):
     with gpu_lib.build_batch(torch.from_numpy(b.edges).cuda(), b.offsets, b.n_upper, b.n_lower) as h:
         h.set_tuning(light_max_wedges=64)
         out = torch.full((len(graphs),), -1, dtype=torch.int64, device="cuda")
+        with pytest.raises(gpu_lib.BfcError) as err:  # the default stream cannot be captured
+            h.capture_total(out, stream=torch.cuda.default_stream())
+        assert err.value.status == 1
         s = torch.cuda.Stream()
         h.capture_total(out, stream=s)
         for k in range(4):
