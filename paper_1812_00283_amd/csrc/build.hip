@@ -194,12 +194,26 @@ __global__ void arc_unpack_kernel(const uint64_t* __restrict__ keys, const uint3
   }
 }
 
-// Reverse slots from side 1's sorted order: slot k of side 1 holds edge
-// perm1[k], whose side-0 slot is eslot[perm1[k]].
-__global__ void link_kernel(int64_t m, const uint32_t* __restrict__ perm1, const int32_t* __restrict__ eslot,
-                            int32_t* __restrict__ rev0, int32_t* __restrict__ rev1) {
+// Side 1 from side 0: key = rank_v of side-0 slot k, value = k.
+__global__ void transpose_keys_kernel(const int32_t* __restrict__ adj0, int64_t m, uint32_t* __restrict__ key,
+                                      uint32_t* __restrict__ val) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t s0 = eslot[perm1[k]];
+    key[k] = (uint32_t)adj0[k];
+    val[k] = (uint32_t)k;
+  }
+}
+
+// Side-1 slot k1 holds the arc of side-0 slot s0 = val[k1]: start rank_v =
+// key[k1], neighbour rank_u = src0[s0]; the two reverse slots point at each
+// other.
+__global__ void transpose_unpack_kernel(const uint32_t* __restrict__ key, const uint32_t* __restrict__ val,
+                                        const int32_t* __restrict__ src0, int64_t m, int32_t* __restrict__ adj1,
+                                        int32_t* __restrict__ src1, int32_t* __restrict__ rev1,
+                                        int32_t* __restrict__ rev0) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s0 = (int32_t)val[k];
+    src1[k] = (int32_t)key[k];
+    adj1[k] = src0[s0];
     rev1[k] = s0;
     rev0[s0] = (int32_t)k;
   }
@@ -393,41 +407,47 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
     exclusive_scan_i32(deg_rank[x].as<int32_t>(), sd.off.as<int32_t>(), nx, sd.off.as<int32_t>() + nx, s);
   }
 
-  // ---- per-side CSR by sorting (rank, neighbour rank) keys; side 0's
-  // order gives eslot (edge -> side-0 slot), side 1's the reverse slots
+  // ---- per-side CSR.  Side 0: sort (rank_u, rank_v) keys; its order gives
+  // eslot (edge -> side-0 slot).  Side 1 is side 0 transposed: side 0's arcs
+  // are in ascending (u, v) order, so a stable sort of them by v alone lists
+  // each v's neighbours u in ascending order.  The sort's values are side-0
+  // slots, which are side 1's reverse slots.
   TmpBuf src[2];
   for (int x = 0; x < 2; ++x) g->side[x].rev.alloc(sizeof(int32_t) * (size_t)m, s);
   g->eslot.alloc(sizeof(int32_t) * (size_t)m, s);
   const int bits[2] = {bits_for((uint64_t)(n[0] > 1 ? n[0] - 1 : 1)), bits_for((uint64_t)(n[1] > 1 ? n[1] - 1 : 1))};
-  {
+  for (int x = 0; x < 2; ++x) {
+    g->side[x].adj.alloc(sizeof(int32_t) * (size_t)m, s);
+    src[x].alloc(sizeof(int32_t) * (size_t)m, s);
+  }
+  if (m > 0) {
     TmpBuf keys, vals, ktmp, vtmp;
     keys.alloc(sizeof(uint64_t) * (size_t)m, s);
     vals.alloc(sizeof(uint32_t) * (size_t)m, s);
     ktmp.alloc(sizeof(uint64_t) * (size_t)m, s);
     vtmp.alloc(sizeof(uint32_t) * (size_t)m, s);
-    for (int x = 0; x < 2; ++x) {
-      Side& sd = g->side[x];
-      sd.adj.alloc(sizeof(int32_t) * (size_t)m, s);
-      src[x].alloc(sizeof(int32_t) * (size_t)m, s);
-      if (m == 0) continue;
-      const int bd = bits[1 - x];
-      arc_keys_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, x, rank_of[x].as<int32_t>(), rank_of[1 - x].as<int32_t>(),
-                                                   bd, keys.as<uint64_t>(), vals.as<uint32_t>());
-      BFC_LAUNCH_CHECK();
-      const bool in_tmp = radix_sort_u64_any(keys.as<uint64_t>(), vals.as<uint32_t>(), ktmp.as<uint64_t>(),
-                                             vtmp.as<uint32_t>(), m, bits[0] + bits[1], s);
-      const uint64_t* sk = in_tmp ? ktmp.as<uint64_t>() : keys.as<uint64_t>();
-      const uint32_t* sv = in_tmp ? vtmp.as<uint32_t>() : vals.as<uint32_t>();
-      arc_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(sk, sv, m, bd,
-                                                     sd.adj.as<int32_t>(), src[x].as<int32_t>(),
-                                                     x == 0 ? g->eslot.as<int32_t>() : nullptr, status.as<int32_t>());
-      BFC_LAUNCH_CHECK();
-      if (x == 1) {
-        link_kernel<<<grid_1d(m), 256, 0, s>>>(m, sv, g->eslot.as<int32_t>(),
-                                                g->side[0].rev.as<int32_t>(), g->side[1].rev.as<int32_t>());
-        BFC_LAUNCH_CHECK();
-      }
-    }
+    arc_keys_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, 0, rank_of[0].as<int32_t>(), rank_of[1].as<int32_t>(),
+                                                 bits[1], keys.as<uint64_t>(), vals.as<uint32_t>());
+    BFC_LAUNCH_CHECK();
+    const bool in_tmp = radix_sort_u64_any(keys.as<uint64_t>(), vals.as<uint32_t>(), ktmp.as<uint64_t>(),
+                                           vtmp.as<uint32_t>(), m, bits[0] + bits[1], s);
+    arc_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(in_tmp ? ktmp.as<uint64_t>() : keys.as<uint64_t>(),
+                                                 in_tmp ? vtmp.as<uint32_t>() : vals.as<uint32_t>(), m, bits[1],
+                                                 g->side[0].adj.as<int32_t>(), src[0].as<int32_t>(),
+                                                 g->eslot.as<int32_t>(), status.as<int32_t>());
+    BFC_LAUNCH_CHECK();
+    // side 1: keys = rank_v of each side-0 slot, values = the slot
+    uint32_t* k1 = reinterpret_cast<uint32_t*>(keys.p);
+    uint32_t* v1 = vals.as<uint32_t>();
+    uint32_t* k1t = reinterpret_cast<uint32_t*>(ktmp.p);
+    uint32_t* v1t = vtmp.as<uint32_t>();
+    transpose_keys_kernel<<<grid_1d(m), 256, 0, s>>>(g->side[0].adj.as<int32_t>(), m, k1, v1);
+    BFC_LAUNCH_CHECK();
+    radix_sort_u32(k1, v1, k1t, v1t, m, bits[1], s);
+    transpose_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(k1, v1, src[0].as<int32_t>(), m, g->side[1].adj.as<int32_t>(),
+                                                       src[1].as<int32_t>(), g->side[1].rev.as<int32_t>(),
+                                                       g->side[0].rev.as<int32_t>());
+    BFC_LAUNCH_CHECK();
   }
 
   // ---- per start: lower-priority prefix length and wedges
