@@ -63,7 +63,7 @@ int64_t bfc_graph_s::device_bytes() const {
     const bfc::Side& s = side[x];
     b += s.off.bytes + s.adj.bytes + s.rev.bytes + s.lo.bytes + s.id_of.bytes + s.work.bytes;
   }
-  b += eslot.bytes + wt[0].bytes + wt[1].bytes + sched.light.bytes + sched.heavy.bytes + scratch.bytes + acc.bytes;
+  b += edge0.bytes + wt[0].bytes + wt[1].bytes + sched.light.bytes + sched.heavy.bytes + scratch.bytes + acc.bytes;
   return b;
 }
 
@@ -103,7 +103,7 @@ const char* bfc_version(void) { return "bfc-mi355x 0.1 (gfx950)"; }
 int64_t bfc_estimate_device_bytes(int64_t m, int32_t n_upper, int32_t n_lower) {
   if (m < 0 || n_upper < 0 || n_lower < 0) return 0;
   const int64_t n = (int64_t)n_upper + n_lower;
-  // resident: 2 sides x (adj + rev) + eslot + per-vertex arrays + window
+  // resident: 2 sides x (adj + rev) + edge0 + per-vertex arrays + window
   // tables (at most 2 bytes per edge each)
   const int64_t resident = m * 4 * 5 + m * 4 + n * (4 + 4 + 4 + 8) + 2 * 4 * (int64_t)2 + 4096;
   // build peak: resident + sort buffers (2 x (8 + 4) bytes per edge) + slots

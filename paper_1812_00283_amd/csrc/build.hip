@@ -183,13 +183,13 @@ __global__ void arc_keys_kernel(const int32_t* __restrict__ edges, int64_t m, in
 
 __global__ void arc_unpack_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t m,
                                   int bits_dst, int32_t* __restrict__ adj, int32_t* __restrict__ src,
-                                  int32_t* __restrict__ slot_of_edge, int32_t* __restrict__ status) {
+                                  int32_t* __restrict__ edge_of_slot, int32_t* __restrict__ status) {
   const uint64_t mask = (1ull << bits_dst) - 1ull;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t key = keys[k];
     adj[k] = (int32_t)(key & mask);
     src[k] = (int32_t)(key >> bits_dst);
-    if (slot_of_edge) slot_of_edge[vals[k]] = (int32_t)k;
+    edge_of_slot[k] = (int32_t)vals[k];
     if (k > 0 && keys[k - 1] == key) atomicOr(&status[1], 1);
   }
 }
@@ -407,14 +407,14 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
     exclusive_scan_i32(deg_rank[x].as<int32_t>(), sd.off.as<int32_t>(), nx, sd.off.as<int32_t>() + nx, s);
   }
 
-  // ---- per-side CSR.  Side 0: sort (rank_u, rank_v) keys; its order gives
-  // eslot (edge -> side-0 slot).  Side 1 is side 0 transposed: side 0's arcs
+  // ---- per-side CSR.  Side 0: sort (rank_u, rank_v) keys; the sort's
+  // values give edge0 (side-0 slot -> input edge index).  Side 1 is side 0 transposed: side 0's arcs
   // are in ascending (u, v) order, so a stable sort of them by v alone lists
   // each v's neighbours u in ascending order.  The sort's values are side-0
   // slots, which are side 1's reverse slots.
   TmpBuf src[2];
   for (int x = 0; x < 2; ++x) g->side[x].rev.alloc(sizeof(int32_t) * (size_t)m, s);
-  g->eslot.alloc(sizeof(int32_t) * (size_t)m, s);
+  g->edge0.alloc(sizeof(int32_t) * (size_t)m, s);
   const int bits[2] = {bits_for((uint64_t)(n[0] > 1 ? n[0] - 1 : 1)), bits_for((uint64_t)(n[1] > 1 ? n[1] - 1 : 1))};
   for (int x = 0; x < 2; ++x) {
     g->side[x].adj.alloc(sizeof(int32_t) * (size_t)m, s);
@@ -434,7 +434,7 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
     arc_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(in_tmp ? ktmp.as<uint64_t>() : keys.as<uint64_t>(),
                                                  in_tmp ? vtmp.as<uint32_t>() : vals.as<uint32_t>(), m, bits[1],
                                                  g->side[0].adj.as<int32_t>(), src[0].as<int32_t>(),
-                                                 g->eslot.as<int32_t>(), status.as<int32_t>());
+                                                 g->edge0.as<int32_t>(), status.as<int32_t>());
     BFC_LAUNCH_CHECK();
     // side 1: keys = rank_v of each side-0 slot, values = the slot
     uint32_t* k1 = reinterpret_cast<uint32_t*>(keys.p);

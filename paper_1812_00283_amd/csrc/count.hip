@@ -1196,14 +1196,14 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
   }
 }
 
-__global__ void fold_edges_kernel(const int32_t* __restrict__ eslot, const int32_t* __restrict__ rev0,
+// B_e of the edge at side-0 slot k: its two arcs' accumulators, written to
+// the edge's input position.
+__global__ void fold_edges_kernel(const int32_t* __restrict__ edge0, const int32_t* __restrict__ rev0,
                                   const unsigned long long* __restrict__ acc0,
                                   const unsigned long long* __restrict__ acc1, int64_t m,
                                   unsigned long long* __restrict__ out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t a = eslot[i];
-    out[i] = acc0[a] + acc1[rev0[a]];
-  }
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
+    out[edge0[k]] = acc0[k] + acc1[rev0[k]];
 }
 
 int num_cus() {
@@ -1351,7 +1351,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   if (mode == kEdge && g->m > 0) {
     int64_t grid = (g->m + 255) / 256;
     if (grid > 65536) grid = 65536;
-    fold_edges_kernel<<<(unsigned)grid, 256, 0, s>>>(g->eslot.as<int32_t>(), g->side[0].rev.as<int32_t>(),
+    fold_edges_kernel<<<(unsigned)grid, 256, 0, s>>>(g->edge0.as<int32_t>(), g->side[0].rev.as<int32_t>(),
                                                      p.acc[0], p.acc[1], g->m,
                                                      reinterpret_cast<unsigned long long*>(out0));
     BFC_LAUNCH_CHECK();

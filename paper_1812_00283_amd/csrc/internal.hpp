@@ -147,7 +147,7 @@ struct bfc_graph_s {
   int64_t m = 0;
   int32_t n_upper = 0, n_lower = 0;
   bfc::Side side[2];      // 0 = upper layer, 1 = lower layer
-  bfc::DevBuf eslot;      // int32 [m] slot of edge i in side[0].adj
+  bfc::DevBuf edge0;      // int32 [m] input edge index of each side[0].adj slot
   // window-boundary tables, one per middle layer o: for the ranks
   // v >= wt_first[o] (the vertices of degree >= wt_min_degree), row v holds
   // wt_row[o] slots; entry w is the first slot of N(v) whose end rank is
