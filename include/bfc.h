@@ -156,7 +156,8 @@ bfc_status bfc_destroy(bfc_graph g);
 /*
  * Tuning knobs for one handle.  None of them changes any count; they choose
  * which kernel path handles each start vertex.  A field <= 0 keeps the
- * current setting (except dense_block, where 0 disables and < 0 keeps).
+ * current setting (except dense_block and medium_max_wedges, where 0
+ * disables and < 0 keeps).
  *   light_max_wedges   starts with at most this many wedges (<= 1024) are
  *                      counted by one wavefront with an LDS hash table;
  *                      larger ones by a workgroup.  Default 1024.
@@ -175,6 +176,11 @@ bfc_status bfc_destroy(bfc_graph g);
  *                      8192.
  *   dense_block        vertices per layer in the top-priority block counted
  *                      with int8 MFMA (0 disables it; multiple of 64).
+ *   medium_max_wedges  workgroup starts with at most this many wedges and at
+ *                      most 512 middles (outside the dense block) use
+ *                      256-thread workgroups with a 32 KB LDS table, four to
+ *                      a CU; the others 1024 threads and 128 KB.  0 puts
+ *                      every workgroup start on 1024 threads.  Default 0.
  */
 typedef struct {
   int32_t light_max_wedges;
@@ -183,6 +189,7 @@ typedef struct {
   int32_t hash_window_wedges;
   int32_t dense_block;
   int32_t dense_min_wedges;
+  int32_t medium_max_wedges;
 } bfc_tuning;
 
 bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t);
@@ -192,7 +199,8 @@ bfc_status bfc_get_tuning(bfc_graph g, bfc_tuning* t);
  * Work split of a built graph (for reporting; all counts are exact integers).
  *   wedges          |W|, the wedges Algorithm 2 processes (Theorem 2's measure)
  *   starts_*        start vertices handed to the wavefront (light) and
- *                   workgroup (heavy) kernels
+ *                   workgroup (heavy) kernels; starts_medium of the heavy
+ *                   ones run on 256-thread workgroups
  *   wedges_*        wedges those starts process
  *   middles_*       lower-priority neighbours (middle vertices) they walk
  *   max_start_wedges  the largest per-start wedge count
@@ -203,6 +211,7 @@ typedef struct {
   int64_t wedges_light, wedges_heavy;
   int64_t middles_light, middles_heavy;
   int64_t max_start_wedges;
+  int64_t starts_medium;
 } bfc_schedule_info;
 
 bfc_status bfc_get_schedule_info(bfc_graph g, bfc_schedule_info* out);

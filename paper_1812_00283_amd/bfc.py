@@ -45,13 +45,14 @@ class BfcError(RuntimeError):
 class Tuning(ctypes.Structure):
     _fields_ = [("light_max_wedges", ctypes.c_int32), ("dense_min_ratio", ctypes.c_int32),
                 ("window_mode", ctypes.c_int32), ("hash_window_wedges", ctypes.c_int32),
-                ("dense_block", ctypes.c_int32), ("dense_min_wedges", ctypes.c_int32)]
+                ("dense_block", ctypes.c_int32), ("dense_min_wedges", ctypes.c_int32),
+                ("medium_max_wedges", ctypes.c_int32)]
 
 
 class ScheduleInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("wedges", "starts_light", "starts_heavy", "wedges_light",
                                                "wedges_heavy", "middles_light", "middles_heavy",
-                                               "max_start_wedges")]
+                                               "max_start_wedges", "starts_medium")]
 
 
 class KernelTimes(ctypes.Structure):
@@ -212,10 +213,12 @@ class Graph:
         return {"m": m.value, "n_upper": nu.value, "n_lower": nl.value, "wedges": w.value, "device_bytes": b.value}
 
     def set_tuning(self, light_max_wedges: int = 0, dense_min_ratio: int = 0, window_mode: int = 0,
-                   hash_window_wedges: int = 0, dense_block: int = -1, dense_min_wedges: int = 0) -> None:
+                   hash_window_wedges: int = 0, dense_block: int = -1, dense_min_wedges: int = 0,
+                   medium_max_wedges: int = -1) -> None:
         """Changes which kernel path handles each start; no count changes.
         window_mode: 1 automatic, 2 dense windows only, 3 hash windows only."""
-        t = Tuning(light_max_wedges, dense_min_ratio, window_mode, hash_window_wedges, dense_block, dense_min_wedges)
+        t = Tuning(light_max_wedges, dense_min_ratio, window_mode, hash_window_wedges, dense_block, dense_min_wedges,
+                   medium_max_wedges)
         _check(load().bfc_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
@@ -223,7 +226,8 @@ class Graph:
         _check(load().bfc_get_tuning(self._h, ctypes.byref(t)))
         return {"light_max_wedges": t.light_max_wedges, "dense_min_ratio": t.dense_min_ratio,
                 "window_mode": t.window_mode, "hash_window_wedges": t.hash_window_wedges,
-                "dense_block": t.dense_block, "dense_min_wedges": t.dense_min_wedges}
+                "dense_block": t.dense_block, "dense_min_wedges": t.dense_min_wedges,
+                "medium_max_wedges": t.medium_max_wedges}
 
     def schedule_info(self) -> dict:
         si = ScheduleInfo()

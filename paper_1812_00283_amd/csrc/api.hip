@@ -362,7 +362,9 @@ bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t) {
     if (t->hash_window_wedges > 0) nt.hash_window_wedges = t->hash_window_wedges;
     if (t->dense_block >= 0) nt.dense_block = t->dense_block;
     if (t->dense_min_wedges > 0) nt.dense_min_wedges = t->dense_min_wedges;
-    const bool resched = nt.light_max_wedges != h->tune.light_max_wedges || nt.dense_block != h->tune.dense_block;
+    if (t->medium_max_wedges >= 0) nt.medium_max_wedges = t->medium_max_wedges;
+    const bool resched = nt.light_max_wedges != h->tune.light_max_wedges || nt.dense_block != h->tune.dense_block ||
+                         nt.medium_max_wedges != h->tune.medium_max_wedges;
     h->tune = nt;
     if (resched) {
       if (h->used) BFC_HIP(hipEventSynchronize(h->done));
@@ -387,6 +389,7 @@ bfc_status bfc_get_schedule_info(bfc_graph g, bfc_schedule_info* out) {
     out->middles_light = sc.middles_light;
     out->middles_heavy = sc.middles_heavy;
     out->max_start_wedges = sc.max_start_wedges;
+    out->starts_medium = sc.n_medium;
   });
 }
 
@@ -426,6 +429,7 @@ bfc_status bfc_get_tuning(bfc_graph g, bfc_tuning* t) {
     t->hash_window_wedges = h->tune.hash_window_wedges;
     t->dense_block = h->tune.dense_block;
     t->dense_min_wedges = h->tune.dense_min_wedges;
+    t->medium_max_wedges = h->tune.medium_max_wedges;
   });
 }
 

@@ -576,20 +576,33 @@ __global__ __launch_bounds__(kClassifyNT) void classify_kernel(const int64_t* __
   }
 }
 
+// Light and heavy lists.  A heavy start is medium (256-thread workgroup)
+// when it has at most medium_max wedges and kMediumMaxPre middles and lies
+// outside the dense block; the key orders big starts first, each class by
+// decreasing work.  n_medium counts the medium starts.
 __global__ void compact_kernel(const int32_t* __restrict__ is_light, const int32_t* __restrict__ is_heavy,
                                const int32_t* __restrict__ pos_light, const int32_t* __restrict__ pos_heavy,
                                int32_t n0, int32_t n1, const int64_t* __restrict__ work0,
-                               const int64_t* __restrict__ work1, int32_t* __restrict__ light,
-                               int32_t* __restrict__ heavy, uint32_t* __restrict__ heavy_key) {
+                               const int64_t* __restrict__ work1, const int32_t* __restrict__ lo0,
+                               const int32_t* __restrict__ lo1, int64_t medium_max, int32_t KU, int32_t KL,
+                               int32_t* __restrict__ light, int32_t* __restrict__ heavy,
+                               uint32_t* __restrict__ heavy_key, unsigned long long* __restrict__ n_medium) {
   const int64_t n = (int64_t)n0 + n1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t code = i < n0 ? (int32_t)i : (int32_t)((1u << 30) | (uint32_t)(i - n0));
     if (is_light[i]) light[pos_light[i]] = code;
+    bool med = false;
     if (is_heavy[i]) {
       const int64_t w = i < n0 ? work0[i] : work1[i - n0];
+      const int32_t pre = i < n0 ? lo0[i] : lo1[i - n0];
+      const bool in_block = i < n0 ? i > (int64_t)n0 - KU : (i - n0) > (int64_t)n1 - KL;
+      med = medium_max > 0 && w <= medium_max && pre <= kMediumMaxPre && !in_block;
+      const uint32_t wc = w < 0x7FFFFFFF ? (uint32_t)w : 0x7FFFFFFFu;
       heavy[pos_heavy[i]] = code;
-      heavy_key[pos_heavy[i]] = 0xFFFFFFFFu - (uint32_t)w;  // ascending key = descending work
+      heavy_key[pos_heavy[i]] = (med ? 0x80000000u : 0u) | (0x7FFFFFFFu - wc);  // ascending = big first, less work later
     }
+    const uint64_t mb = __ballot(med);
+    if (__lane_id() == 0 && mb) atomicAdd(n_medium, (unsigned long long)__popcll(mb));
   }
 }
 
@@ -645,15 +658,21 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   if (n > 0) {
     compact_kernel<<<grid_1d(n), 256, 0, s>>>(flags_l.as<int32_t>(), flags_h.as<int32_t>(), pos_l.as<int32_t>(),
                                                pos_h.as<int32_t>(), n0, n1, g->side[0].work.as<int64_t>(),
-                                               g->side[1].work.as<int64_t>(), sc.light.as<int32_t>(),
-                                               sc.heavy.as<int32_t>(), hkey.as<uint32_t>());
+                                               g->side[1].work.as<int64_t>(), g->side[0].lo.as<int32_t>(),
+                                               g->side[1].lo.as<int32_t>(), (int64_t)g->tune.medium_max_wedges, KU,
+                                               KL, sc.light.as<int32_t>(), sc.heavy.as<int32_t>(),
+                                               hkey.as<uint32_t>(), sums.as<unsigned long long>() + 7);
     BFC_LAUNCH_CHECK();
   }
   if (sc.n_heavy > 1) {
     radix_sort_u32(hkey.as<uint32_t>(), sc.heavy.as<uint32_t>(), hkey_tmp.as<uint32_t>(), hval_tmp.as<uint32_t>(),
                    sc.n_heavy, 32, s);
   }
+  int64_t n_medium = 0;
+  BFC_HIP(hipMemcpyAsync(&n_medium, sums.as<int64_t>() + 7, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
+  sc.n_medium = (int32_t)n_medium;
+  sc.medium_max = g->tune.medium_max_wedges;
 }
 
 // ---------------------------------------------------------------- batches

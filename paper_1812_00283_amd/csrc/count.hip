@@ -345,11 +345,16 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
 }
 
 // ------------------------------------------------------------ heavy
-constexpr int kHeavyNT = 1024;
-constexpr int kHeavyWaves = kHeavyNT / 64;
-constexpr int kTableWords = 32768;          // 128 KB of LDS
-constexpr int kHashCap = kTableWords / 2;   // keys | counts
-constexpr int kHashSingleMax = 8192;        // one hash window suffices below this many wedges
+// Workgroup shapes of the heavy kernel: big starts take 1024 threads and a
+// 128 KB LDS table; medium starts (few wedges and at most kMedPre middles)
+// take 256 threads and a 32 KB table, four workgroups to a CU, so their
+// per-window barriers and scans occupy a quarter of the wavefronts.
+constexpr int kBigNT = 1024;
+constexpr int kBigWords = 32768;
+constexpr int kMedNT = 256;
+constexpr int kMedWords = 8192;
+constexpr int kMedPre = kMediumMaxPre;  // = 2 * kMedNT: medium starts keep their middles resident
+static_assert(kMedPre == 2 * kMedNT, "medium starts must fit the resident mode");
 constexpr int32_t kNone = 0x7FFFFFFF;       // "no further end" in a middle's cursor
 
 // Inserts end w into the workgroup hash table (count 1, or bumps its count).
@@ -550,22 +555,24 @@ __device__ __forceinline__ void chunk_walk(const int32_t* __restrict__ oadj, con
   }
 }
 
-// Segment list capacities: pass 1 keeps (se, sd); pass 2 also keeps the
-// middle index and a 64-bit delta sum per segment.
-constexpr int kSeg1 = 2048;
-constexpr int kSeg2 = 1024;
-constexpr int kSegWords = 5124;  // max(2 * kSeg1 + 1, 3 * kSeg2 + 2 + 2 * kSeg2), rounded up
 // A dense window of a total count whose wedges fit one batch and number
 // fewer than this is finalized by walking its wedges again (each end's
 // counter read and cleared once) instead of scanning every counter.
 constexpr int32_t kRewalkMax = 8192;
 
-// One instantiation per count mode: the total count carries no second pass.
-template <int kMode>
-__global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
-  __shared__ __align__(16) int32_t table[kTableWords];
-  __shared__ __align__(16) int32_t segbuf[kSegWords];
-  __shared__ unsigned long long s_red64[kHeavyWaves + 1];
+// One instantiation per count mode (the total count carries no second pass)
+// and per workgroup shape: kNT threads and an LDS table of kWords words.
+template <int kMode, int kNT, int kWords>
+__global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
+  constexpr int kWaves = kNT / 64;
+  constexpr int kCap = kWords / 2;          // hash entries (keys | counts)
+  constexpr int kSingleMax = kCap / 2;      // one hash window suffices below this many wedges
+  constexpr int kS1 = 2 * kNT;              // segment list capacity, pass 1 (and resident middles)
+  constexpr int kS2 = kNT;                  // segment list capacity, pass 2
+  constexpr int kSW = ((2 * kS1 + 1 > 5 * kS2 + 2 ? 2 * kS1 + 1 : 5 * kS2 + 2) + 3) / 4 * 4;
+  __shared__ __align__(16) int32_t table[kWords];
+  __shared__ __align__(16) int32_t segbuf[kSW];
+  __shared__ unsigned long long s_red64[kWaves + 1];
   __shared__ int32_t s_idx, s_fill, s_over, s_cut_j, s_cut_lex;
   __shared__ int32_t s_ticket;  // chunk ticket of the dense walk
   __shared__ unsigned long long s_emit;  // resident emission: count << 32 | total length
@@ -579,7 +586,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
   int32_t* pos = p.cursor + (int64_t)blockIdx.x * 3 * p.cursor_stride;
   int32_t* nxt = pos + p.cursor_stride;
   int32_t* cend = nxt + p.cursor_stride;
-  for (int i = t; i < kTableWords; i += kHeavyNT) table[i] = 0;
+  for (int i = t; i < kWords; i += kNT) table[i] = 0;
   unsigned long long acc_total = 0;
 
   for (;;) {
@@ -619,9 +626,9 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
     const int32_t sparse_end = in_block ? top : range;
     // Windows: hash windows over [0, hash_end) (width hwidth, adapted as they
     // go), then dense windows of `width` ranks up to sparse_end.
-    int32_t width = half ? 2 * kTableWords : kTableWords;
+    int32_t width = half ? 2 * kWords : kWords;
     int32_t hwidth = 0, hash_end = 0;
-    uint32_t cap = kHashCap;
+    uint32_t cap = kCap;
     if (dense) {
       const int32_t base_lo = S.off[rlo];
       hash_end = rlo;
@@ -635,7 +642,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         // hash_window_wedges of them (one 64-lane probe of off_X); a wrong
         // guess costs time only (an overfull hash window is split).
         const int32_t step0 = (sparse_end - rlo + 63) / 64;
-        const int32_t step = (step0 + 2 * kTableWords - 1) / (2 * kTableWords) * (2 * kTableWords);
+        const int32_t step = (step0 + 2 * kWords - 1) / (2 * kWords) * (2 * kWords);
         const int64_t xl = rlo + (int64_t)(lane + 1) * step;
         const bool ok = xl < sparse_end && (double)W * (double)(S.off[xl] - base_lo) <=
                                                (double)p.hash_window_wedges * (double)(base - base_lo);
@@ -644,7 +651,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       }
     } else {
       hash_end = sparse_end;
-      if (W <= kHashSingleMax) {
+      if (W <= kSingleMax) {
         hwidth = span;
         cap = 512;
         while ((int64_t)cap < 2 * W) cap <<= 1;
@@ -666,7 +673,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
     // one window over [0, range) needs no cursors; otherwise every middle
     // below tfirst keeps its next slot and next end id in scratch
     auto init_cursors = [&] {
-      for (int32_t j = t; j < pre; j += kHeavyNT) {
+      for (int32_t j = t; j < pre; j += kNT) {
         const int32_t k = base + j;
         const int32_t v = S.adj[k];
         if (v >= tfirst) continue;
@@ -676,13 +683,13 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       }
     };
     bool cursors = !(sparse_end == range && (hash_end >= range ? hwidth >= span : (hash_end == rlo && width >= span)));
-    // Resident mode: a multi-window start with at most 2 * kHeavyNT middles
+    // Resident mode: a multi-window start with at most 2 * kNT middles
     // keeps middle 2t + h's slice state in thread t's registers: the end of
     // its list below r (re), the start of its current slice (rcs), and raux
     // = the middle's table row offset (>= 0) or -1 - (end id at rcs).  A
     // window's slice ends (rce, and rnv = end id there) are computed from
     // these, and committed once the window is final.
-    const bool resident = cursors && pre <= 2 * kHeavyNT;
+    const bool resident = cursors && pre <= 2 * kNT;
     int32_t re[2], rcs[2], raux[2], rce[2], rnv[2];
     if (resident) {
 #pragma unroll
@@ -723,7 +730,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       const int32_t pre1 = seeded ? pre_out : pre;
       if (seeded) {
         const int32_t* crow = (x ? p.dC[1] : p.dC[0]) + (int64_t)(r - top) * (x ? p.dld[1] : p.dld[0]);
-        for (int32_t i = t; i < range - top; i += kHeavyNT) table[i] = crow[i];
+        for (int32_t i = t; i < range - top; i += kNT) table[i] = crow[i];
       }
       // cursors advance during pass 1 only for dense windows of a total count
       // (a hash window may have to be redone; pass 2 needs the old cursors)
@@ -731,7 +738,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
 
       // Fills the segment list with the non-empty slices [cs, ce) of window
       // [lo_w, hi_w) of middles rj, rj+1, ... < npre, up to `segcap` of
-      // them, 2 * kHeavyNT middles per sweep in middle order (one packed
+      // them, 2 * kNT middles per sweep in middle order (one packed
       // workgroup scan of (active, length)).  Leaves rj at the first middle
       // not taken and returns the segment count and total length; the cursors
       // of taken middles advance (or record the window end, cend) here.
@@ -785,7 +792,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
           const unsigned long long packed =
               ((unsigned long long)((int)actv[0] + (int)actv[1]) << 32) | (uint32_t)(l0 + l1);
           unsigned long long tot;
-          const unsigned long long ex = block_exclusive_scan<unsigned long long, kHeavyNT>(packed, s_red64, &tot);
+          const unsigned long long ex = block_exclusive_scan<unsigned long long, kNT>(packed, s_red64, &tot);
           const int32_t room = segcap - nseg;
           const int32_t nact = (int32_t)(tot >> 32);
           int32_t ia = (int32_t)(ex >> 32);
@@ -819,7 +826,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
           if (nact <= room) {
             nseg += nact;
             T += (int32_t)(uint32_t)tot;
-            rj = npre - rj > 2 * kHeavyNT ? rj + 2 * kHeavyNT : npre;
+            rj = npre - rj > 2 * kNT ? rj + 2 * kNT : npre;
           } else {
             __syncthreads();
             rj = s_cut_j;
@@ -832,8 +839,8 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       };
       // this wavefront's share of the batch's positions
       auto share = [&](int32_t T, int32_t& F0, int32_t& F1) {
-        F0 = (int32_t)((int64_t)T * wv / kHeavyWaves);
-        F1 = (int32_t)((int64_t)T * (wv + 1) / kHeavyWaves);
+        F0 = (int32_t)((int64_t)T * wv / kWaves);
+        F1 = (int32_t)((int64_t)T * (wv + 1) / kWaves);
       };
 
       // Resident mode: slice ends of window [lo_w, hi_w) for the thread's middles.
@@ -879,7 +886,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         const unsigned long long packed =
             ((unsigned long long)((int)actv[0] + (int)actv[1]) << 32) | (uint32_t)(len[0] + len[1]);
         unsigned long long tot;
-        const unsigned long long ex = block_exclusive_scan<unsigned long long, kHeavyNT>(packed, s_red64, &tot);
+        const unsigned long long ex = block_exclusive_scan<unsigned long long, kNT>(packed, s_red64, &tot);
         nact = (int32_t)(tot >> 32);
         int32_t ia = (int32_t)(ex >> 32);
         int32_t lex = (int32_t)(uint32_t)ex;
@@ -937,7 +944,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         if (t == 0) { s_fill = 0; s_over = 0; s_emit = 0ull; }
         __syncthreads();
         int32_t* se = segbuf;
-        int32_t* sd = segbuf + kSeg1 + 1;
+        int32_t* sd = segbuf + kS1 + 1;
         int32_t rj = 0;
         bool over = false;
         batches = 0;
@@ -980,9 +987,9 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
               }
               __syncthreads();
             }
-            rj = pre1;  // one batch holds every slice (pre <= kSeg1)
+            rj = pre1;  // one batch holds every slice (pre <= kS1)
           } else {
-            fill(pre1, kSeg1, false, se, sd, nullptr, nullptr, rj, nseg, T);
+            fill(pre1, kS1, false, se, sd, nullptr, nullptr, rj, nseg, T);
           }
           ++batches;
           last_n = nseg;
@@ -1020,7 +1027,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         // the window holds too many distinct ends for the table: halve it and
         // redo.  A start walked without cursors (one window over its whole
         // end range) switches to cursors first, so the smaller window applies.
-        for (int i = t; i < (int)(2 * cap); i += kHeavyNT) table[i] = 0;
+        for (int i = t; i < (int)(2 * cap); i += kNT) table[i] = 0;
         if (!cursors) {
           init_cursors();
           cursors = true;
@@ -1041,19 +1048,19 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         unsigned long long* acc_o = pick_ptr(p.acc, 1 - x);
         unsigned long long* vmid = pick_ptr(p.vout, 1 - x);
         int32_t* se = segbuf;
-        int32_t* sd = segbuf + kSeg2 + 1;
-        int32_t* sj = sd + kSeg2;
-        unsigned long long* sdel = reinterpret_cast<unsigned long long*>(segbuf + 3 * kSeg2 + 2);
+        int32_t* sd = segbuf + kS2 + 1;
+        int32_t* sj = sd + kS2;
+        unsigned long long* sdel = reinterpret_cast<unsigned long long*>(segbuf + 3 * kS2 + 2);
         int32_t rj = 0, b0 = 0;
         while (rj < pre) {
           int32_t nseg, T;
           if (resident) {
             int32_t nact;
-            res_emit(pre, b0, kSeg2, true, se, sd, sj, sdel, nseg, T, nact);
-            b0 += kSeg2;
+            res_emit(pre, b0, kS2, true, se, sd, sj, sdel, nseg, T, nact);
+            b0 += kS2;
             if (b0 >= nact) rj = pre;
           } else {
-            fill(pre, kSeg2, true, se, sd, sj, sdel, rj, nseg, T);
+            fill(pre, kS2, true, se, sd, sj, sdel, rj, nseg, T);
           }
           int32_t F0, F1;
           share(T, F0, F1);
@@ -1079,7 +1086,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
                    [] { return false; });
           if (run) atomicAdd(&sdel[cur], run);
           __syncthreads();
-          for (int32_t i = t; i < nseg; i += kHeavyNT) {
+          for (int32_t i = t; i < nseg; i += kNT) {
             const unsigned long long d = sdel[i];
             if (d) {
               const int32_t k = base + sj[i];
@@ -1091,7 +1098,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         }
       } else if (cursors && !advance_now && !resident) {
         // hash window of a total count: advance the cursors now that the window is final
-        for (int32_t j = t; j < pre1; j += kHeavyNT) {
+        for (int32_t j = t; j < pre1; j += kNT) {
           if (S.adj[base + j] < tfirst && nxt[j] < hi_w) {
             const int32_t ce = cend[j];
             pos[j] = ce;
@@ -1106,7 +1113,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         // the window's segment list is still in LDS: visit its wedges again
         int32_t F0, F1;
         share(last_t, F0, F1);
-        seg_walk(O.adj, segbuf, segbuf + kSeg1 + 1, last_n, F0, F1,
+        seg_walk(O.adj, segbuf, segbuf + kS1 + 1, last_n, F0, F1,
                  [&](int32_t, int32_t, int32_t w) {
                    const int32_t i = w - lo_w;
                    int32_t c;
@@ -1125,7 +1132,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
         const int32_t words = whalf ? (wn + 1) >> 1 : wn;
         const int32_t quads = (words + 3) >> 2;
         uint4* t4 = reinterpret_cast<uint4*>(table);
-        for (int32_t i4 = t; i4 < quads; i4 += kHeavyNT) {
+        for (int32_t i4 = t; i4 < quads; i4 += kNT) {
           const uint4 q4 = t4[i4];
           if ((q4.x | q4.y | q4.z | q4.w) == 0u) continue;
           const uint32_t wd[4] = {q4.x, q4.y, q4.z, q4.w};
@@ -1155,7 +1162,7 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
           t4[i4] = make_uint4(0u, 0u, 0u, 0u);
         }
       } else {
-        for (uint32_t h = t; h < cap; h += kHeavyNT) {
+        for (uint32_t h = t; h < cap; h += kNT) {
           const int32_t key = table[h];
           if (key) {
             const int32_t c = table[cap + h];
@@ -1181,17 +1188,17 @@ __global__ __launch_bounds__(kHeavyNT) void heavy_kernel(CountParams p) {
       lo_w = hi_w;
     }
     if (mode == kVertex) {
-      const unsigned long long sa = block_sum<unsigned long long, kHeavyNT>(start_acc, s_red64);
+      const unsigned long long sa = block_sum<unsigned long long, kNT>(start_acc, s_red64);
       if (t == 0 && sa) atomicAdd(&pick_ptr(p.vout, x)[S.id_of[r]], sa);
     } else if (mode == kTotal && p.gtotal) {
-      const unsigned long long sa = block_sum<unsigned long long, kHeavyNT>(start_acc, s_red64);
+      const unsigned long long sa = block_sum<unsigned long long, kNT>(start_acc, s_red64);
       if (t == 0 && sa) atomicAdd(&p.gtotal[graph_index(p, x, r)], sa);
     } else {
       acc_total += start_acc;
     }
   }
   if (mode == kTotal && p.total) {
-    const unsigned long long s = block_sum<unsigned long long, kHeavyNT>(acc_total, s_red64);
+    const unsigned long long s = block_sum<unsigned long long, kNT>(acc_total, s_red64);
     if (t == 0 && s) atomicAdd(p.total, s);
   }
 }
@@ -1218,12 +1225,25 @@ int num_cus() {
 
 namespace {
 
-int heavy_grid_for(const bfc_graph_s* g) {
+// workgroups of the big and medium heavy launches
+int big_grid_for(const bfc_graph_s* g) {
   const int cus = num_cus();
-  return g->sched.n_heavy < cus ? g->sched.n_heavy : cus;
+  const int n = g->sched.n_heavy - g->sched.n_medium;
+  return n < cus ? n : cus;
+}
+int med_grid_for(const bfc_graph_s* g) {
+  const int w = 4 * num_cus();
+  return g->sched.n_medium < w ? g->sched.n_medium : w;
 }
 
 int64_t cursor_stride_for(const bfc_graph_s* g) { return ((int64_t)g->sched.max_prefix + 63) / 64 * 64; }
+
+// scratch: three cursor arrays per big workgroup, three per medium workgroup
+// (stride kMedPre), then 256 bytes: the two tickets and the status word
+size_t big_cursor_bytes(const bfc_graph_s* g) {
+  return (size_t)big_grid_for(g) * 3 * (size_t)cursor_stride_for(g) * sizeof(int32_t);
+}
+size_t med_cursor_bytes(const bfc_graph_s* g) { return (size_t)med_grid_for(g) * 3 * kMedPre * sizeof(int32_t); }
 
 __global__ void fill_zero_kernel(unsigned long long* __restrict__ p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -1246,8 +1266,7 @@ int32_t* count_status(bfc_graph_s* g) {
 
 void prepare_count(bfc_graph_s* g, hipStream_t s) {
   prepare_dense(g, s);
-  // three cursor arrays per heavy workgroup, then 256 bytes for the ticket
-  const size_t need = (size_t)heavy_grid_for(g) * 3 * (size_t)cursor_stride_for(g) * sizeof(int32_t) + 256;
+  const size_t need = big_cursor_bytes(g) + med_cursor_bytes(g) + 256;
   if (g->scratch_bytes < need) {
     g->scratch.alloc(need, s);
     g->scratch_bytes = need;
@@ -1258,9 +1277,12 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
            int64_t* gtotals) {
   const Schedule& sc = g->sched;
   const int cus = num_cus();
-  const int heavy_grid = heavy_grid_for(g);
+  const int big_grid = big_grid_for(g);
+  const int med_grid = med_grid_for(g);
   const int64_t stride = cursor_stride_for(g);
   int32_t* cursor = g->scratch.as<int32_t>();
+  int32_t* med_cursor = reinterpret_cast<int32_t*>(g->scratch.as<char>() + big_cursor_bytes(g));
+  // tickets: [0] big heavy starts, [1] medium heavy starts
   unsigned int* ticket = reinterpret_cast<unsigned int*>(g->scratch.as<char>() + g->scratch_bytes - 256);
   int32_t* status = reinterpret_cast<int32_t*>(g->scratch.as<char>() + g->scratch_bytes - 128);
 
@@ -1320,7 +1342,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     p.dld[0] = d.PU;
     p.dld[1] = d.PL;
   }
-  zero_u64(ticket, 1, s);      // ticket (4 bytes) and padding
+  zero_u64(ticket, 1, s);      // both tickets
   zero_u64(status, 1, s);
   // events: [0] dense block [1] light [2] heavy [3] fold [4]
   bfc_graph_s::TimedCall tc{};
@@ -1339,12 +1361,25 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     BFC_LAUNCH_CHECK();
   }
   if (g->timing) BFC_HIP(hipEventRecord(tc.ev[2], s));
-  if (sc.n_heavy > 0) {
+  // the heavy list holds the big starts (decreasing work), then the medium ones
+  const int32_t n_big = sc.n_heavy - sc.n_medium;
+  if (n_big > 0) {
     p.list = g->sched.heavy.as<int32_t>();
-    p.n_list = sc.n_heavy;
-    if (mode == kTotal) heavy_kernel<kTotal><<<(unsigned)heavy_grid, kHeavyNT, 0, s>>>(p);
-    else if (mode == kVertex) heavy_kernel<kVertex><<<(unsigned)heavy_grid, kHeavyNT, 0, s>>>(p);
-    else heavy_kernel<kEdge><<<(unsigned)heavy_grid, kHeavyNT, 0, s>>>(p);
+    p.n_list = n_big;
+    if (mode == kTotal) heavy_kernel<kTotal, kBigNT, kBigWords><<<(unsigned)big_grid, kBigNT, 0, s>>>(p);
+    else if (mode == kVertex) heavy_kernel<kVertex, kBigNT, kBigWords><<<(unsigned)big_grid, kBigNT, 0, s>>>(p);
+    else heavy_kernel<kEdge, kBigNT, kBigWords><<<(unsigned)big_grid, kBigNT, 0, s>>>(p);
+    BFC_LAUNCH_CHECK();
+  }
+  if (sc.n_medium > 0) {
+    p.list = g->sched.heavy.as<int32_t>() + n_big;
+    p.n_list = sc.n_medium;
+    p.ticket = ticket + 1;
+    p.cursor = med_cursor;
+    p.cursor_stride = kMedPre;
+    if (mode == kTotal) heavy_kernel<kTotal, kMedNT, kMedWords><<<(unsigned)med_grid, kMedNT, 0, s>>>(p);
+    else if (mode == kVertex) heavy_kernel<kVertex, kMedNT, kMedWords><<<(unsigned)med_grid, kMedNT, 0, s>>>(p);
+    else heavy_kernel<kEdge, kMedNT, kMedWords><<<(unsigned)med_grid, kMedNT, 0, s>>>(p);
     BFC_LAUNCH_CHECK();
   }
   if (g->timing) BFC_HIP(hipEventRecord(tc.ev[3], s));

@@ -16,6 +16,8 @@ constexpr int kWave = 64;
 // Window-boundary tables: entries every 2^kWinShift end ranks, rows for the
 // middles of degree >= max(2 x row length, kWinMinDegree).
 constexpr int kWinShift = 15;
+// Medium heavy starts (256-thread workgroups) have at most this many middles.
+constexpr int32_t kMediumMaxPre = 512;
 constexpr int32_t kWinMinDegree = 64;
 
 // ------------------------------------------------------------ errors
@@ -113,6 +115,7 @@ struct Side {
 struct Schedule {
   int32_t n_light = 0;   // starts counted by one wavefront
   int32_t n_heavy = 0;   // starts counted by one workgroup
+  int32_t n_medium = 0;  // of those, the last n_medium use the 256-thread shape
   DevBuf light;          // int32 codes (side << 30 | rank)
   DevBuf heavy;          // int32 codes, by decreasing work
   int64_t wedges = 0;    // |W|
@@ -120,7 +123,8 @@ struct Schedule {
   int64_t wedges_light = 0, wedges_heavy = 0;
   int64_t middles_light = 0, middles_heavy = 0;
   int64_t max_start_wedges = 0;
-  int32_t light_max = 0; // threshold the lists were built with
+  int32_t light_max = 0; // thresholds the lists were built with
+  int32_t medium_max = 0;
 };
 
 struct Tuning {
@@ -130,6 +134,7 @@ struct Tuning {
   int32_t hash_window_wedges = 8192;
   int32_t dense_block = 0;
   int32_t dense_min_wedges = 8192;
+  int32_t medium_max_wedges = 0;  // 256-thread workgroups measured slower on the degree-skewed workloads
 };
 
 // Dense block of top-priority vertices (int8 MFMA, see dense.hip).

@@ -108,6 +108,13 @@ TUNINGS = {
     # sized for far too many wedges (split by halving), and small prefixes
     "auto-prefix-overfull": {"light_max_wedges": 64, "hash_window_wedges": 1 << 30},
     "auto-prefix-small": {"light_max_wedges": 64, "dense_min_wedges": 256, "hash_window_wedges": 2048},
+    # 256-thread workgroups for small workgroup starts: off, hash windows,
+    # tiny (halving) hash windows, and next to the dense block
+    "medium-off": {"medium_max_wedges": 0},
+    "medium-hash": {"light_max_wedges": 16, "window_mode": 3, "medium_max_wedges": 1 << 30},
+    "medium-hash-tiny": {"light_max_wedges": 1, "window_mode": 3, "hash_window_wedges": 32,
+                         "medium_max_wedges": 1 << 30},
+    "medium-dense-block": {"light_max_wedges": 64, "dense_block": 1024, "medium_max_wedges": 1 << 30},
 }
 
 
