@@ -397,6 +397,41 @@ __device__ __forceinline__ int32_t dense_get(const int32_t* table, int32_t i, bo
   return table[i];
 }
 
+// Packed hash entries, for starts whose counts fit kPackBits bits (fewer
+// middles than 2^kPackBits) in windows narrower than kPackMaxWidth ranks:
+// one 32-bit word holds (end - lo_w + 1) << kPackBits | count, so the LDS
+// table holds twice as many entries.  Same probing and overflow rules as
+// block_hash_add.
+constexpr int kPackBits = 12;
+constexpr uint32_t kPackMask = (1u << kPackBits) - 1u;
+constexpr int32_t kPackMaxPre = 1 << kPackBits;
+constexpr int32_t kPackMaxWidth = (1 << (32 - kPackBits)) - 1;
+
+__device__ __forceinline__ int packed_hash_add(uint32_t* tab, uint32_t cap, uint32_t key, int32_t* s_over) {
+  if (*(volatile int32_t*)s_over) return 0;
+  const uint32_t mask = cap - 1;
+  uint32_t h = mix32(key) & mask;
+  for (uint32_t probe = 0; probe < kMaxProbe; ++probe) {
+    const uint32_t cur = tab[h];
+    if ((cur >> kPackBits) == key) { atomicAdd(&tab[h], 1u); return 0; }
+    if (cur == 0) {
+      const uint32_t old = atomicCAS(&tab[h], 0u, (key << kPackBits) | 1u);
+      if (old == 0) return 1;
+      if ((old >> kPackBits) == key) { atomicAdd(&tab[h], 1u); return 0; }
+    }
+    h = (h + 1) & mask;
+  }
+  *s_over = 1;
+  return 0;
+}
+
+__device__ __forceinline__ int32_t packed_hash_get(const uint32_t* tab, uint32_t mask, uint32_t key) {
+  uint32_t h = mix32(key) & mask;
+  while ((tab[h] >> kPackBits) != key) h = (h + 1) & mask;
+  return (int32_t)(tab[h] & kPackMask);
+}
+
+
 // ------------------------------------------------------------ flattened walk
 // A batch of (middle, window) slices is held in LDS as a segment list:
 // se[i] = exclusive prefix of the slice lengths (strictly increasing, every
@@ -615,8 +650,15 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     const int32_t* tab = x ? p.wt[0] : p.wt[1];
     const int32_t tfirst = tab ? (x ? p.wt_first[0] : p.wt_first[1]) : 0x7FFFFFFF;
     const int32_t trow = x ? p.wt_row[0] : p.wt_row[1];
-    const bool dense = p.window_mode == 2 || (p.window_mode == 1 && (W > p.dense_min_wedges ||
-                                                                     W * (int64_t)p.dense_ratio >= (int64_t)span));
+    // A start whose counts fit kPackBits bits packs each hash entry into one
+    // word, so one hash window over its whole end range holds up to 5/8 of
+    // the table's words in distinct ends.
+    const bool packable = pre < kPackMaxPre && span < kPackMaxWidth;
+    const int64_t psingle = (int64_t)kWords / 8 * 5;
+    const bool dense =
+        p.window_mode == 2 ||
+        (p.window_mode == 1 && ((W > p.dense_min_wedges && !(packable && W <= psingle)) ||
+                                W * (int64_t)p.dense_ratio >= (int64_t)span));
     const bool half = pre < 65536;
     // Starts in the dense block: the last window covers the block's end ranks
     // [top, r); its counters start from the MFMA products and its first pass
@@ -651,13 +693,15 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
       }
     } else {
       hash_end = sparse_end;
-      if (W <= kSingleMax) {
+      const uint32_t cmax = packable ? (uint32_t)kWords : (uint32_t)kCap;
+      if (W <= (packable ? psingle : (int64_t)kSingleMax)) {
         hwidth = span;
         cap = 512;
-        while ((int64_t)cap < 2 * W) cap <<= 1;
+        while (cap < cmax && (int64_t)cap < 2 * W) cap <<= 1;
       } else {
         const int64_t wd = (int64_t)span * p.hash_window_wedges / W;
         hwidth = (int32_t)(wd < 256 ? 256 : (wd > span ? span : wd));
+        cap = cmax;
       }
     }
     int32_t pre_out = pre;
@@ -728,6 +772,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         break;
       }
       const int32_t pre1 = seeded ? pre_out : pre;
+      const bool wpacked = !wdense && packable;  // hash entries of this window: key | count words
       if (seeded) {
         const int32_t* crow = (x ? p.dC[1] : p.dC[0]) + (int64_t)(r - top) * (x ? p.dld[1] : p.dld[0]);
         for (int32_t i = t; i < range - top; i += kNT) table[i] = crow[i];
@@ -1008,14 +1053,25 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
                      [] { return false; });
           } else {
             int32_t fresh = 0;
-            seg_walk(O.adj, se, sd, nseg, F0, F1,
-                     [&](int32_t, int32_t, int32_t w) { fresh += block_hash_add(table, cap, w, &s_over); },
-                     [&] {
-                       const int32_t fw = wave_sum(fresh);
-                       fresh = 0;
-                       if (lane == 0 && fw && atomicAdd(&s_fill, fw) + fw > (int32_t)(cap / 8 * 5)) s_over = 1;
-                       return __builtin_amdgcn_readfirstlane(*(volatile int32_t*)&s_over) != 0;
-                     });
+            auto poll = [&] {
+              const int32_t fw = wave_sum(fresh);
+              fresh = 0;
+              if (lane == 0 && fw && atomicAdd(&s_fill, fw) + fw > (int32_t)(cap / 8 * 5)) s_over = 1;
+              return __builtin_amdgcn_readfirstlane(*(volatile int32_t*)&s_over) != 0;
+            };
+            if (wpacked) {
+              uint32_t* pt = reinterpret_cast<uint32_t*>(table);
+              const int32_t kb = lo_w - 1;  // key = end - lo_w + 1
+              seg_walk(O.adj, se, sd, nseg, F0, F1,
+                       [&](int32_t, int32_t, int32_t w) {
+                         fresh += packed_hash_add(pt, cap, (uint32_t)(w - kb), &s_over);
+                       },
+                       poll);
+            } else {
+              seg_walk(O.adj, se, sd, nseg, F0, F1,
+                       [&](int32_t, int32_t, int32_t w) { fresh += block_hash_add(table, cap, w, &s_over); }, poll);
+            }
+            poll();  // the walk does not poll after its last iteration
           }
           __syncthreads();
           if (!wdense && s_over) {
@@ -1027,7 +1083,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         // the window holds too many distinct ends for the table: halve it and
         // redo.  A start walked without cursors (one window over its whole
         // end range) switches to cursors first, so the smaller window applies.
-        for (int i = t; i < (int)(2 * cap); i += kNT) table[i] = 0;
+        for (int i = t; i < (int)(wpacked ? cap : 2 * cap); i += kNT) table[i] = 0;
         if (!cursors) {
           init_cursors();
           cursors = true;
@@ -1070,8 +1126,11 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
           unsigned long long run = 0;
           seg_walk(O.adj, se, sd, nseg, F0, F1,
                    [&](int32_t sg, int32_t slot, int32_t w) {
-                     const int32_t c = wdense ? dense_get(table, w - lo_w, whalf)
-                                              : hash_get(table, table + cap, cap - 1, w);
+                     const int32_t c =
+                         wdense ? dense_get(table, w - lo_w, whalf)
+                                : (wpacked ? packed_hash_get(reinterpret_cast<const uint32_t*>(table), cap - 1,
+                                                             (uint32_t)(w - lo_w + 1))
+                                           : hash_get(table, table + cap, cap - 1, w));
                      if (c > 1) {
                        const unsigned long long d = (unsigned long long)(c - 1);
                        if (mode == kEdge) atomicAdd(&acc_o[slot], d);
@@ -1160,6 +1219,20 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
             }
           }
           t4[i4] = make_uint4(0u, 0u, 0u, 0u);
+        }
+      } else if (wpacked) {
+        uint32_t* pt = reinterpret_cast<uint32_t*>(table);
+        for (uint32_t h = t; h < cap; h += kNT) {
+          const uint32_t word = pt[h];
+          if (word) {
+            const int32_t c = (int32_t)(word & kPackMask);
+            if (c > 1) {
+              const unsigned long long cc = choose2(c);
+              start_acc += cc;
+              if (mode == kVertex) atomicAdd(&vs[S.id_of[lo_w - 1 + (int32_t)(word >> kPackBits)]], cc);
+            }
+            pt[h] = 0u;
+          }
         }
       } else {
         for (uint32_t h = t; h < cap; h += kNT) {
