@@ -200,7 +200,8 @@ bfc_status bfc_get_tuning(bfc_graph g, bfc_tuning* t);
  *   wedges          |W|, the wedges Algorithm 2 processes (Theorem 2's measure)
  *   starts_*        start vertices handed to the wavefront (light) and
  *                   workgroup (heavy) kernels; starts_medium of the heavy
- *                   ones run on 256-thread workgroups
+ *                   ones run on 256-thread workgroups; starts_small of the
+ *                   light ones (at most 256 wedges) use the small-table kernel
  *   wedges_*        wedges those starts process
  *   middles_*       lower-priority neighbours (middle vertices) they walk
  *   max_start_wedges  the largest per-start wedge count
@@ -212,6 +213,7 @@ typedef struct {
   int64_t middles_light, middles_heavy;
   int64_t max_start_wedges;
   int64_t starts_medium;
+  int64_t starts_small;
 } bfc_schedule_info;
 
 bfc_status bfc_get_schedule_info(bfc_graph g, bfc_schedule_info* out);

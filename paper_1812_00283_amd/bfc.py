@@ -52,7 +52,7 @@ class Tuning(ctypes.Structure):
 class ScheduleInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("wedges", "starts_light", "starts_heavy", "wedges_light",
                                                "wedges_heavy", "middles_light", "middles_heavy",
-                                               "max_start_wedges", "starts_medium")]
+                                               "max_start_wedges", "starts_medium", "starts_small")]
 
 
 class KernelTimes(ctypes.Structure):

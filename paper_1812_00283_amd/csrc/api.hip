@@ -390,6 +390,7 @@ bfc_status bfc_get_schedule_info(bfc_graph g, bfc_schedule_info* out) {
     out->middles_heavy = sc.middles_heavy;
     out->max_start_wedges = sc.max_start_wedges;
     out->starts_medium = sc.n_medium;
+    out->starts_small = sc.n_small;
   });
 }
 

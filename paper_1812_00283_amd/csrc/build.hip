@@ -513,7 +513,7 @@ constexpr int kClassifyNT = 256;
 
 __global__ __launch_bounds__(kClassifyNT) void classify_kernel(const int64_t* __restrict__ work0, const int32_t* __restrict__ lo0, int32_t n0,
                                 const int64_t* __restrict__ work1, const int32_t* __restrict__ lo1, int32_t n1,
-                                int64_t light_max, int32_t KU, int32_t KL, int32_t* __restrict__ is_light,
+                                int64_t light_max, int32_t KU, int32_t KL, int64_t* __restrict__ is_light,
                                 int32_t* __restrict__ is_heavy, unsigned long long* __restrict__ sums) {
   const int64_t n = (int64_t)n0 + n1;
   unsigned long long s_all = 0, s_lw = 0, s_hw = 0, s_lm = 0, s_hm = 0, max_w = 0;
@@ -525,7 +525,8 @@ __global__ __launch_bounds__(kClassifyNT) void classify_kernel(const int64_t* __
     const bool heavy = w > light_max || (in_block && w >= 2);
     const bool light = w >= 2 && !heavy;
     s_all += (unsigned long long)w;
-    is_light[i] = light ? 1 : 0;
+    // light starts: small ones count in the low word, the others in the high word
+    is_light[i] = light ? (w <= kSmallMax ? 1ll : (1ll << 32)) : 0ll;
     is_heavy[i] = heavy ? 1 : 0;
     if (light) { s_lw += (unsigned long long)w; s_lm += (unsigned long long)pre; }
     if (heavy) {
@@ -580,17 +581,28 @@ __global__ __launch_bounds__(kClassifyNT) void classify_kernel(const int64_t* __
 // when it has at most medium_max wedges and kMediumMaxPre middles and lies
 // outside the dense block; the key orders big starts first, each class by
 // decreasing work.  n_medium counts the medium starts.
-__global__ void compact_kernel(const int32_t* __restrict__ is_light, const int32_t* __restrict__ is_heavy,
-                               const int32_t* __restrict__ pos_light, const int32_t* __restrict__ pos_heavy,
+__global__ void compact_kernel(const int64_t* __restrict__ is_light, const int32_t* __restrict__ is_heavy,
+                               const int64_t* __restrict__ pos_light, const int32_t* __restrict__ pos_heavy,
                                int32_t n0, int32_t n1, const int64_t* __restrict__ work0,
                                const int64_t* __restrict__ work1, const int32_t* __restrict__ lo0,
-                               const int32_t* __restrict__ lo1, int64_t medium_max, int32_t KU, int32_t KL,
-                               int32_t* __restrict__ light, int32_t* __restrict__ heavy,
+                               const int32_t* __restrict__ lo1, const int32_t* __restrict__ off0,
+                               const int32_t* __restrict__ off1, int64_t medium_max, int32_t KU, int32_t KL,
+                               int4* __restrict__ light, int32_t* __restrict__ heavy,
                                uint32_t* __restrict__ heavy_key, unsigned long long* __restrict__ n_medium) {
   const int64_t n = (int64_t)n0 + n1;
+  // the small light starts come first, then the other light starts
+  const int32_t n_small = (int32_t)(pos_light[n] & 0xFFFFFFFFll);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t code = i < n0 ? (int32_t)i : (int32_t)((1u << 30) | (uint32_t)(i - n0));
-    if (is_light[i]) light[pos_light[i]] = code;
+    const int64_t fl = is_light[i];
+    if (fl) {
+      const int64_t pl = pos_light[i];
+      const int32_t at = (fl & 0xFFFFFFFFll) ? (int32_t)(pl & 0xFFFFFFFFll) : n_small + (int32_t)(pl >> 32);
+      const int32_t base = i < n0 ? off0[i] : off1[i - n0];
+      const int32_t pre = i < n0 ? lo0[i] : lo1[i - n0];
+      const int32_t w = (int32_t)(i < n0 ? work0[i] : work1[i - n0]);
+      light[at] = make_int4(code, base, pre, w);
+    }
     bool med = false;
     if (is_heavy[i]) {
       const int64_t w = i < n0 ? work0[i] : work1[i - n0];
@@ -613,9 +625,9 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   const int32_t n0 = g->side[0].n, n1 = g->side[1].n;
   const int64_t n = (int64_t)n0 + n1;
   TmpBuf flags_l, flags_h, pos_l, pos_h, sums;
-  flags_l.alloc(sizeof(int32_t) * (size_t)n, s);
+  flags_l.alloc(sizeof(int64_t) * (size_t)n, s);
   flags_h.alloc(sizeof(int32_t) * (size_t)n, s);
-  pos_l.alloc(sizeof(int32_t) * (size_t)(n + 1), s);
+  pos_l.alloc(sizeof(int64_t) * (size_t)(n + 1), s);
   pos_h.alloc(sizeof(int32_t) * (size_t)(n + 1), s);
   sums.alloc(8 * sizeof(int64_t), s);
   BFC_HIP(hipMemsetAsync(sums.p, 0, 8 * sizeof(int64_t), s));
@@ -627,20 +639,22 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   if (n > 0) {
     classify_kernel<<<grid_1d(n) < 1024 ? grid_1d(n) : 1024, kClassifyNT, 0, s>>>(g->side[0].work.as<int64_t>(), g->side[0].lo.as<int32_t>(), n0,
                                                 g->side[1].work.as<int64_t>(), g->side[1].lo.as<int32_t>(), n1,
-                                                light_max, KU, KL, flags_l.as<int32_t>(), flags_h.as<int32_t>(),
+                                                light_max, KU, KL, flags_l.as<int64_t>(), flags_h.as<int32_t>(),
                                                 sums.as<unsigned long long>());
     BFC_LAUNCH_CHECK();
   }
-  exclusive_scan_i32(flags_l.as<int32_t>(), pos_l.as<int32_t>(), n, pos_l.as<int32_t>() + n, s);
+  exclusive_scan_i64(flags_l.as<int64_t>(), pos_l.as<int64_t>(), n, pos_l.as<int64_t>() + n, s);
   exclusive_scan_i32(flags_h.as<int32_t>(), pos_h.as<int32_t>(), n, pos_h.as<int32_t>() + n, s);
-  int32_t counts[2] = {0, 0};
+  int64_t light_counts = 0;
+  int32_t heavy_count = 0;
   int64_t wsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  BFC_HIP(hipMemcpyAsync(&counts[0], pos_l.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  BFC_HIP(hipMemcpyAsync(&counts[1], pos_h.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  BFC_HIP(hipMemcpyAsync(&light_counts, pos_l.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BFC_HIP(hipMemcpyAsync(&heavy_count, pos_h.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipMemcpyAsync(wsum, sums.p, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
-  sc.n_light = counts[0];
-  sc.n_heavy = counts[1];
+  sc.n_small = (int32_t)(light_counts & 0xFFFFFFFFll);
+  sc.n_light = sc.n_small + (int32_t)(light_counts >> 32);
+  sc.n_heavy = heavy_count;
   sc.wedges = wsum[0];
   sc.max_prefix = (int32_t)wsum[1];
   sc.wedges_light = wsum[2];
@@ -649,18 +663,19 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   sc.middles_heavy = wsum[5];
   sc.max_start_wedges = wsum[6];
   sc.light_max = g->tune.light_max_wedges;
-  sc.light.alloc(sizeof(int32_t) * (size_t)sc.n_light, s);
+  sc.light.alloc(sizeof(int4) * (size_t)sc.n_light, s);
   sc.heavy.alloc(sizeof(int32_t) * (size_t)sc.n_heavy, s);
   TmpBuf hkey, hkey_tmp, hval_tmp;
   hkey.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
   hkey_tmp.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
   hval_tmp.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
   if (n > 0) {
-    compact_kernel<<<grid_1d(n), 256, 0, s>>>(flags_l.as<int32_t>(), flags_h.as<int32_t>(), pos_l.as<int32_t>(),
+    compact_kernel<<<grid_1d(n), 256, 0, s>>>(flags_l.as<int64_t>(), flags_h.as<int32_t>(), pos_l.as<int64_t>(),
                                                pos_h.as<int32_t>(), n0, n1, g->side[0].work.as<int64_t>(),
                                                g->side[1].work.as<int64_t>(), g->side[0].lo.as<int32_t>(),
-                                               g->side[1].lo.as<int32_t>(), (int64_t)g->tune.medium_max_wedges, KU,
-                                               KL, sc.light.as<int32_t>(), sc.heavy.as<int32_t>(),
+                                               g->side[1].lo.as<int32_t>(), g->side[0].off.as<int32_t>(),
+                                               g->side[1].off.as<int32_t>(), (int64_t)g->tune.medium_max_wedges, KU,
+                                               KL, sc.light.as<int4>(), sc.heavy.as<int32_t>(),
                                                hkey.as<uint32_t>(), sums.as<unsigned long long>() + 7);
     BFC_LAUNCH_CHECK();
   }

@@ -162,70 +162,102 @@ __device__ __forceinline__ int32_t table_lb(const int32_t* __restrict__ oadj, co
   return gallop_lower_bound(oadj, a, rowp[w + 1], key);
 }
 
+// ------------------------------------------------------------ wavefront helpers
+// end id at slot (a 32-bit byte offset from a wavefront-uniform base)
+__device__ __forceinline__ int32_t load_end(const int32_t* __restrict__ oadj, int32_t slot) {
+  return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(oadj) + ((uint32_t)slot << 2));
+}
+
+// number of set bits of m in lanes below this one, plus add
+__device__ __forceinline__ int32_t mbcnt(uint64_t m, int32_t add) {
+  return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)add));
+}
+
+// Inclusive prefix maximum over the lanes of non-negative values: shifts of
+// 1, 2, 4 and 8 lanes inside each row of 16, then the row broadcasts of
+// lanes 15 and 31 (lanes a shift moves out of range read 0).
+__device__ __forceinline__ int32_t wave_prefix_max(int32_t v) {
+  int32_t t;
+  t = __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v = v > t ? v : t;
+  t = __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v = v > t ? v : t;
+  t = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v = v > t ? v : t;
+  t = __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v = v > t ? v : t;
+  t = __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1 and 3
+  v = v > t ? v : t;
+  t = __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2 and 3
+  v = v > t ? v : t;
+  return v;
+}
+
 // ------------------------------------------------------------ wavefront walk
-// Positions each lane takes per step of a walk (strided by 64, so one load
-// instruction reads 64 consecutive slots of one or a few middles).
-constexpr int kSteps = 8;
+// Steps of 64 positions each lane loads before using any of them.
+constexpr int kLightSteps = 4;
 
-// Per-wavefront LDS state of one walk: slice starts and exclusive offsets of
-// up to 64 middles (exc[64] holds the total).
-struct WalkLds {
-  int32_t cs[64];
-  int32_t exc[65];
-};
-
-// Visits every wedge of a group of up to 64 middles.  Lane l holds middle
-// l's end slice [cs, cs + len) in adj_other.  Wedges are numbered 0..tot-1
-// in middle order; position f is taken by lane f mod 64, and each lane keeps
-// its current middle and advances it through the offsets in LDS (positions
-// only increase), so finding a wedge's middle costs about one LDS read.
-// Each lane issues kSteps end-id loads before using any of them.
-// fn(middle lane, slot, end) is called per wedge.
+// Visits every wedge of a group of up to 64 middles; lane j holds middle
+// j's end slice [cs, cs + len) in adj_other.  Wedges are numbered 0..tot-1
+// in middle order and position f is taken by lane f mod 64.  The middle of
+// position f is the last non-empty middle whose first position is <= f: per
+// step of 64 positions, a ballot finds the last one starting at or before
+// the step, the middles starting inside the step mark their first lane
+// (ds_permute; non-empty middles start at distinct positions) and a prefix
+// maximum over the lanes picks the latest mark.  fn(middle lane, slot, end)
+// is called per wedge.
 template <typename Fn>
-__device__ __forceinline__ void wave_walk(const int32_t* __restrict__ oadj, int32_t cs, int32_t len, WalkLds& L,
-                                          Fn&& fn) {
+__device__ __forceinline__ void light_walk(const int32_t* __restrict__ oadj, int32_t cs, int32_t len, Fn&& fn) {
   const int lane = __lane_id();
   const int32_t inc = wave_inclusive_scan(len);
   const int32_t tot = __shfl(inc, 63, 64);
-  __builtin_amdgcn_wave_barrier();
-  L.cs[lane] = cs;
-  L.exc[lane] = inc - len;
-  if (lane == 63) L.exc[64] = tot;
-  __builtin_amdgcn_wave_barrier();
-  int mid = 0;
-  for (int32_t f0 = 0; f0 < tot; f0 += 64 * kSteps) {
-    int32_t slot[kSteps], w[kSteps];
-    int midq[kSteps];
+  const int32_t exc = inc - len;
+  const int32_t delta = cs - exc;  // slot of position f in this middle: delta + f
+  for (int32_t f0 = 0; f0 < tot; f0 += 64 * kLightSteps) {
+    int32_t slot[kLightSteps], w[kLightSteps], mid[kLightSteps];
 #pragma unroll
-    for (int q = 0; q < kSteps; ++q) {
-      const int32_t f = f0 + 64 * q + lane;
+    for (int q = 0; q < kLightSteps; ++q) {
+      const int32_t fq = f0 + 64 * q;
       w[q] = -1;
       slot[q] = 0;
-      midq[q] = 0;
-      if (f < tot) {
-        while (L.exc[mid + 1] <= f) ++mid;  // exc[64] = tot > f bounds the loop
-        slot[q] = L.cs[mid] + (f - L.exc[mid]);
-        midq[q] = mid;
-        w[q] = oadj[slot[q]];
+      mid[q] = 0;
+      if (fq < tot) {
+        // the middle holding position fq starts at or before it, so the ballot is non-empty
+        const uint64_t before = __ballot(len > 0 && exc <= fq);
+        const int32_t carry = 63 - (int32_t)__builtin_clzll(before);
+        const int32_t e = exc - fq;
+        const bool mk = len > 0 && e > 0 && e < 64;
+        const int32_t mark = __builtin_amdgcn_ds_permute(mk ? e << 2 : 0, mk ? lane + 1 : 0);
+        int32_t m = wave_prefix_max(mark) - 1;
+        m = m > carry ? m : carry;
+        const int32_t dm = __builtin_amdgcn_ds_bpermute(m << 2, delta);
+        const int32_t f = fq + lane;
+        if (f < tot) {
+          slot[q] = dm + f;
+          mid[q] = m;
+          w[q] = load_end(oadj, slot[q]);
+        }
       }
     }
 #pragma unroll
-    for (int q = 0; q < kSteps; ++q)
-      if (w[q] >= 0) fn(midq[q], slot[q], w[q]);
+    for (int q = 0; q < kLightSteps; ++q)
+      if (w[q] >= 0) fn(mid[q], slot[q], w[q]);
   }
-  __builtin_amdgcn_wave_barrier();
 }
 
 // ------------------------------------------------------------ hash tables
-__device__ __forceinline__ void wave_hash_add(int32_t* keys, int32_t* cnt, uint32_t mask, int32_t w) {
+// Counts one wedge to end w in a wavefront's table (keys hold w + 1, 0 when
+// empty); returns the end's count before this wedge.  Summed over all
+// wedges, the returned counts give sum over ends of C(count, 2).
+__device__ __forceinline__ int32_t wave_hash_inc(int32_t* keys, int32_t* cnt, uint32_t mask, int32_t w) {
   const int32_t key = w + 1;
   uint32_t h = mix32((uint32_t)w) & mask;
   for (;;) {
     const int32_t cur = keys[h];
-    if (cur == key) { atomicAdd(&cnt[h], 1); return; }
+    if (cur == key) return atomicAdd(&cnt[h], 1);
     if (cur == 0) {
       const int32_t old = atomicCAS(&keys[h], 0, key);
-      if (old == 0 || old == key) { atomicAdd(&cnt[h], 1); return; }
+      if (old == 0 || old == key) return atomicAdd(&cnt[h], 1);
     }
     h = (h + 1) & mask;
   }
@@ -239,38 +271,46 @@ __device__ __forceinline__ int32_t hash_get(const int32_t* keys, const int32_t* 
 }
 
 // ------------------------------------------------------------ light
+// Light starts come in two classes by wedge count: up to kSmallMax wedges
+// (a 512-entry table per wavefront, so a CU holds 32 wavefronts) and the
+// rest up to light_max (2048 entries, 8 wavefronts per CU).  A table has at
+// least twice as many entries as its start has wedges.
 constexpr int kLightNT = 256;
 constexpr int kLightWaves = kLightNT / 64;
-constexpr int kLightCap = 2048;  // table entries per wavefront; light_max <= kLightCap / 2
+constexpr int kLightCap = 2048;  // light_max <= kLightCap / 2
+constexpr int kSmallCap = 2 * kSmallMax;
 
-__global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
-  __shared__ int32_t tkeys[kLightWaves][kLightCap];
-  __shared__ int32_t tcnt[kLightWaves][kLightCap];
-  __shared__ WalkLds twalk[kLightWaves];
-  __shared__ unsigned long long tdelta[kLightWaves][64];
+// Each entry of the light list is {code, first slot of N(r), middles, wedges}.
+template <int kMode, int kCap>
+__global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const int4* __restrict__ list,
+                                                         int32_t n_list) {
+  __shared__ int32_t tkeys[kLightWaves][kCap];
+  __shared__ int32_t tcnt[kLightWaves][kCap];
+  __shared__ unsigned long long tdelta[kLightWaves][kMode == kTotal ? 1 : 64];
   const int lane = __lane_id();
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int32_t* keys = tkeys[wv];
   int32_t* cnt = tcnt[wv];
-  WalkLds& L = twalk[wv];
   unsigned long long* dsum = tdelta[wv];
-  for (int h = lane; h < kLightCap; h += 64) { keys[h] = 0; cnt[h] = 0; }
-  dsum[lane] = 0;
+  for (int h = lane; h < kCap; h += 64) { keys[h] = 0; cnt[h] = 0; }
+  if (kMode != kTotal) dsum[lane] = 0;
   unsigned long long acc_total = 0;
-  const int mode = p.mode;
-  for (int64_t idx = (int64_t)blockIdx.x * kLightWaves + wv; idx < p.n_list;
-       idx += (int64_t)gridDim.x * kLightWaves) {
-    const int32_t code = p.list[idx];
-    const int x = (int)((uint32_t)code >> 30);
-    const int32_t r = code & ((1 << 30) - 1);
+  const int64_t stride = (int64_t)gridDim.x * kLightWaves;
+  int64_t idx = (int64_t)blockIdx.x * kLightWaves + wv;
+  int4 next = idx < n_list ? list[idx] : make_int4(0, 0, 0, 0);
+  for (; idx < n_list; idx += stride) {
+    const int4 cur = next;
+    if (idx + stride < n_list) next = list[idx + stride];
+    const int x = (int)((uint32_t)cur.x >> 30);
+    const int32_t r = cur.x & ((1 << 30) - 1);
+    const int32_t base = cur.y;
+    const int32_t pre = cur.z;
     const SideView S = pick(p, x);
     const SideView O = pick(p, 1 - x);
-    const int32_t base = S.off[r];
-    const int32_t pre = S.lo[r];
-    const int64_t W = S.work[r];
     uint32_t cap = 64;
-    while ((int64_t)cap < 2 * W) cap <<= 1;
+    while ((int32_t)cap < 2 * cur.w) cap <<= 1;
     const uint32_t mask = cap - 1;
+    unsigned long long a = 0;
     for (int32_t j0 = 0; j0 < pre; j0 += 64) {
       const int32_t j = j0 + lane;
       int32_t cs = 0, len = 0;
@@ -279,34 +319,28 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
         cs = O.off[S.adj[k]];
         len = S.rev[k] - cs;
       }
-      wave_walk(O.adj, cs, len, L, [&](int, int32_t, int32_t w) { wave_hash_add(keys, cnt, mask, w); });
+      light_walk(O.adj, cs, len, [&](int, int32_t, int32_t w) { a += (unsigned)wave_hash_inc(keys, cnt, mask, w); });
     }
-    unsigned long long a = 0;
-    if (mode == kVertex) {
-      unsigned long long* vs = pick_ptr(p.vout, x);
-      for (uint32_t h = lane; h < cap; h += 64) {
-        const int32_t c = cnt[h];
-        if (c > 1) {
-          const unsigned long long cc = choose2(c);
-          a += cc;
-          atomicAdd(&vs[S.id_of[keys[h] - 1]], cc);
-        }
-      }
-      a = wave_sum(a);
-      if (lane == 0 && a) atomicAdd(&vs[S.id_of[r]], a);
-    } else if (mode == kTotal) {
-      for (uint32_t h = lane; h < cap; h += 64) {
-        const int32_t c = cnt[h];
-        if (c > 1) a += choose2(c);
-      }
+    if (kMode == kTotal) {
       if (p.gtotal) {
         a = wave_sum(a);
         if (lane == 0 && a) atomicAdd(&p.gtotal[graph_index(p, x, r)], a);
       } else {
         acc_total += a;
       }
-    }
-    if (mode != kTotal) {
+    } else {
+      if (kMode == kVertex) {
+        // each end w gains C(count_w, 2); the start gains their sum
+        unsigned long long* vs = pick_ptr(p.vout, x);
+        for (uint32_t h = lane; h < cap; h += 64) {
+          const int32_t c = cnt[h];
+          if (c > 1) atomicAdd(&vs[S.id_of[keys[h] - 1]], choose2(c));
+        }
+        a = wave_sum(a);
+        if (lane == 0 && a) atomicAdd(&vs[S.id_of[r]], a);
+      }
+      // second pass: every wedge (r, v, w) adds count_w - 1 to the middle v
+      // (Lemma 1) and, per edge, to the arcs (r, v) and (v, w) (Algorithm 4)
       unsigned long long* vmid = pick_ptr(p.vout, 1 - x);
       unsigned long long* acc_s = pick_ptr(p.acc, x);
       unsigned long long* acc_o = pick_ptr(p.acc, 1 - x);
@@ -319,26 +353,29 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p) {
           cs = O.off[v];
           len = S.rev[k] - cs;
         }
-        wave_walk(O.adj, cs, len, L, [&](int mid, int32_t slot, int32_t w) {
+        light_walk(O.adj, cs, len, [&](int mid, int32_t slot, int32_t w) {
           const int32_t c = hash_get(keys, cnt, mask, w);
           if (c > 1) {
             const unsigned long long d = (unsigned long long)(c - 1);
-            if (mode == kEdge) atomicAdd(&acc_o[slot], d);
+            if (kMode == kEdge) atomicAdd(&acc_o[slot], d);
             atomicAdd(&dsum[mid], d);
           }
         });
+        __builtin_amdgcn_wave_barrier();
         const unsigned long long d = dsum[lane];
         if (d) {
-          if (mode == kEdge) atomicAdd(&acc_s[base + j], d);
+          if (kMode == kEdge) atomicAdd(&acc_s[base + j], d);
           else atomicAdd(&vmid[O.id_of[v]], d);
           dsum[lane] = 0;
         }
         __builtin_amdgcn_wave_barrier();
       }
     }
+    __builtin_amdgcn_wave_barrier();
     for (uint32_t h = lane; h < cap; h += 64) { keys[h] = 0; cnt[h] = 0; }
+    __builtin_amdgcn_wave_barrier();
   }
-  if (mode == kTotal && p.total) {
+  if (kMode == kTotal && p.total) {
     acc_total = wave_sum(acc_total);
     if (lane == 0 && acc_total) atomicAdd(p.total, acc_total);
   }
@@ -450,16 +487,6 @@ __device__ __forceinline__ int32_t packed_hash_get(const uint32_t* tab, uint32_t
 // one's are used.  fn(segment, slot, end) is called per wedge; stop() is
 // polled (uniformly) once per iteration.
 constexpr int kSegSteps = 8;
-
-// end id at slot (a 32-bit byte offset from a wavefront-uniform base)
-__device__ __forceinline__ int32_t load_end(const int32_t* __restrict__ oadj, int32_t slot) {
-  return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(oadj) + ((uint32_t)slot << 2));
-}
-
-// number of set bits of m in lanes below this one, plus add
-__device__ __forceinline__ int32_t mbcnt(uint64_t m, int32_t add) {
-  return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)add));
-}
 
 template <typename Fn, typename Stop>
 __device__ __forceinline__ void seg_walk(const int32_t* __restrict__ oadj, const int32_t* se, const int32_t* sd,
@@ -1425,13 +1452,29 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   }
   dense_block(g, s);
   if (g->timing) BFC_HIP(hipEventRecord(tc.ev[1], s));
-  if (sc.n_light > 0) {
-    p.list = g->sched.light.as<int32_t>();
-    p.n_list = sc.n_light;
-    int64_t grid = ((int64_t)sc.n_light + kLightWaves - 1) / kLightWaves;
-    if (grid > (int64_t)cus * 16) grid = (int64_t)cus * 16;
-    light_kernel<<<(unsigned)grid, kLightNT, 0, s>>>(p);
-    BFC_LAUNCH_CHECK();
+  {
+    // the light list holds the small starts, then the others
+    const int4* llist = g->sched.light.as<int4>();
+    auto light_grid = [&](int32_t n) {
+      int64_t grid = ((int64_t)n + kLightWaves - 1) / kLightWaves;
+      return (unsigned)(grid > (int64_t)cus * 16 ? (int64_t)cus * 16 : grid);
+    };
+    const int32_t n_small = sc.n_small, n_large = sc.n_light - sc.n_small;
+    if (n_small > 0) {
+      const unsigned grid = light_grid(n_small);
+      if (mode == kTotal) light_kernel<kTotal, kSmallCap><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
+      else if (mode == kVertex) light_kernel<kVertex, kSmallCap><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
+      else light_kernel<kEdge, kSmallCap><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
+      BFC_LAUNCH_CHECK();
+    }
+    if (n_large > 0) {
+      const unsigned grid = light_grid(n_large);
+      const int4* l = llist + n_small;
+      if (mode == kTotal) light_kernel<kTotal, kLightCap><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+      else if (mode == kVertex) light_kernel<kVertex, kLightCap><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+      else light_kernel<kEdge, kLightCap><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+      BFC_LAUNCH_CHECK();
+    }
   }
   if (g->timing) BFC_HIP(hipEventRecord(tc.ev[2], s));
   // the heavy list holds the big starts (decreasing work), then the medium ones

@@ -19,6 +19,8 @@ constexpr int kWinShift = 15;
 // Medium heavy starts (256-thread workgroups) have at most this many middles.
 constexpr int32_t kMediumMaxPre = 512;
 constexpr int32_t kWinMinDegree = 64;
+// Light starts of at most this many wedges use the small-table kernel.
+constexpr int32_t kSmallMax = 256;
 
 // ------------------------------------------------------------ errors
 struct Error {
@@ -114,9 +116,10 @@ struct Side {
 
 struct Schedule {
   int32_t n_light = 0;   // starts counted by one wavefront
+  int32_t n_small = 0;   // of those, the first n_small have at most kSmallMax wedges
   int32_t n_heavy = 0;   // starts counted by one workgroup
   int32_t n_medium = 0;  // of those, the last n_medium use the 256-thread shape
-  DevBuf light;          // int32 codes (side << 30 | rank)
+  DevBuf light;          // int4 {code (side << 30 | rank), off[rank], lo[rank], wedges}
   DevBuf heavy;          // int32 codes, by decreasing work
   int64_t wedges = 0;    // |W|
   int32_t max_prefix = 0;
