@@ -116,23 +116,10 @@ __device__ __forceinline__ int32_t gallop_lower_bound(const int32_t* __restrict_
 constexpr int32_t kNoEnd = 0x7FFFFFFF;  // "no further end" (no rank reaches it)
 
 // First index in [lo, hi) with a[index] >= key when the answer is usually
-// within a few entries of lo: four independent loads, then a gallop.
-__device__ __forceinline__ int32_t near_lower_bound(const int32_t* __restrict__ a, int32_t lo, int32_t hi,
-                                                    int32_t key) {
-  const int32_t n = hi - lo;
-  if (n <= 0) return lo;
-  const int32_t a0 = a[lo];
-  const int32_t a1 = n > 1 ? a[lo + 1] : key;
-  const int32_t a2 = n > 2 ? a[lo + 2] : key;
-  const int32_t a3 = n > 3 ? a[lo + 3] : key;
-  if (a0 >= key) return lo;
-  if (a1 >= key) return lo + 1;
-  if (a2 >= key) return lo + 2;
-  if (a3 >= key) return lo + 3;
-  return gallop_lower_bound(a, lo + 4, hi, key);
-}
-
-// near_lower_bound that also returns a[index] (kNoEnd when index == hi).
+// within a few entries of lo: four probes, then a gallop.  Also returns
+// a[index] in val (kNoEnd when index == hi).  (Probes made unconditional, or
+// more of them, measured slower: more loads and registers in the window
+// set-up than the latency they save.)
 __device__ __forceinline__ int32_t near_lower_bound_v(const int32_t* __restrict__ a, int32_t lo, int32_t hi,
                                                       int32_t key, int32_t& val) {
   const int32_t n = hi - lo;
@@ -149,6 +136,12 @@ __device__ __forceinline__ int32_t near_lower_bound_v(const int32_t* __restrict_
   const int32_t i = gallop_lower_bound(a, lo + 4, hi, key);
   if (i < hi) val = a[i];
   return i;
+}
+
+__device__ __forceinline__ int32_t near_lower_bound(const int32_t* __restrict__ a, int32_t lo, int32_t hi,
+                                                    int32_t key) {
+  int32_t val;
+  return near_lower_bound_v(a, lo, hi, key, val);
 }
 
 // First slot of a table middle's list (row `rowp` of the window-boundary
@@ -395,14 +388,14 @@ static_assert(kMedPre == 2 * kMedNT, "medium starts must fit the resident mode")
 constexpr int32_t kNone = 0x7FFFFFFF;       // "no further end" in a middle's cursor
 
 // Inserts end w into the workgroup hash table (count 1, or bumps its count).
-// Returns 1 when w is a new key.  A probe sequence longer than kMaxProbe, or
-// a window already flagged as overfull, sets/keeps the flag and inserts
-// nothing more: the window is then halved and walked again, so an overfull
-// table never turns into long scans.
+// Returns 1 when w is a new key, 0 when it was present, and kOverfull when
+// its probe sequence reached kMaxProbe slots without finding w or a free
+// slot (nothing is inserted): the caller then flags the window, which is
+// halved and walked again, so an overfull table never turns into long scans.
 constexpr uint32_t kMaxProbe = 64;
+constexpr int kOverfull = 2;
 
-__device__ __forceinline__ int block_hash_add(int32_t* table, uint32_t cap, int32_t w, int32_t* s_over) {
-  if (*(volatile int32_t*)s_over) return 0;
+__device__ __forceinline__ int block_hash_add(int32_t* table, uint32_t cap, int32_t w) {
   int32_t* keys = table;
   int32_t* cnt = table + cap;
   const int32_t key = w + 1;
@@ -418,8 +411,7 @@ __device__ __forceinline__ int block_hash_add(int32_t* table, uint32_t cap, int3
     }
     h = (h + 1) & mask;
   }
-  *s_over = 1;
-  return 0;
+  return kOverfull;
 }
 
 // Dense window counters: 32-bit, or two 16-bit counters per word when every
@@ -444,8 +436,7 @@ constexpr uint32_t kPackMask = (1u << kPackBits) - 1u;
 constexpr int32_t kPackMaxPre = 1 << kPackBits;
 constexpr int32_t kPackMaxWidth = (1 << (32 - kPackBits)) - 1;
 
-__device__ __forceinline__ int packed_hash_add(uint32_t* tab, uint32_t cap, uint32_t key, int32_t* s_over) {
-  if (*(volatile int32_t*)s_over) return 0;
+__device__ __forceinline__ int packed_hash_add(uint32_t* tab, uint32_t cap, uint32_t key) {
   const uint32_t mask = cap - 1;
   uint32_t h = mix32(key) & mask;
   for (uint32_t probe = 0; probe < kMaxProbe; ++probe) {
@@ -458,8 +449,7 @@ __device__ __forceinline__ int packed_hash_add(uint32_t* tab, uint32_t cap, uint
     }
     h = (h + 1) & mask;
   }
-  *s_over = 1;
-  return 0;
+  return kOverfull;
 }
 
 __device__ __forceinline__ int32_t packed_hash_get(const uint32_t* tab, uint32_t mask, uint32_t key) {
@@ -1079,24 +1069,36 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
             seg_walk(O.adj, se, sd, nseg, F0, F1, [&](int32_t, int32_t, int32_t w) { atomicAdd(&tw[w], 1); },
                      [] { return false; });
           } else {
+            // this lane's new keys since the last poll, and whether a probe overran
             int32_t fresh = 0;
+            bool overran = false;
             auto poll = [&] {
+              const bool ovf = __ballot(overran) != 0;
               const int32_t fw = wave_sum(fresh);
               fresh = 0;
-              if (lane == 0 && fw && atomicAdd(&s_fill, fw) + fw > (int32_t)(cap / 8 * 5)) s_over = 1;
-              return __builtin_amdgcn_readfirstlane(*(volatile int32_t*)&s_over) != 0;
+              if (lane == 0 && (ovf || (fw && atomicAdd(&s_fill, fw) + fw > (int32_t)(cap / 8 * 5)))) s_over = 1;
+              // a plain LDS read of the flag (other wavefronts may have set it)
+              return __builtin_amdgcn_readfirstlane(
+                         __hip_atomic_load(&s_over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != 0;
             };
             if (wpacked) {
               uint32_t* pt = reinterpret_cast<uint32_t*>(table);
               const int32_t kb = lo_w - 1;  // key = end - lo_w + 1
               seg_walk(O.adj, se, sd, nseg, F0, F1,
                        [&](int32_t, int32_t, int32_t w) {
-                         fresh += packed_hash_add(pt, cap, (uint32_t)(w - kb), &s_over);
+                         const int res = packed_hash_add(pt, cap, (uint32_t)(w - kb));
+                         fresh += res & 1;
+                         overran |= res == kOverfull;
                        },
                        poll);
             } else {
               seg_walk(O.adj, se, sd, nseg, F0, F1,
-                       [&](int32_t, int32_t, int32_t w) { fresh += block_hash_add(table, cap, w, &s_over); }, poll);
+                       [&](int32_t, int32_t, int32_t w) {
+                         const int res = block_hash_add(table, cap, w);
+                         fresh += res & 1;
+                         overran |= res == kOverfull;
+                       },
+                       poll);
             }
             poll();  // the walk does not poll after its last iteration
           }
