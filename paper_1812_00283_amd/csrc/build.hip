@@ -618,6 +618,21 @@ __global__ void compact_kernel(const int64_t* __restrict__ is_light, const int32
   }
 }
 
+// Heavy list entries {code, off[rank], lo[rank], wedges (clamped to int32)}
+// in the sorted order of the codes.
+__global__ void heavy_entries_kernel(const uint32_t* __restrict__ codes, int32_t n, const int32_t* __restrict__ off0,
+                                     const int32_t* __restrict__ off1, const int32_t* __restrict__ lo0,
+                                     const int32_t* __restrict__ lo1, const int64_t* __restrict__ work0,
+                                     const int64_t* __restrict__ work1, int4* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t code = (int32_t)codes[i];
+    const int x = (int)((uint32_t)code >> 30);
+    const int32_t r = code & ((1 << 30) - 1);
+    const int64_t w = x ? work1[r] : work0[r];
+    out[i] = make_int4(code, x ? off1[r] : off0[r], x ? lo1[r] : lo0[r], w < 0x7FFFFFFF ? (int32_t)w : 0x7FFFFFFF);
+  }
+}
+
 }  // namespace
 
 void build_schedule(bfc_graph_s* g, hipStream_t s) {
@@ -664,8 +679,9 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   sc.max_start_wedges = wsum[6];
   sc.light_max = g->tune.light_max_wedges;
   sc.light.alloc(sizeof(int4) * (size_t)sc.n_light, s);
-  sc.heavy.alloc(sizeof(int32_t) * (size_t)sc.n_heavy, s);
-  TmpBuf hkey, hkey_tmp, hval_tmp;
+  sc.heavy.alloc(sizeof(int4) * (size_t)sc.n_heavy, s);
+  TmpBuf hkey, hkey_tmp, hval_tmp, hcode;
+  hcode.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
   hkey.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
   hkey_tmp.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
   hval_tmp.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
@@ -675,13 +691,20 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
                                                g->side[1].work.as<int64_t>(), g->side[0].lo.as<int32_t>(),
                                                g->side[1].lo.as<int32_t>(), g->side[0].off.as<int32_t>(),
                                                g->side[1].off.as<int32_t>(), (int64_t)g->tune.medium_max_wedges, KU,
-                                               KL, sc.light.as<int4>(), sc.heavy.as<int32_t>(),
+                                               KL, sc.light.as<int4>(), hcode.as<int32_t>(),
                                                hkey.as<uint32_t>(), sums.as<unsigned long long>() + 7);
     BFC_LAUNCH_CHECK();
   }
   if (sc.n_heavy > 1) {
-    radix_sort_u32(hkey.as<uint32_t>(), sc.heavy.as<uint32_t>(), hkey_tmp.as<uint32_t>(), hval_tmp.as<uint32_t>(),
+    radix_sort_u32(hkey.as<uint32_t>(), hcode.as<uint32_t>(), hkey_tmp.as<uint32_t>(), hval_tmp.as<uint32_t>(),
                    sc.n_heavy, 32, s);
+  }
+  if (sc.n_heavy > 0) {
+    heavy_entries_kernel<<<grid_1d(sc.n_heavy), 256, 0, s>>>(
+        hcode.as<uint32_t>(), sc.n_heavy, g->side[0].off.as<int32_t>(), g->side[1].off.as<int32_t>(),
+        g->side[0].lo.as<int32_t>(), g->side[1].lo.as<int32_t>(), g->side[0].work.as<int64_t>(),
+        g->side[1].work.as<int64_t>(), sc.heavy.as<int4>());
+    BFC_LAUNCH_CHECK();
   }
   int64_t n_medium = 0;
   BFC_HIP(hipMemcpyAsync(&n_medium, sums.as<int64_t>() + 7, sizeof(int64_t), hipMemcpyDeviceToHost, s));

@@ -42,7 +42,7 @@ struct SideView {
 
 struct CountParams {
   SideView sv[2];
-  const int32_t* list;
+  const int4* list;            // heavy starts: {code, off[rank], lo[rank], wedges clamped to int32}
   int32_t n_list;
   int32_t mode;
   unsigned long long* total;
@@ -625,7 +625,8 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
   __shared__ __align__(16) int32_t table[kWords];
   __shared__ __align__(16) int32_t segbuf[kSW];
   __shared__ unsigned long long s_red64[kWaves + 1];
-  __shared__ int32_t s_idx, s_fill, s_over, s_cut_j, s_cut_lex;
+  __shared__ int32_t s_fill, s_over, s_cut_j, s_cut_lex;
+  __shared__ int4 s_entry;      // the next start's list entry (code -1: none left)
   __shared__ int32_t s_ticket;  // chunk ticket of the dense walk
   __shared__ unsigned long long s_emit;  // resident emission: count << 32 | total length
 
@@ -641,20 +642,26 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
   for (int i = t; i < kWords; i += kNT) table[i] = 0;
   unsigned long long acc_total = 0;
 
+  // Starts come from a global ticket.  Thread 0 takes the next start's
+  // ticket when a start begins and loads its entry when the start ends, so
+  // the ticket's round trip overlaps the start's work.
+  auto entry_of = [&](uint32_t i) { return (int32_t)i < p.n_list ? p.list[i] : make_int4(-1, 0, 0, 0); };
+  if (t == 0) s_entry = entry_of(atomicAdd(p.ticket, 1u));
   for (;;) {
-    if (t == 0) s_idx = (int32_t)atomicAdd(p.ticket, 1u);
     __syncthreads();
-    const int32_t idx = s_idx;
+    const int4 ent = s_entry;
     __syncthreads();
-    if (idx >= p.n_list) break;
-    const int32_t code = p.list[idx];
+    if (ent.x < 0) break;
+    uint32_t next_ticket = 0;
+    if (t == 0) next_ticket = atomicAdd(p.ticket, 1u);
+    const int32_t code = ent.x;
     const int x = (int)((uint32_t)code >> 30);
     const int32_t r = code & ((1 << 30) - 1);
     const SideView S = pick(p, x);
     const SideView O = pick(p, 1 - x);
-    const int32_t base = S.off[r];
-    const int32_t pre = S.lo[r];
-    const int64_t W = S.work[r];
+    const int32_t base = ent.y;
+    const int32_t pre = ent.z;
+    const int64_t W = ent.w < 0x7FFFFFFF ? (int64_t)ent.w : S.work[r];
     const int32_t range = r;
     // ends lie in [rlo, r): a batch ranks each graph's vertices contiguously
     // (rlo = the graph's first rank, rounded down to even because dense
@@ -1298,6 +1305,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     } else {
       acc_total += start_acc;
     }
+    if (t == 0) s_entry = entry_of(next_ticket);
   }
   if (mode == kTotal && p.total) {
     const unsigned long long s = block_sum<unsigned long long, kNT>(acc_total, s_red64);
@@ -1482,7 +1490,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   // the heavy list holds the big starts (decreasing work), then the medium ones
   const int32_t n_big = sc.n_heavy - sc.n_medium;
   if (n_big > 0) {
-    p.list = g->sched.heavy.as<int32_t>();
+    p.list = g->sched.heavy.as<int4>();
     p.n_list = n_big;
     if (mode == kTotal) heavy_kernel<kTotal, kBigNT, kBigWords><<<(unsigned)big_grid, kBigNT, 0, s>>>(p);
     else if (mode == kVertex) heavy_kernel<kVertex, kBigNT, kBigWords><<<(unsigned)big_grid, kBigNT, 0, s>>>(p);
@@ -1490,7 +1498,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     BFC_LAUNCH_CHECK();
   }
   if (sc.n_medium > 0) {
-    p.list = g->sched.heavy.as<int32_t>() + n_big;
+    p.list = g->sched.heavy.as<int4>() + n_big;
     p.n_list = sc.n_medium;
     p.ticket = ticket + 1;
     p.cursor = med_cursor;

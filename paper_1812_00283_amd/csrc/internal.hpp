@@ -120,7 +120,7 @@ struct Schedule {
   int32_t n_heavy = 0;   // starts counted by one workgroup
   int32_t n_medium = 0;  // of those, the last n_medium use the 256-thread shape
   DevBuf light;          // int4 {code (side << 30 | rank), off[rank], lo[rank], wedges}
-  DevBuf heavy;          // int32 codes, by decreasing work
+  DevBuf heavy;          // int4 entries as in `light`, by decreasing work
   int64_t wedges = 0;    // |W|
   int32_t max_prefix = 0;
   int64_t wedges_light = 0, wedges_heavy = 0;
