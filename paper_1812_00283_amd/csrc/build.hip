@@ -225,28 +225,54 @@ __global__ void transpose_unpack_kernel(const uint32_t* __restrict__ key, const 
 // rev[k] - off_other[neighbour].  With the global id putting every upper
 // vertex above every lower one, for an upper u and lower v:
 // p(v) < p(u)  <=>  deg(v) <= deg(u).
-__global__ void middle_kernel(int64_t m, int x, const int32_t* __restrict__ src, const int32_t* __restrict__ adj,
-                              const int32_t* __restrict__ rev, const int32_t* __restrict__ off_other,
-                              const int32_t* __restrict__ deg_self, const int32_t* __restrict__ deg_other,
-                              int32_t* __restrict__ mid_flag, int64_t* __restrict__ mid_work) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t r = src[k];
-    const int32_t v = adj[k];
-    const int32_t ds = deg_self[r], dv = deg_other[v];
-    const bool mid = x == 0 ? dv <= ds : dv < ds;
-    mid_flag[k] = mid ? 1 : 0;
-    mid_work[k] = mid ? (int64_t)(rev[k] - off_other[v]) : 0;
-  }
-}
-
-// lo[r] and work[r] from the prefix sums of the per-arc values over row r.
-__global__ void row_sums_kernel(int32_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ flag_scan,
-                                const int64_t* __restrict__ work_scan, int32_t* __restrict__ lo,
-                                int64_t* __restrict__ work) {
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t a = off[r], b = off[r + 1];
-    lo[r] = flag_scan[b] - flag_scan[a];
-    work[r] = work_scan[b] - work_scan[a];
+// Per start r of side x: lo[r] = its middles (the neighbours v of lower
+// priority, a prefix of N(r): deg(v) <= deg(r) across the layers, ties to
+// the lower layer) and work[r] = the wedges Algorithm 2 walks from r, the
+// sum over middles of v's neighbours below r (rev[k] - off_other[v]).
+// Arc-parallel over the side's CSR, whose starts ascend: a wavefront sums
+// its 64 arcs per run of equal start (segmented scan) and the run's last
+// lane adds the sums with one atomic each (lo and work start at zero).
+__global__ void start_stats_kernel(int64_t m, int x, const int32_t* __restrict__ src,
+                                   const int32_t* __restrict__ adj, const int32_t* __restrict__ rev,
+                                   const int32_t* __restrict__ off_other, const int32_t* __restrict__ deg_self,
+                                   const int32_t* __restrict__ deg_other, int32_t* __restrict__ lo,
+                                   unsigned long long* __restrict__ work) {
+  const int lane = __lane_id();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~63ll; b < m; b += stride) {
+    const int64_t k = b + lane;
+    int32_t r = -1, f = 0;
+    unsigned long long w = 0;
+    if (k < m) {
+      r = src[k];
+      const int32_t v = adj[k];
+      const int32_t ds = deg_self[r], dv = deg_other[v];
+      if (x == 0 ? dv <= ds : dv < ds) {
+        f = 1;
+        w = (unsigned long long)(rev[k] - off_other[v]);
+      }
+    }
+    // run boundaries: a lane heads a run when its start differs from the lane below
+    const int32_t r_prev = __shfl_up(r, 1, 64);
+    const int32_t r_next = __shfl_down(r, 1, 64);
+    const bool head = lane == 0 || r_prev != r;
+    const bool tail = lane == 63 || r_next != r;
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = lane == 63 ? heads : heads & ((2ull << lane) - 1ull);
+    const int s0 = 63 - (int)__builtin_clzll(upto);  // first lane of this lane's run
+    const int32_t inc_f = wave_inclusive_scan(f);
+    const unsigned long long inc_w = wave_inclusive_scan(w);
+    const int src_lane = s0 > 0 ? s0 - 1 : 0;
+    const int32_t pf = __shfl(inc_f, src_lane, 64);
+    const unsigned long long pw = __shfl(inc_w, src_lane, 64);
+    if (tail && r >= 0) {
+      const int32_t sf = inc_f - (s0 > 0 ? pf : 0);
+      const unsigned long long sw = inc_w - (s0 > 0 ? pw : 0ull);
+      if (sf) {
+        atomicAdd(&lo[r], sf);
+        atomicAdd(&work[r], sw);
+      }
+    }
   }
 }
 
@@ -455,21 +481,17 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
     Side& sd = g->side[x];
     sd.lo.alloc(sizeof(int32_t) * (size_t)sd.n, s);
     sd.work.alloc(sizeof(int64_t) * (size_t)sd.n, s);
-    TmpBuf flag, work;
-    flag.alloc(sizeof(int32_t) * (size_t)(m + 1), s);
-    work.alloc(sizeof(int64_t) * (size_t)(m + 1), s);
-    if (m > 0) {
-      middle_kernel<<<grid_1d(m), 256, 0, s>>>(m, x, src[x].as<int32_t>(), sd.adj.as<int32_t>(), sd.rev.as<int32_t>(),
-                                                g->side[1 - x].off.as<int32_t>(), deg_rank[x].as<int32_t>(),
-                                                deg_rank[1 - x].as<int32_t>(), flag.as<int32_t>(),
-                                                work.as<int64_t>());
-      BFC_LAUNCH_CHECK();
-    }
-    exclusive_scan_i32(flag.as<int32_t>(), flag.as<int32_t>(), m, flag.as<int32_t>() + m, s);
-    exclusive_scan_i64(work.as<int64_t>(), work.as<int64_t>(), m, work.as<int64_t>() + m, s);
     if (sd.n > 0) {
-      row_sums_kernel<<<grid_1d(sd.n), 256, 0, s>>>(sd.n, sd.off.as<int32_t>(), flag.as<int32_t>(),
-                                                     work.as<int64_t>(), sd.lo.as<int32_t>(), sd.work.as<int64_t>());
+      BFC_HIP(hipMemsetAsync(sd.lo.p, 0, sizeof(int32_t) * (size_t)sd.n, s));
+      BFC_HIP(hipMemsetAsync(sd.work.p, 0, sizeof(int64_t) * (size_t)sd.n, s));
+    }
+    if (m > 0) {
+      int64_t grid = (m + 255) / 256;
+      if (grid > 8192) grid = 8192;
+      start_stats_kernel<<<(unsigned)grid, 256, 0, s>>>(m, x, src[x].as<int32_t>(), sd.adj.as<int32_t>(),
+                                                        sd.rev.as<int32_t>(), g->side[1 - x].off.as<int32_t>(),
+                                                        deg_rank[x].as<int32_t>(), deg_rank[1 - x].as<int32_t>(),
+                                                        sd.lo.as<int32_t>(), sd.work.as<unsigned long long>());
       BFC_LAUNCH_CHECK();
     }
   }
