@@ -1066,11 +1066,15 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
           int32_t F0, F1;
           share(T, F0, F1);
           if (wdense && whalf) {
-            // lo_w is even: counter pair (w >> 1) - (lo_w >> 1), half (w & 1)
-            uint32_t* tw = reinterpret_cast<uint32_t*>(table) - (lo_w >> 1);
+            // lo_w is even: counter pair (w >> 1) - (lo_w >> 1), half (w & 1):
+            // byte offset (w & ~1) * 2 from tw, add 1 or 1 << 16
+            char* tw = reinterpret_cast<char*>(table) - 2 * lo_w;
             chunk_walk(O.adj, se, sd, nseg, T, &s_ticket,
-                     [&](int32_t, int32_t, int32_t w) { atomicAdd(&tw[w >> 1], (uint32_t)(w & 1) * 65535u + 1u); },
-                     [] { return false; });
+                       [&](int32_t, int32_t, int32_t w) {
+                         atomicAdd(reinterpret_cast<uint32_t*>(tw + ((uint32_t)(w & ~1) << 1)),
+                                   __umul24((uint32_t)w & 1u, 65535u) + 1u);
+                       },
+                       [] { return false; });
           } else if (wdense) {
             int32_t* tw = table - lo_w;
             seg_walk(O.adj, se, sd, nseg, F0, F1, [&](int32_t, int32_t, int32_t w) { atomicAdd(&tw[w], 1); },
@@ -1222,6 +1226,27 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
                    if (c > 1) start_acc += choose2(c);
                  },
                  [] { return false; });
+      } else if (wdense && whalf && mode != kVertex) {
+        // sum of c (c - 1) over the 16-bit counters: c (c - 1) < 2^32 is
+        // exact in a 24-bit multiply and is 0 for c = 0 or 1, so no branch
+        // per counter; the sum is even and halves exactly
+        const int32_t words = (hi_w - lo_w + 1) >> 1;
+        const int32_t quads = (words + 3) >> 2;
+        uint4* t4 = reinterpret_cast<uint4*>(table);
+        unsigned long long twice = 0;
+        for (int32_t i4 = t; i4 < quads; i4 += kNT) {
+          const uint4 q4 = t4[i4];
+          if ((q4.x | q4.y | q4.z | q4.w) == 0u) continue;
+          const uint32_t wd[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const uint32_t c0 = wd[c] & 0xFFFFu, c1 = wd[c] >> 16;
+            twice += (unsigned long long)(__umul24(c0, c0) - c0);
+            twice += (unsigned long long)(__umul24(c1, c1) - c1);
+          }
+          t4[i4] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        start_acc += twice >> 1;
       } else if (wdense) {
         const int32_t wn = hi_w - lo_w;
         const int32_t words = whalf ? (wn + 1) >> 1 : wn;
