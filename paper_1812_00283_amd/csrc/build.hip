@@ -169,28 +169,39 @@ __global__ void invert_kernel(const uint32_t* __restrict__ id_of, int32_t* __res
 }
 
 // keys for one side's CSR sort: (rank of source) << bits_other | rank of neighbour
+// Arc keys (rank_u << bits_dst | rank_v).  bits_idx > 0: the key is shifted
+// up by bits_idx and the edge index fills the low bits (no value array);
+// otherwise vals receives the edge index.
 __global__ void arc_keys_kernel(const int32_t* __restrict__ edges, int64_t m, int src_col,
                                 const int32_t* __restrict__ rank_src, const int32_t* __restrict__ rank_dst,
-                                int bits_dst, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                int bits_dst, int bits_idx, uint64_t* __restrict__ keys,
+                                uint32_t* __restrict__ vals) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
     const int2 e = reinterpret_cast<const int2*>(edges)[i];
     const int32_t a = src_col == 0 ? e.x : e.y;
     const int32_t b = src_col == 0 ? e.y : e.x;
-    keys[i] = ((uint64_t)(uint32_t)rank_src[a] << bits_dst) | (uint64_t)(uint32_t)rank_dst[b];
-    vals[i] = (uint32_t)i;
+    const uint64_t key = ((uint64_t)(uint32_t)rank_src[a] << bits_dst) | (uint64_t)(uint32_t)rank_dst[b];
+    if (bits_idx > 0) {
+      keys[i] = (key << bits_idx) | (uint64_t)i;
+    } else {
+      keys[i] = key;
+      vals[i] = (uint32_t)i;
+    }
   }
 }
 
 __global__ void arc_unpack_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t m,
-                                  int bits_dst, int32_t* __restrict__ adj, int32_t* __restrict__ src,
+                                  int bits_dst, int bits_idx, int32_t* __restrict__ adj, int32_t* __restrict__ src,
                                   int32_t* __restrict__ edge_of_slot, int32_t* __restrict__ status) {
   const uint64_t mask = (1ull << bits_dst) - 1ull;
+  const uint64_t imask = bits_idx > 0 ? (1ull << bits_idx) - 1ull : 0ull;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t key = keys[k];
+    const uint64_t packed = keys[k];
+    const uint64_t key = packed >> bits_idx;
     adj[k] = (int32_t)(key & mask);
     src[k] = (int32_t)(key >> bits_dst);
-    edge_of_slot[k] = (int32_t)vals[k];
-    if (k > 0 && keys[k - 1] == key) atomicOr(&status[1], 1);
+    edge_of_slot[k] = bits_idx > 0 ? (int32_t)(packed & imask) : (int32_t)vals[k];
+    if (k > 0 && (keys[k - 1] >> bits_idx) == key) atomicOr(&status[1], 1);
   }
 }
 
@@ -452,15 +463,23 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
     vals.alloc(sizeof(uint32_t) * (size_t)m, s);
     ktmp.alloc(sizeof(uint64_t) * (size_t)m, s);
     vtmp.alloc(sizeof(uint32_t) * (size_t)m, s);
+    // when the key and the edge index fit 64 bits together the sort moves
+    // keys only (8 bytes per arc and pass instead of 12)
+    const int bits_idx = bits_for((uint64_t)(m - 1));
+    const bool packed = bits[0] + bits[1] + bits_idx <= 64;
     arc_keys_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, 0, rank_of[0].as<int32_t>(), rank_of[1].as<int32_t>(),
-                                                 bits[1], keys.as<uint64_t>(), vals.as<uint32_t>());
+                                                 bits[1], packed ? bits_idx : 0, keys.as<uint64_t>(),
+                                                 vals.as<uint32_t>());
     BFC_LAUNCH_CHECK();
-    const bool in_tmp = radix_sort_u64_any(keys.as<uint64_t>(), vals.as<uint32_t>(), ktmp.as<uint64_t>(),
-                                           vtmp.as<uint32_t>(), m, bits[0] + bits[1], s);
+    const bool in_tmp =
+        packed ? radix_sort_u64_keys_any(keys.as<uint64_t>(), ktmp.as<uint64_t>(), m, bits_idx, bits[0] + bits[1], s)
+               : radix_sort_u64_any(keys.as<uint64_t>(), vals.as<uint32_t>(), ktmp.as<uint64_t>(),
+                                    vtmp.as<uint32_t>(), m, bits[0] + bits[1], s);
     arc_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(in_tmp ? ktmp.as<uint64_t>() : keys.as<uint64_t>(),
                                                  in_tmp ? vtmp.as<uint32_t>() : vals.as<uint32_t>(), m, bits[1],
-                                                 g->side[0].adj.as<int32_t>(), src[0].as<int32_t>(),
-                                                 g->edge0.as<int32_t>(), status.as<int32_t>());
+                                                 packed ? bits_idx : 0, g->side[0].adj.as<int32_t>(),
+                                                 src[0].as<int32_t>(), g->edge0.as<int32_t>(),
+                                                 status.as<int32_t>());
     BFC_LAUNCH_CHECK();
     // side 1: keys = rank_v of each side-0 slot, values = the slot
     uint32_t* k1 = reinterpret_cast<uint32_t*>(keys.p);

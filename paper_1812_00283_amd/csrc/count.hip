@@ -1281,6 +1281,22 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
           }
           t4[i4] = make_uint4(0u, 0u, 0u, 0u);
         }
+      } else if (wpacked && mode != kVertex) {
+        // c (c - 1) of the 12-bit counts, branch-free (see the dense case); cap >= 512 is a multiple of 4
+        uint4* t4 = reinterpret_cast<uint4*>(table);
+        unsigned long long twice = 0;
+        for (uint32_t i4 = t; i4 < cap / 4; i4 += kNT) {
+          const uint4 q4 = t4[i4];
+          if ((q4.x | q4.y | q4.z | q4.w) == 0u) continue;
+          const uint32_t wd[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const uint32_t n = wd[c] & kPackMask;
+            twice += (unsigned long long)(__umul24(n, n) - n);
+          }
+          t4[i4] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        start_acc += twice >> 1;
       } else if (wpacked) {
         uint32_t* pt = reinterpret_cast<uint32_t*>(table);
         for (uint32_t h = t; h < cap; h += kNT) {

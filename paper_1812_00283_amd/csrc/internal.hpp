@@ -211,6 +211,9 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t
 // returns true when that is (keys_tmp, vals_tmp).
 bool radix_sort_u64_any(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, int64_t n, int bits,
                         hipStream_t s);
+// Keys only, on key bits [lo_bit, lo_bit + bits) (lower bits ride along);
+// same return convention.
+bool radix_sort_u64_keys_any(uint64_t* keys, uint64_t* keys_tmp, int64_t n, int lo_bit, int bits, hipStream_t s);
 
 // ------------------------------------------------------------ build and count
 // groups (batches): per layer, G + 1 device offsets of each graph's ids;

@@ -122,7 +122,8 @@ __global__ __launch_bounds__(kSortNT) void sort_hist_kernel(const K* __restrict_
   if (threadIdx.x < 256) counts[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-template <typename K>
+// kVals false: keys only (vin and vout unused).
+template <typename K, bool kVals>
 __global__ __launch_bounds__(kSortNT) void sort_scatter_kernel(const K* __restrict__ kin,
                                                                const uint32_t* __restrict__ vin,
                                                                K* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(kSortNT) void sort_scatter_kernel(const K* __restri
   __shared__ uint32_t goff[256];
   __shared__ uint32_t red[kSortWaves + 1];
   __shared__ K skey[kSortTile];
-  __shared__ uint32_t sval[kSortTile];
+  __shared__ uint32_t sval[kVals ? kSortTile : 1];
 
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(kSortNT) void sort_scatter_kernel(const K* __restri
     const int64_t idx = tile0 + (int64_t)w * kPerWave + j * 64 + lane;
     const bool valid = idx < n;
     k[j] = valid ? kin[idx] : K(0);
-    v[j] = valid ? vin[idx] : 0u;
+    v[j] = (kVals && valid) ? vin[idx] : 0u;
     const uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(kSortNT) void sort_scatter_kernel(const K* __restri
       const uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
       const uint32_t pos = dstart[d] + wcnt[w][d] + r[j];
       skey[pos] = k[j];
-      sval[pos] = v[j];
+      if (kVals) sval[pos] = v[j];
     }
   }
   __syncthreads();
@@ -203,14 +204,15 @@ __global__ __launch_bounds__(kSortNT) void sort_scatter_kernel(const K* __restri
     const uint32_t d = (uint32_t)(kk >> shift) & 255u;
     const int64_t dst = (int64_t)goff[d] + (p - (int64_t)dstart[d]);
     kout[dst] = kk;
-    vout[dst] = sval[p];
+    if (kVals) vout[dst] = sval[p];
   }
 }
 
+// Sorts on key bits [lo_bit, lo_bit + bits); vals may be null (keys only).
 // Returns true when the sorted data ends in (ktmp, vtmp) (copy_back false).
 template <typename K>
 bool radix_sort_impl(K* keys, uint32_t* vals, K* ktmp, uint32_t* vtmp, int64_t n, int bits, hipStream_t s,
-                     bool copy_back = true) {
+                     bool copy_back = true, int lo_bit = 0) {
   if (n <= 1 || bits <= 0) return false;
   const int64_t tiles = (n + kSortTile - 1) / kSortTile;
   uint32_t* counts = nullptr;
@@ -219,11 +221,14 @@ bool radix_sort_impl(K* keys, uint32_t* vals, K* ktmp, uint32_t* vtmp, int64_t n
   K* kd = ktmp;
   uint32_t* vs = vals;
   uint32_t* vd = vtmp;
-  for (int shift = 0; shift < bits; shift += 8) {
+  for (int shift = lo_bit; shift < lo_bit + bits; shift += 8) {
     sort_hist_kernel<K><<<(unsigned)tiles, kSortNT, 0, s>>>(ks, n, shift, counts, tiles);
     BFC_LAUNCH_CHECK();
     exclusive_scan_impl<uint32_t>(counts, counts, 256 * tiles, nullptr, s);
-    sort_scatter_kernel<K><<<(unsigned)tiles, kSortNT, 0, s>>>(ks, vs, kd, vd, n, shift, counts, tiles);
+    if (vals)
+      sort_scatter_kernel<K, true><<<(unsigned)tiles, kSortNT, 0, s>>>(ks, vs, kd, vd, n, shift, counts, tiles);
+    else
+      sort_scatter_kernel<K, false><<<(unsigned)tiles, kSortNT, 0, s>>>(ks, vs, kd, vd, n, shift, counts, tiles);
     BFC_LAUNCH_CHECK();
     K* tk = ks; ks = kd; kd = tk;
     uint32_t* tv = vs; vs = vd; vd = tv;
@@ -231,7 +236,7 @@ bool radix_sort_impl(K* keys, uint32_t* vals, K* ktmp, uint32_t* vtmp, int64_t n
   const bool in_tmp = ks != keys;
   if (in_tmp && copy_back) {
     BFC_HIP(hipMemcpyAsync(keys, ks, sizeof(K) * (size_t)n, hipMemcpyDeviceToDevice, s));
-    BFC_HIP(hipMemcpyAsync(vals, vs, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    if (vals) BFC_HIP(hipMemcpyAsync(vals, vs, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
   }
   cache_free(counts, s);
   return in_tmp && !copy_back;
@@ -259,6 +264,9 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* ktmp, uint32_t* vt
 bool radix_sort_u64_any(uint64_t* keys, uint32_t* vals, uint64_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
                         hipStream_t s) {
   return radix_sort_impl<uint64_t>(keys, vals, ktmp, vtmp, n, bits, s, false);
+}
+bool radix_sort_u64_keys_any(uint64_t* keys, uint64_t* ktmp, int64_t n, int lo_bit, int bits, hipStream_t s) {
+  return radix_sort_impl<uint64_t>(keys, nullptr, ktmp, nullptr, n, bits, s, false, lo_bit);
 }
 
 }  // namespace bfc
