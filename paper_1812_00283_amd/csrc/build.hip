@@ -140,22 +140,30 @@ __global__ __launch_bounds__(kPartNT) void part_scatter_kernel(const int32_t* __
   }
 }
 
+// kDegSplit workgroups share a bucket: each counts a slice of its ids in
+// LDS and adds its non-zero counts to the (zeroed) degrees.
+constexpr int kDegSplit = 8;
 __global__ __launch_bounds__(kPartNT) void part_degree_kernel(const int32_t* __restrict__ part,
                                                               const uint32_t* __restrict__ off, int32_t BU,
                                                               int32_t nU, int32_t nL, int32_t* __restrict__ degU,
                                                               int32_t* __restrict__ degL) {
   __shared__ uint32_t h[kBucketIds];
-  const int b = blockIdx.x;
+  const int b = blockIdx.x / kDegSplit;
+  const int sp = blockIdx.x % kDegSplit;
   const bool lower = b >= BU;
   const int32_t id0 = (lower ? b - BU : b) << kBucketShift;
   const int32_t n = lower ? nL : nU;
   const int32_t w = n - id0 < kBucketIds ? n - id0 : kBucketIds;
   for (int i = threadIdx.x; i < w; i += kPartNT) h[i] = 0;
   __syncthreads();
-  for (uint32_t i = off[b] + threadIdx.x; i < off[b + 1]; i += kPartNT) atomicAdd(&h[part[i] - id0], 1u);
+  const uint32_t a0 = off[b], len = off[b + 1] - a0;
+  const uint32_t s0 = a0 + (uint32_t)((uint64_t)len * sp / kDegSplit);
+  const uint32_t s1 = a0 + (uint32_t)((uint64_t)len * (sp + 1) / kDegSplit);
+  for (uint32_t i = s0 + threadIdx.x; i < s1; i += kPartNT) atomicAdd(&h[part[i] - id0], 1u);
   __syncthreads();
   int32_t* deg = lower ? degL : degU;
-  for (int i = threadIdx.x; i < w; i += kPartNT) deg[id0 + i] = (int32_t)h[i];
+  for (int i = threadIdx.x; i < w; i += kPartNT)
+    if (h[i]) atomicAdd(&deg[id0 + i], (int32_t)h[i]);
 }
 
 __global__ void iota_kernel(uint32_t* __restrict__ a, int64_t n) {
@@ -384,7 +392,7 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
                                                   fill.as<uint32_t>(), part.as<int32_t>());
     BFC_LAUNCH_CHECK();
     if (nb > 0) {
-      part_degree_kernel<<<(unsigned)nb, kPartNT, 0, s>>>(part.as<int32_t>(), cnt.as<uint32_t>(), BU, n[0], n[1],
+      part_degree_kernel<<<(unsigned)nb * kDegSplit, kPartNT, 0, s>>>(part.as<int32_t>(), cnt.as<uint32_t>(), BU, n[0], n[1],
                                                           deg[0].as<int32_t>(), deg[1].as<int32_t>());
       BFC_LAUNCH_CHECK();
     }
