@@ -134,8 +134,8 @@ bfc_status bfc_build(const int32_t* edges_dev, int64_t m, int32_t n_upper, int32
       g->n_lower = n_lower;
       build_graph(g, edges_dev, s);
       build_schedule(g, s);
+      finish_schedule(g, s);
       prepare_count(g, s);
-      BFC_HIP(hipStreamSynchronize(s));
     } catch (...) {
       // let queued build work finish before its buffers return to the cache
       (void)hipStreamSynchronize(s);
@@ -191,8 +191,8 @@ bfc_status bfc_build_batch(const int32_t* edges_dev, const int64_t* edge_offsets
       BFC_HIP(hipEventCreateWithFlags(&g->done, hipEventDisableTiming));
       build_batch(g, edges_dev, edge_offsets_host, n_upper_host, n_lower_host, G, s);
       build_schedule(g, s);
+      finish_schedule(g, s);
       prepare_count(g, s);
-      BFC_HIP(hipStreamSynchronize(s));
     } catch (...) {
       // let queued build work finish before its buffers return to the cache
       (void)hipStreamSynchronize(s);
@@ -370,6 +370,7 @@ bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t) {
       if (h->used) BFC_HIP(hipEventSynchronize(h->done));
       BFC_HIP(hipDeviceSynchronize());
       build_schedule(h, nullptr);
+      finish_schedule(h, nullptr);
       prepare_count(h, nullptr);
       BFC_HIP(hipStreamSynchronize(nullptr));
     }

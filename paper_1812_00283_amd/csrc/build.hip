@@ -248,13 +248,15 @@ __global__ void transpose_unpack_kernel(const uint32_t* __restrict__ key, const 
 // priority, a prefix of N(r): deg(v) <= deg(r) across the layers, ties to
 // the lower layer) and work[r] = the wedges Algorithm 2 walks from r, the
 // sum over middles of v's neighbours below r (rev[k] - off_other[v]).
+// Degrees are differences of adjacent CSR offsets, so the other layer's
+// offset and degree come from one cache line per arc.
 // Arc-parallel over the side's CSR, whose starts ascend: a wavefront sums
 // its 64 arcs per run of equal start (segmented scan) and the run's last
 // lane adds the sums with one atomic each (lo and work start at zero).
 __global__ void start_stats_kernel(int64_t m, int x, const int32_t* __restrict__ src,
                                    const int32_t* __restrict__ adj, const int32_t* __restrict__ rev,
-                                   const int32_t* __restrict__ off_other, const int32_t* __restrict__ deg_self,
-                                   const int32_t* __restrict__ deg_other, int32_t* __restrict__ lo,
+                                   const int32_t* __restrict__ off_self, const int32_t* __restrict__ off_other,
+                                   int32_t* __restrict__ lo,
                                    unsigned long long* __restrict__ work) {
   const int lane = __lane_id();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -265,10 +267,11 @@ __global__ void start_stats_kernel(int64_t m, int x, const int32_t* __restrict__
     if (k < m) {
       r = src[k];
       const int32_t v = adj[k];
-      const int32_t ds = deg_self[r], dv = deg_other[v];
+      const int32_t ov = off_other[v];
+      const int32_t ds = off_self[r + 1] - off_self[r], dv = off_other[v + 1] - ov;
       if (x == 0 ? dv <= ds : dv < ds) {
         f = 1;
-        w = (unsigned long long)(rev[k] - off_other[v]);
+        w = (unsigned long long)(rev[k] - ov);
       }
     }
     // run boundaries: a lane heads a run when its start differs from the lane below
@@ -360,15 +363,30 @@ __global__ void window_table_kernel(const int32_t* __restrict__ off, const int32
   }
 }
 
+// Largest of n degrees into *out (atomic max; *out starts at 0).
+__global__ void max_kernel(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ out) {
+  int32_t mx = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    mx = a[i] > mx ? a[i] : mx;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const int32_t o = __shfl_xor(mx, d, 64);
+    mx = o > mx ? o : mx;
+  }
+  if (__lane_id() == 0 && mx) atomicMax(out, mx);
+}
+
 }  // namespace
 
 void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int32_t* const* groups, int32_t G) {
   const int64_t m = g->m;
   const int32_t n[2] = {g->n_upper, g->n_lower};
 
-  TmpBuf status;
-  status.alloc(4 * sizeof(int32_t), s);
-  BFC_HIP(hipMemsetAsync(status.p, 0, 4 * sizeof(int32_t), s));
+  // status: [0] id out of range, [1] duplicate edge, [2 + o] first table row of layer o,
+  // [4 + x] largest degree of layer x
+  g->info.alloc(256, s);
+  BFC_HIP(hipMemsetAsync(g->info.p, 0, 256, s));
+  DevBuf& status = g->info;
   TmpBuf deg[2];
   for (int x = 0; x < 2; ++x) {
     deg[x].alloc(sizeof(int32_t) * (size_t)(n[x] + 1), s);
@@ -403,7 +421,13 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
                                                    status.as<int32_t>());
     BFC_LAUNCH_CHECK();
   }
-  int32_t st[4] = {0, 0, 0, 0};
+  for (int x = 0; x < 2; ++x) {
+    if (n[x] == 0) continue;
+    const int64_t grid = n[x] / 256 + 1 < 1024 ? n[x] / 256 + 1 : 1024;
+    max_kernel<<<(unsigned)grid, 256, 0, s>>>(deg[x].as<int32_t>(), n[x], status.as<int32_t>() + 4 + x);
+    BFC_LAUNCH_CHECK();
+  }
+  int32_t st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   BFC_HIP(hipMemcpyAsync(st, status.p, sizeof(st), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
   if (st[0]) throw Error{BFC_ERR_VERTEX_OUT_OF_RANGE, "an edge has an upper id outside [0,n_upper) or a lower id outside [0,n_lower)"};
@@ -423,8 +447,8 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
     if (nx > 0) {
       iota_kernel<<<grid_1d(nx), 256, 0, s>>>(vals.as<uint32_t>(), nx);
       BFC_LAUNCH_CHECK();
-      const int64_t max_deg = m < n[1 - x] ? m : n[1 - x];
-      const int db = bits_for((uint64_t)max_deg);
+      // the priority keys are the degrees: sort on the bits of the largest
+      const int db = bits_for((uint64_t)st[4 + x]);
       if (groups && G > 1) {
         // batch: sort by (graph, degree); the degrees in rank order are the keys' low bits
         TmpBuf key, key_tmp;
@@ -516,9 +540,9 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
       int64_t grid = (m + 255) / 256;
       if (grid > 8192) grid = 8192;
       start_stats_kernel<<<(unsigned)grid, 256, 0, s>>>(m, x, src[x].as<int32_t>(), sd.adj.as<int32_t>(),
-                                                        sd.rev.as<int32_t>(), g->side[1 - x].off.as<int32_t>(),
-                                                        deg_rank[x].as<int32_t>(), deg_rank[1 - x].as<int32_t>(),
-                                                        sd.lo.as<int32_t>(), sd.work.as<unsigned long long>());
+                                                        sd.rev.as<int32_t>(), sd.off.as<int32_t>(),
+                                                        g->side[1 - x].off.as<int32_t>(), sd.lo.as<int32_t>(),
+                                                        sd.work.as<unsigned long long>());
       BFC_LAUNCH_CHECK();
     }
   }
@@ -540,14 +564,9 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
         status.as<int32_t>() + 2 + o, g->wt[o].as<int32_t>());
     BFC_LAUNCH_CHECK();
   }
-  BFC_HIP(hipMemcpyAsync(st, status.p, sizeof(st), hipMemcpyDeviceToHost, s));
-  BFC_HIP(hipStreamSynchronize(s));
-  if (st[1]) throw Error{BFC_ERR_DUPLICATE_EDGE, "the edge list repeats an (upper, lower) pair"};
-  for (int o = 0; o < 2; ++o) {
-    if (rows_max[o] <= 0) continue;
-    const int32_t lo = (int32_t)(n[o] - rows_max[o]);
-    g->wt_first[o] = st[2 + o] > lo ? st[2 + o] : lo;
-  }
+  // duplicates and the tables' first rows are read by finish_schedule
+  g->rows_max[0] = rows_max[0];
+  g->rows_max[1] = rows_max[1];
 }
 
 // ---------------------------------------------------------------- schedule
@@ -637,10 +656,15 @@ __global__ void compact_kernel(const int64_t* __restrict__ is_light, const int32
                                const int32_t* __restrict__ lo1, const int32_t* __restrict__ off0,
                                const int32_t* __restrict__ off1, int64_t medium_max, int32_t KU, int32_t KL,
                                int4* __restrict__ light, int32_t* __restrict__ heavy,
-                               uint32_t* __restrict__ heavy_key, unsigned long long* __restrict__ n_medium) {
+                               uint32_t* __restrict__ heavy_key, unsigned long long* __restrict__ n_medium,
+                               long long* __restrict__ counts) {
   const int64_t n = (int64_t)n0 + n1;
   // the small light starts come first, then the other light starts
   const int32_t n_small = (int32_t)(pos_light[n] & 0xFFFFFFFFll);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    counts[0] = pos_light[n];
+    counts[1] = pos_heavy[n];
+  }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t code = i < n0 ? (int32_t)i : (int32_t)((1u << 30) | (uint32_t)(i - n0));
     const int64_t fl = is_light[i];
@@ -658,9 +682,10 @@ __global__ void compact_kernel(const int64_t* __restrict__ is_light, const int32
       const int32_t pre = i < n0 ? lo0[i] : lo1[i - n0];
       const bool in_block = i < n0 ? i > (int64_t)n0 - KU : (i - n0) > (int64_t)n1 - KL;
       med = medium_max > 0 && w <= medium_max && pre <= kMediumMaxPre && !in_block;
-      const uint32_t wc = w < 0x7FFFFFFF ? (uint32_t)w : 0x7FFFFFFFu;
+      // ascending keys: big starts by decreasing work (steps of 2^(1/512)), then medium ones
+      const int32_t lg = (int32_t)(512.0f * log2f((float)w));
       heavy[pos_heavy[i]] = code;
-      heavy_key[pos_heavy[i]] = (med ? 0x80000000u : 0u) | (0x7FFFFFFFu - wc);  // ascending = big first, less work later
+      heavy_key[pos_heavy[i]] = (med ? 0x8000u : 0u) | (uint32_t)(32767 - (lg < 32767 ? lg : 32767));
     }
     const uint64_t mb = __ballot(med);
     if (__lane_id() == 0 && mb) atomicAdd(n_medium, (unsigned long long)__popcll(mb));
@@ -669,10 +694,12 @@ __global__ void compact_kernel(const int64_t* __restrict__ is_light, const int32
 
 // Heavy list entries {code, off[rank], lo[rank], wedges (clamped to int32)}
 // in the sorted order of the codes.
-__global__ void heavy_entries_kernel(const uint32_t* __restrict__ codes, int32_t n, const int32_t* __restrict__ off0,
+__global__ void heavy_entries_kernel(const uint32_t* __restrict__ codes, const int32_t* __restrict__ n_dev,
+                                     const int32_t* __restrict__ off0,
                                      const int32_t* __restrict__ off1, const int32_t* __restrict__ lo0,
                                      const int32_t* __restrict__ lo1, const int64_t* __restrict__ work0,
                                      const int64_t* __restrict__ work1, int4* __restrict__ out) {
+  const int32_t n = *n_dev;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t code = (int32_t)codes[i];
     const int x = (int)((uint32_t)code >> 30);
@@ -688,13 +715,15 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   Schedule& sc = g->sched;
   const int32_t n0 = g->side[0].n, n1 = g->side[1].n;
   const int64_t n = (int64_t)n0 + n1;
-  TmpBuf flags_l, flags_h, pos_l, pos_h, sums;
+  // totals go to g->info from byte 64: [0..7] the classify sums, [7] medium
+  // starts, [8] light counts (small | other << 32), [9] heavy starts
+  unsigned long long* sums = reinterpret_cast<unsigned long long*>(g->info.as<char>() + 64);
+  BFC_HIP(hipMemsetAsync(sums, 0, 16 * sizeof(int64_t), s));
+  TmpBuf flags_l, flags_h, pos_l, pos_h;
   flags_l.alloc(sizeof(int64_t) * (size_t)n, s);
   flags_h.alloc(sizeof(int32_t) * (size_t)n, s);
   pos_l.alloc(sizeof(int64_t) * (size_t)(n + 1), s);
   pos_h.alloc(sizeof(int32_t) * (size_t)(n + 1), s);
-  sums.alloc(8 * sizeof(int64_t), s);
-  BFC_HIP(hipMemsetAsync(sums.p, 0, 8 * sizeof(int64_t), s));
   const int64_t light_max = g->tune.light_max_wedges;
   const int32_t K = g->tune.dense_block;
   int32_t KU = K > 0 ? (K < n0 ? K : n0) : 0;
@@ -704,62 +733,84 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
     classify_kernel<<<grid_1d(n) < 1024 ? grid_1d(n) : 1024, kClassifyNT, 0, s>>>(g->side[0].work.as<int64_t>(), g->side[0].lo.as<int32_t>(), n0,
                                                 g->side[1].work.as<int64_t>(), g->side[1].lo.as<int32_t>(), n1,
                                                 light_max, KU, KL, flags_l.as<int64_t>(), flags_h.as<int32_t>(),
-                                                sums.as<unsigned long long>());
+                                                sums);
     BFC_LAUNCH_CHECK();
   }
   exclusive_scan_i64(flags_l.as<int64_t>(), pos_l.as<int64_t>(), n, pos_l.as<int64_t>() + n, s);
   exclusive_scan_i32(flags_h.as<int32_t>(), pos_h.as<int32_t>(), n, pos_h.as<int32_t>() + n, s);
-  int64_t light_counts = 0;
-  int32_t heavy_count = 0;
-  int64_t wsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  BFC_HIP(hipMemcpyAsync(&light_counts, pos_l.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  BFC_HIP(hipMemcpyAsync(&heavy_count, pos_h.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  BFC_HIP(hipMemcpyAsync(wsum, sums.p, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  BFC_HIP(hipStreamSynchronize(s));
-  sc.n_small = (int32_t)(light_counts & 0xFFFFFFFFll);
-  sc.n_light = sc.n_small + (int32_t)(light_counts >> 32);
-  sc.n_heavy = heavy_count;
-  sc.wedges = wsum[0];
-  sc.max_prefix = (int32_t)wsum[1];
-  sc.wedges_light = wsum[2];
-  sc.wedges_heavy = wsum[3];
-  sc.middles_light = wsum[4];
-  sc.middles_heavy = wsum[5];
-  sc.max_start_wedges = wsum[6];
-  sc.light_max = g->tune.light_max_wedges;
-  sc.light.alloc(sizeof(int4) * (size_t)sc.n_light, s);
-  sc.heavy.alloc(sizeof(int4) * (size_t)sc.n_heavy, s);
+  // the list sizes are known once the build is read back: size the lists
+  // for every start (finish_schedule trims them)
+  sc.light.alloc(sizeof(int4) * (size_t)n, s);
+  sc.heavy.alloc(sizeof(int4) * (size_t)n, s);
   TmpBuf hkey, hkey_tmp, hval_tmp, hcode;
-  hcode.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
-  hkey.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
-  hkey_tmp.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
-  hval_tmp.alloc(sizeof(uint32_t) * (size_t)sc.n_heavy, s);
+  hcode.alloc(sizeof(uint32_t) * (size_t)n, s);
+  hkey.alloc(sizeof(uint32_t) * (size_t)n, s);
+  hkey_tmp.alloc(sizeof(uint32_t) * (size_t)n, s);
+  hval_tmp.alloc(sizeof(uint32_t) * (size_t)n, s);
   if (n > 0) {
+    BFC_HIP(hipMemsetAsync(hkey.p, 0xFF, sizeof(uint32_t) * (size_t)n, s));  // past the heavy starts: key 0xFFFF...
     compact_kernel<<<grid_1d(n), 256, 0, s>>>(flags_l.as<int64_t>(), flags_h.as<int32_t>(), pos_l.as<int64_t>(),
                                                pos_h.as<int32_t>(), n0, n1, g->side[0].work.as<int64_t>(),
                                                g->side[1].work.as<int64_t>(), g->side[0].lo.as<int32_t>(),
                                                g->side[1].lo.as<int32_t>(), g->side[0].off.as<int32_t>(),
                                                g->side[1].off.as<int32_t>(), (int64_t)g->tune.medium_max_wedges, KU,
-                                               KL, sc.light.as<int4>(), hcode.as<int32_t>(),
-                                               hkey.as<uint32_t>(), sums.as<unsigned long long>() + 7);
+                                               KL, sc.light.as<int4>(), hcode.as<int32_t>(), hkey.as<uint32_t>(),
+                                               sums + 7, reinterpret_cast<long long*>(sums + 8));
     BFC_LAUNCH_CHECK();
-  }
-  if (sc.n_heavy > 1) {
-    radix_sort_u32(hkey.as<uint32_t>(), hcode.as<uint32_t>(), hkey_tmp.as<uint32_t>(), hval_tmp.as<uint32_t>(),
-                   sc.n_heavy, 32, s);
-  }
-  if (sc.n_heavy > 0) {
-    heavy_entries_kernel<<<grid_1d(sc.n_heavy), 256, 0, s>>>(
-        hcode.as<uint32_t>(), sc.n_heavy, g->side[0].off.as<int32_t>(), g->side[1].off.as<int32_t>(),
+    // heavy starts first, in key order (16-bit keys)
+    if (n > 1)
+      radix_sort_u32(hkey.as<uint32_t>(), hcode.as<uint32_t>(), hkey_tmp.as<uint32_t>(), hval_tmp.as<uint32_t>(), n,
+                     16, s);
+    heavy_entries_kernel<<<grid_1d(n), 256, 0, s>>>(
+        hcode.as<uint32_t>(), pos_h.as<int32_t>() + n, g->side[0].off.as<int32_t>(), g->side[1].off.as<int32_t>(),
         g->side[0].lo.as<int32_t>(), g->side[1].lo.as<int32_t>(), g->side[0].work.as<int64_t>(),
         g->side[1].work.as<int64_t>(), sc.heavy.as<int4>());
     BFC_LAUNCH_CHECK();
   }
-  int64_t n_medium = 0;
-  BFC_HIP(hipMemcpyAsync(&n_medium, sums.as<int64_t>() + 7, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+}
+
+namespace {
+// Replaces b's block by a copy of its first `bytes` bytes (stream-ordered).
+void trim(DevBuf& b, size_t bytes, hipStream_t s) {
+  if (bytes == 0) bytes = 256;
+  if (bytes >= b.bytes) return;
+  void* p = cache_alloc(bytes, s);
+  BFC_HIP(hipMemcpyAsync(p, b.p, bytes, hipMemcpyDeviceToDevice, s));
+  cache_free(b.p, s);
+  b.p = p;
+  b.bytes = bytes;
+}
+}  // namespace
+
+void finish_schedule(bfc_graph_s* g, hipStream_t s) {
+  Schedule& sc = g->sched;
+  int32_t st[16];
+  int64_t t[16];
+  BFC_HIP(hipMemcpyAsync(st, g->info.p, sizeof(st), hipMemcpyDeviceToHost, s));
+  BFC_HIP(hipMemcpyAsync(t, g->info.as<char>() + 64, sizeof(t), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
-  sc.n_medium = (int32_t)n_medium;
+  if (st[1]) throw Error{BFC_ERR_DUPLICATE_EDGE, "the edge list repeats an (upper, lower) pair"};
+  const int32_t nn[2] = {g->side[0].n, g->side[1].n};
+  for (int o = 0; o < 2; ++o) {
+    if (g->rows_max[o] <= 0) continue;
+    const int32_t lo = (int32_t)(nn[o] - g->rows_max[o]);
+    g->wt_first[o] = st[2 + o] > lo ? st[2 + o] : lo;
+  }
+  sc.wedges = t[0];
+  sc.max_prefix = (int32_t)t[1];
+  sc.wedges_light = t[2];
+  sc.wedges_heavy = t[3];
+  sc.middles_light = t[4];
+  sc.middles_heavy = t[5];
+  sc.max_start_wedges = t[6];
+  sc.n_medium = (int32_t)t[7];
+  sc.n_small = (int32_t)(t[8] & 0xFFFFFFFFll);
+  sc.n_light = sc.n_small + (int32_t)(t[8] >> 32);
+  sc.n_heavy = (int32_t)t[9];
+  sc.light_max = g->tune.light_max_wedges;
   sc.medium_max = g->tune.medium_max_wedges;
+  trim(sc.light, sizeof(int4) * (size_t)sc.n_light, s);
+  trim(sc.heavy, sizeof(int4) * (size_t)sc.n_heavy, s);
 }
 
 // ---------------------------------------------------------------- batches

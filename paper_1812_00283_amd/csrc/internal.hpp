@@ -167,6 +167,10 @@ struct bfc_graph_s {
   int32_t n_graphs = 1;
   bfc::DevBuf gid[2];
   bfc::DevBuf grank[2];   // per layer: first rank of each graph (G + 1), batches only
+  // build status (int32 [8]) and schedule totals (int64 [16] from byte 64),
+  // read back once when the build is complete
+  bfc::DevBuf info;
+  int64_t rows_max[2] = {0, 0};  // window-table rows allocated per layer
   std::vector<int64_t> graph_wedges;
   // captured total count
   hipGraph_t cap_graph = nullptr;
@@ -222,6 +226,9 @@ bool radix_sort_u64_keys_any(uint64_t* keys, uint64_t* keys_tmp, int64_t n, int 
 void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int32_t* const* groups = nullptr,
                  int32_t G = 0);
 void build_schedule(bfc_graph_s* g, hipStream_t s);
+// Waits for the build and schedule queued on s and reads their results
+// (throws on a duplicate edge).  The only wait after the degree check.
+void finish_schedule(bfc_graph_s* g, hipStream_t s);
 
 enum CountMode { kTotal = 0, kVertex = 1, kEdge = 2 };
 // Runs the wedge kernels.  kTotal: adds B_G into total_dev.  kVertex: adds
