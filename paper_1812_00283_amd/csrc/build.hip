@@ -225,6 +225,26 @@ __global__ void transpose_keys_kernel(const int32_t* __restrict__ adj0, int64_t 
 // Side-1 slot k1 holds the arc of side-0 slot s0 = val[k1]: start rank_v =
 // key[k1], neighbour rank_u = src0[s0]; the two reverse slots point at each
 // other.
+// Packed transpose: key (v << (bu + bs)) | (u << bs) | s0 per side-0 slot
+// s0 = (u, v); sorted on its v bits, it yields side 1 without gathers.
+__global__ void transpose_keys_packed_kernel(const int32_t* __restrict__ adj0, const int32_t* __restrict__ src0,
+                                             int64_t m, int bu, int bs, uint64_t* __restrict__ key) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
+    key[k] = ((uint64_t)(uint32_t)adj0[k] << (bu + bs)) | ((uint64_t)(uint32_t)src0[k] << bs) | (uint64_t)k;
+}
+__global__ void transpose_unpack_packed_kernel(const uint64_t* __restrict__ key, int64_t m, int bu, int bs,
+                                               int32_t* __restrict__ adj1, int32_t* __restrict__ src1,
+                                               int32_t* __restrict__ rev1, int32_t* __restrict__ rev0) {
+  const uint64_t smask = (1ull << bs) - 1ull, umask = (1ull << bu) - 1ull;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t kk = key[k];
+    const int32_t s0 = (int32_t)(kk & smask);
+    src1[k] = (int32_t)(kk >> (bu + bs));
+    adj1[k] = (int32_t)((kk >> bs) & umask);
+    rev1[k] = s0;
+    rev0[s0] = (int32_t)k;
+  }
+}
 __global__ void transpose_unpack_kernel(const uint32_t* __restrict__ key, const uint32_t* __restrict__ val,
                                         const int32_t* __restrict__ src0, int64_t m, int32_t* __restrict__ adj1,
                                         int32_t* __restrict__ src1, int32_t* __restrict__ rev1,
@@ -513,18 +533,31 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
                                                  src[0].as<int32_t>(), g->edge0.as<int32_t>(),
                                                  status.as<int32_t>());
     BFC_LAUNCH_CHECK();
-    // side 1: keys = rank_v of each side-0 slot, values = the slot
-    uint32_t* k1 = reinterpret_cast<uint32_t*>(keys.p);
-    uint32_t* v1 = vals.as<uint32_t>();
-    uint32_t* k1t = reinterpret_cast<uint32_t*>(ktmp.p);
-    uint32_t* v1t = vtmp.as<uint32_t>();
-    transpose_keys_kernel<<<grid_1d(m), 256, 0, s>>>(g->side[0].adj.as<int32_t>(), m, k1, v1);
-    BFC_LAUNCH_CHECK();
-    radix_sort_u32(k1, v1, k1t, v1t, m, bits[1], s);
-    transpose_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(k1, v1, src[0].as<int32_t>(), m, g->side[1].adj.as<int32_t>(),
-                                                       src[1].as<int32_t>(), g->side[1].rev.as<int32_t>(),
-                                                       g->side[0].rev.as<int32_t>());
-    BFC_LAUNCH_CHECK();
+    if (packed) {
+      // side 1: one 64-bit key per side-0 slot carrying (v, u, slot), sorted on v
+      transpose_keys_packed_kernel<<<grid_1d(m), 256, 0, s>>>(g->side[0].adj.as<int32_t>(), src[0].as<int32_t>(), m,
+                                                              bits[0], bits_idx, keys.as<uint64_t>());
+      BFC_LAUNCH_CHECK();
+      const bool t_tmp =
+          radix_sort_u64_keys_any(keys.as<uint64_t>(), ktmp.as<uint64_t>(), m, bits[0] + bits_idx, bits[1], s);
+      transpose_unpack_packed_kernel<<<grid_1d(m), 256, 0, s>>>(
+          t_tmp ? ktmp.as<uint64_t>() : keys.as<uint64_t>(), m, bits[0], bits_idx, g->side[1].adj.as<int32_t>(),
+          src[1].as<int32_t>(), g->side[1].rev.as<int32_t>(), g->side[0].rev.as<int32_t>());
+      BFC_LAUNCH_CHECK();
+    } else {
+      // side 1: keys = rank_v of each side-0 slot, values = the slot
+      uint32_t* k1 = reinterpret_cast<uint32_t*>(keys.p);
+      uint32_t* v1 = vals.as<uint32_t>();
+      uint32_t* k1t = reinterpret_cast<uint32_t*>(ktmp.p);
+      uint32_t* v1t = vtmp.as<uint32_t>();
+      transpose_keys_kernel<<<grid_1d(m), 256, 0, s>>>(g->side[0].adj.as<int32_t>(), m, k1, v1);
+      BFC_LAUNCH_CHECK();
+      radix_sort_u32(k1, v1, k1t, v1t, m, bits[1], s);
+      transpose_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(k1, v1, src[0].as<int32_t>(), m,
+                                                         g->side[1].adj.as<int32_t>(), src[1].as<int32_t>(),
+                                                         g->side[1].rev.as<int32_t>(), g->side[0].rev.as<int32_t>());
+      BFC_LAUNCH_CHECK();
+    }
   }
 
   // ---- per start: lower-priority prefix length and wedges
