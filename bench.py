@@ -37,9 +37,9 @@ DEFAULT_WORKLOAD = "chunglu-1m-500k-20m"
 # hash to the value they were measured with (any change voids the figure).
 HEAVY_TRAFFIC = {
     "workload": DEFAULT_WORKLOAD,
-    "sources_sha256": "153344fdc4cf49a8f2010d4c1116c95278fc811fce098df909a7c572656eb91c",
-    "fetch_kib": 16666189.9,
-    "write_kib": 1457497.0,
+    "sources_sha256": "37d0b4bb750ef171fd6a3b132d586103e6014d353491b1cf53498bbba2658ac1",
+    "fetch_kib": 17197687.4,
+    "write_kib": 1671001.3,
     "fetch_factor": 2.0,
     "write_factor": 1.0,
 }

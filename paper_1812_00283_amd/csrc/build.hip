@@ -383,8 +383,11 @@ __global__ void window_table_kernel(const int32_t* __restrict__ off, const int32
   }
 }
 
-// Largest of n degrees into *out (atomic max; *out starts at 0).
-__global__ void max_kernel(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ out) {
+// Largest of n degrees into *out (one atomic max per workgroup of 256
+// threads; *out starts at 0).
+__global__ __launch_bounds__(256) void max_kernel(const int32_t* __restrict__ a, int64_t n,
+                                                  int32_t* __restrict__ out) {
+  __shared__ int32_t red[4];
   int32_t mx = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     mx = a[i] > mx ? a[i] : mx;
@@ -393,7 +396,13 @@ __global__ void max_kernel(const int32_t* __restrict__ a, int64_t n, int32_t* __
     const int32_t o = __shfl_xor(mx, d, 64);
     mx = o > mx ? o : mx;
   }
-  if (__lane_id() == 0 && mx) atomicMax(out, mx);
+  if (__lane_id() == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int32_t m0 = red[0] > red[1] ? red[0] : red[1], m1 = red[2] > red[3] ? red[2] : red[3];
+    const int32_t m = m0 > m1 ? m0 : m1;
+    if (m) atomicMax(out, m);
+  }
 }
 
 }  // namespace
@@ -443,7 +452,7 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
   }
   for (int x = 0; x < 2; ++x) {
     if (n[x] == 0) continue;
-    const int64_t grid = n[x] / 256 + 1 < 1024 ? n[x] / 256 + 1 : 1024;
+    const int64_t grid = n[x] / 256 + 1 < 256 ? n[x] / 256 + 1 : 256;
     max_kernel<<<(unsigned)grid, 256, 0, s>>>(deg[x].as<int32_t>(), n[x], status.as<int32_t>() + 4 + x);
     BFC_LAUNCH_CHECK();
   }

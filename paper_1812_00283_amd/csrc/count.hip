@@ -621,6 +621,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
   constexpr int kSingleMax = kCap / 2;      // one hash window suffices below this many wedges
   constexpr int kS1 = 2 * kNT;              // segment list capacity, pass 1 (and resident middles)
   constexpr int kS2 = kNT;                  // segment list capacity, pass 2
+  constexpr int kFill = 2;                  // middles per thread and sweep of a segment-list fill (4 measured slower: sweeps past the list capacity redo their cut middles)
   constexpr int kSW = ((2 * kS1 + 1 > 5 * kS2 + 2 ? 2 * kS1 + 1 : 5 * kS2 + 2) + 3) / 4 * 4;
   __shared__ __align__(16) int32_t table[kWords];
   __shared__ __align__(16) int32_t segbuf[kSW];
@@ -807,7 +808,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
 
       // Fills the segment list with the non-empty slices [cs, ce) of window
       // [lo_w, hi_w) of middles rj, rj+1, ... < npre, up to `segcap` of
-      // them, 2 * kNT middles per sweep in middle order (one packed
+      // them, kFill * kNT middles per sweep in middle order (one packed
       // workgroup scan of (active, length)).  Leaves rj at the first middle
       // not taken and returns the segment count and total length; the cursors
       // of taken middles advance (or record the window end, cend) here.
@@ -816,11 +817,11 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         nseg = 0;
         T = 0;
         while (nseg < segcap && rj < npre) {
-          int32_t jv[2], csv[2], cev[2], ev[2], vv[2];
-          bool actv[2];
+          int32_t jv[kFill], csv[kFill], cev[kFill], ev[kFill], vv[kFill];
+          bool actv[kFill];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int32_t j = rj + 2 * t + h;
+          for (int h = 0; h < kFill; ++h) {
+            const int32_t j = rj + kFill * t + h;
             jv[h] = j;
             actv[h] = false;
             csv[h] = cev[h] = ev[h] = vv[h] = 0;
@@ -856,10 +857,13 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
               }
             }
           }
-          const int32_t l0 = actv[0] ? cev[0] - csv[0] : 0;
-          const int32_t l1 = actv[1] ? cev[1] - csv[1] : 0;
-          const unsigned long long packed =
-              ((unsigned long long)((int)actv[0] + (int)actv[1]) << 32) | (uint32_t)(l0 + l1);
+          int32_t na = 0, ln = 0;
+#pragma unroll
+          for (int h = 0; h < kFill; ++h) {
+            na += (int)actv[h];
+            ln += actv[h] ? cev[h] - csv[h] : 0;
+          }
+          const unsigned long long packed = ((unsigned long long)na << 32) | (uint32_t)ln;
           unsigned long long tot;
           const unsigned long long ex = block_exclusive_scan<unsigned long long, kNT>(packed, s_red64, &tot);
           const int32_t room = segcap - nseg;
@@ -867,7 +871,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
           int32_t ia = (int32_t)(ex >> 32);
           int32_t lex = (int32_t)(uint32_t)ex;
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
+          for (int h = 0; h < kFill; ++h) {
             if (!actv[h]) continue;
             if (ia < room) {
               const int32_t ps = nseg + ia;
@@ -895,7 +899,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
           if (nact <= room) {
             nseg += nact;
             T += (int32_t)(uint32_t)tot;
-            rj = npre - rj > 2 * kNT ? rj + 2 * kNT : npre;
+            rj = npre - rj > kFill * kNT ? rj + kFill * kNT : npre;
           } else {
             __syncthreads();
             rj = s_cut_j;
