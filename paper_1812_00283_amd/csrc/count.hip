@@ -585,24 +585,30 @@ __device__ __forceinline__ void seg_walk(const int32_t* __restrict__ oadj, const
   }
 }
 
-// Walks all T positions of a segment list, the workgroup's wavefronts
-// taking chunks of whole iterations from an LDS ticket (0 on entry), so a
-// wavefront that meets a slow stretch (short segments) takes fewer chunks.
+// Walks all T positions of a segment list, the workgroup's `waves`
+// wavefronts taking chunks of whole iterations from an LDS cursor (the next
+// position, 0 on entry).  Chunks shrink as the list drains (about the rest
+// over twice the wavefronts, 512 to 8,192 positions), so the wavefronts
+// finish close together and one that meets a slow stretch (short segments)
+// takes fewer positions.
 template <typename Fn, typename Stop>
 __device__ __forceinline__ void chunk_walk(const int32_t* __restrict__ oadj, const int32_t* se, const int32_t* sd,
-                                           int32_t n, int32_t T, int32_t* ticket, Fn&& fn, Stop&& stop) {
-  // about four chunks per wavefront
-  int32_t chunk = (T / 64 + 511) & ~511;
-  chunk = chunk < 512 ? 512 : (chunk > 8192 ? 8192 : chunk);
+                                           int32_t n, int32_t T, int32_t* ticket, int waves, Fn&& fn,
+                                           Stop&& stop) {
   bool stopped = false;
   for (;;) {
-    int32_t c = 0;
-    if (__lane_id() == 0) c = atomicAdd(ticket, 1);
+    int32_t F0 = 0, c = 0;
+    if (__lane_id() == 0) {
+      const int32_t seen = __hip_atomic_load(ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      c = ((T - seen) / (2 * waves)) & ~511;
+      c = c < 512 ? 512 : (c > 8192 ? 8192 : c);
+      F0 = atomicAdd(ticket, c);
+    }
+    F0 = __shfl(F0, 0, 64);
     c = __shfl(c, 0, 64);
-    const int64_t F0 = (int64_t)c * chunk;
     if (F0 >= T) break;
-    const int32_t F1 = F0 + chunk < T ? (int32_t)F0 + chunk : T;
-    seg_walk(oadj, se, sd, n, (int32_t)F0, F1, fn, [&] { stopped = stop(); return stopped; });
+    const int32_t F1 = T - F0 > c ? F0 + c : T;
+    seg_walk(oadj, se, sd, n, F0, F1, fn, [&] { stopped = stop(); return stopped; });
     if (stopped) break;
   }
 }
@@ -1073,7 +1079,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
             // lo_w is even: counter pair (w >> 1) - (lo_w >> 1), half (w & 1):
             // byte offset (w & ~1) * 2 from tw, add 1 or 1 << 16
             char* tw = reinterpret_cast<char*>(table) - 2 * lo_w;
-            chunk_walk(O.adj, se, sd, nseg, T, &s_ticket,
+            chunk_walk(O.adj, se, sd, nseg, T, &s_ticket, kWaves,
                        [&](int32_t, int32_t, int32_t w) {
                          atomicAdd(reinterpret_cast<uint32_t*>(tw + ((uint32_t)(w & ~1) << 1)),
                                    __umul24((uint32_t)w & 1u, 65535u) + 1u);
