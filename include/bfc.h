@@ -158,9 +158,12 @@ bfc_status bfc_destroy(bfc_graph g);
  * which kernel path handles each start vertex.  A field <= 0 keeps the
  * current setting (except dense_block and medium_max_wedges, where 0
  * disables and < 0 keeps).
- *   light_max_wedges   starts with at most this many wedges (<= 1024) are
+ *   light_max_wedges   starts with at most this many wedges (<= 2048) are
  *                      counted by one wavefront with an LDS hash table;
- *                      larger ones by a workgroup.  Default 1024.
+ *                      larger ones by a workgroup.  Default 2048; values
+ *                      above 1024 apply only while both layers have fewer
+ *                      than 2^20 vertices (the wavefront tables pack an end
+ *                      and its count into one word), else 1024 is used.
  *   dense_min_ratio    a workgroup start uses dense LDS counter windows when
  *                      wedges * dense_min_ratio >= its end-rank range, else LDS
  *                      hash windows.  Default 4.

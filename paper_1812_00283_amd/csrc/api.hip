@@ -350,8 +350,8 @@ bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t) {
     if (!t) throw Error{BFC_ERR_INVALID_ARGUMENT, "tuning is null"};
     DeviceScope ds(h->device);
     std::lock_guard<std::mutex> hold(h->mu);
-    if (t->light_max_wedges > 1024)
-      throw Error{BFC_ERR_INVALID_ARGUMENT, "light_max_wedges must be at most 1024"};
+    if (t->light_max_wedges > 2048)
+      throw Error{BFC_ERR_INVALID_ARGUMENT, "light_max_wedges must be at most 2048"};
     if (t->dense_block > 0 && (t->dense_block % 64 || t->dense_block > 32768))
       throw Error{BFC_ERR_INVALID_ARGUMENT, "dense_block must be a multiple of 64 and at most 32768"};
     if (t->window_mode > 3) throw Error{BFC_ERR_INVALID_ARGUMENT, "window_mode must be 1, 2 or 3"};

@@ -410,6 +410,7 @@ __global__ __launch_bounds__(256) void max_kernel(const int32_t* __restrict__ a,
 void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int32_t* const* groups, int32_t G) {
   const int64_t m = g->m;
   const int32_t n[2] = {g->n_upper, g->n_lower};
+  g->light_packed = n[0] < (1 << 20) && n[1] < (1 << 20);
 
   // status: [0] id out of range, [1] duplicate edge, [2 + o] first table row of layer o,
   // [4 + x] largest degree of layer x
@@ -766,7 +767,8 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   flags_h.alloc(sizeof(int32_t) * (size_t)n, s);
   pos_l.alloc(sizeof(int64_t) * (size_t)(n + 1), s);
   pos_h.alloc(sizeof(int32_t) * (size_t)(n + 1), s);
-  const int64_t light_max = g->tune.light_max_wedges;
+  const int64_t light_max =
+      g->tune.light_max_wedges < g->light_max_cap() ? g->tune.light_max_wedges : g->light_max_cap();
   const int32_t K = g->tune.dense_block;
   int32_t KU = K > 0 ? (K < n0 ? K : n0) : 0;
   int32_t KL = K > 0 ? (K < n1 ? K : n1) : 0;
@@ -849,7 +851,7 @@ void finish_schedule(bfc_graph_s* g, hipStream_t s) {
   sc.n_small = (int32_t)(t[8] & 0xFFFFFFFFll);
   sc.n_light = sc.n_small + (int32_t)(t[8] >> 32);
   sc.n_heavy = (int32_t)t[9];
-  sc.light_max = g->tune.light_max_wedges;
+  sc.light_max = g->tune.light_max_wedges < g->light_max_cap() ? g->tune.light_max_wedges : g->light_max_cap();
   sc.medium_max = g->tune.medium_max_wedges;
   trim(sc.light, sizeof(int4) * (size_t)sc.n_light, s);
   trim(sc.heavy, sizeof(int4) * (size_t)sc.n_heavy, s);

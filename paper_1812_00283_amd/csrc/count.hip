@@ -263,29 +263,64 @@ __device__ __forceinline__ int32_t hash_get(const int32_t* keys, const int32_t* 
   return cnt[h];
 }
 
+// Packed wavefront tables: one word per entry, (w + 1) << kLightCountBits |
+// count, for layers of fewer than 2^(32 - kLightCountBits) vertices and
+// starts of fewer than 2^kLightCountBits wedges.  Same probing and return
+// value as wave_hash_inc.
+constexpr int kLightCountBits = 12;
+constexpr uint32_t kLightCountMask = (1u << kLightCountBits) - 1u;
+
+__device__ __forceinline__ int32_t wave_packed_inc(uint32_t* tab, uint32_t mask, int32_t w) {
+  const uint32_t key = (uint32_t)w + 1u;
+  uint32_t h = mix32((uint32_t)w) & mask;
+  for (;;) {
+    const uint32_t cur = tab[h];
+    if ((cur >> kLightCountBits) == key) return (int32_t)(atomicAdd(&tab[h], 1u) & kLightCountMask);
+    if (cur == 0) {
+      const uint32_t old = atomicCAS(&tab[h], 0u, (key << kLightCountBits) | 1u);
+      if (old == 0) return 0;
+      if ((old >> kLightCountBits) == key) return (int32_t)(atomicAdd(&tab[h], 1u) & kLightCountMask);
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__device__ __forceinline__ int32_t wave_packed_get(const uint32_t* tab, uint32_t mask, int32_t w) {
+  const uint32_t key = (uint32_t)w + 1u;
+  uint32_t h = mix32((uint32_t)w) & mask;
+  while ((tab[h] >> kLightCountBits) != key) h = (h + 1) & mask;
+  return (int32_t)(tab[h] & kLightCountMask);
+}
+
 // ------------------------------------------------------------ light
 // Light starts come in two classes by wedge count: up to kSmallMax wedges
 // (a 512-entry table per wavefront, so a CU holds 32 wavefronts) and the
-// rest up to light_max (2048 entries, 8 wavefronts per CU).  A table has at
-// least twice as many entries as its start has wedges.
+// rest up to light_max: 2048 wedges in packed 4,096-entry tables where the
+// layers allow packing, else 1024 wedges in 2,048-entry tables (both 16 KB,
+// 8 wavefronts per CU).  A table has at least twice as many entries as its
+// start has wedges.
 constexpr int kLightNT = 256;
 constexpr int kLightWaves = kLightNT / 64;
-constexpr int kLightCap = 2048;  // light_max <= kLightCap / 2
+constexpr int kLightCap = 2048;        // unpacked: light_max <= kLightCap / 2
+constexpr int kLightPackedCap = 4096;  // packed: light_max <= kLightPackedCap / 2
 constexpr int kSmallCap = 2 * kSmallMax;
+static_assert(kLightPackedCap / 2 < (1 << kLightCountBits), "packed counts must fit");
 
 // Each entry of the light list is {code, first slot of N(r), middles, wedges}.
-template <int kMode, int kCap>
+template <int kMode, int kCap, bool kPacked>
 __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const int4* __restrict__ list,
                                                          int32_t n_list) {
-  __shared__ int32_t tkeys[kLightWaves][kCap];
-  __shared__ int32_t tcnt[kLightWaves][kCap];
+  // packed: kCap words; else kCap keys then kCap counts
+  constexpr int kWordsPerWave = kPacked ? kCap : 2 * kCap;
+  __shared__ uint32_t ttab[kLightWaves][kWordsPerWave];
   __shared__ unsigned long long tdelta[kLightWaves][kMode == kTotal ? 1 : 64];
   const int lane = __lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int32_t* keys = tkeys[wv];
-  int32_t* cnt = tcnt[wv];
+  uint32_t* ptab = ttab[wv];
+  int32_t* keys = reinterpret_cast<int32_t*>(ptab);
+  int32_t* cnt = keys + kCap;
   unsigned long long* dsum = tdelta[wv];
-  for (int h = lane; h < kCap; h += 64) { keys[h] = 0; cnt[h] = 0; }
+  for (int h = lane; h < kWordsPerWave; h += 64) ptab[h] = 0u;
   if (kMode != kTotal) dsum[lane] = 0;
   unsigned long long acc_total = 0;
   const int64_t stride = (int64_t)gridDim.x * kLightWaves;
@@ -312,7 +347,9 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
         cs = O.off[S.adj[k]];
         len = S.rev[k] - cs;
       }
-      light_walk(O.adj, cs, len, [&](int, int32_t, int32_t w) { a += (unsigned)wave_hash_inc(keys, cnt, mask, w); });
+      light_walk(O.adj, cs, len, [&](int, int32_t, int32_t w) {
+        a += (unsigned)(kPacked ? wave_packed_inc(ptab, mask, w) : wave_hash_inc(keys, cnt, mask, w));
+      });
     }
     if (kMode == kTotal) {
       if (p.gtotal) {
@@ -326,8 +363,10 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
         // each end w gains C(count_w, 2); the start gains their sum
         unsigned long long* vs = pick_ptr(p.vout, x);
         for (uint32_t h = lane; h < cap; h += 64) {
-          const int32_t c = cnt[h];
-          if (c > 1) atomicAdd(&vs[S.id_of[keys[h] - 1]], choose2(c));
+          const uint32_t word = ptab[h];
+          const int32_t c = kPacked ? (int32_t)(word & kLightCountMask) : cnt[h];
+          const int32_t key = kPacked ? (int32_t)(word >> kLightCountBits) : keys[h];
+          if (c > 1) atomicAdd(&vs[S.id_of[key - 1]], choose2(c));
         }
         a = wave_sum(a);
         if (lane == 0 && a) atomicAdd(&vs[S.id_of[r]], a);
@@ -347,7 +386,7 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
           len = S.rev[k] - cs;
         }
         light_walk(O.adj, cs, len, [&](int mid, int32_t slot, int32_t w) {
-          const int32_t c = hash_get(keys, cnt, mask, w);
+          const int32_t c = kPacked ? wave_packed_get(ptab, mask, w) : hash_get(keys, cnt, mask, w);
           if (c > 1) {
             const unsigned long long d = (unsigned long long)(c - 1);
             if (kMode == kEdge) atomicAdd(&acc_o[slot], d);
@@ -365,7 +404,14 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
       }
     }
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t h = lane; h < cap; h += 64) { keys[h] = 0; cnt[h] = 0; }
+    for (uint32_t h = lane; h < cap; h += 64) {
+      if (kPacked) {
+        ptab[h] = 0u;
+      } else {
+        keys[h] = 0;
+        cnt[h] = 0;
+      }
+    }
     __builtin_amdgcn_wave_barrier();
   }
   if (kMode == kTotal && p.total) {
@@ -1523,17 +1569,23 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     const int32_t n_small = sc.n_small, n_large = sc.n_light - sc.n_small;
     if (n_small > 0) {
       const unsigned grid = light_grid(n_small);
-      if (mode == kTotal) light_kernel<kTotal, kSmallCap><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
-      else if (mode == kVertex) light_kernel<kVertex, kSmallCap><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
-      else light_kernel<kEdge, kSmallCap><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
+      if (mode == kTotal) light_kernel<kTotal, kSmallCap, false><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
+      else if (mode == kVertex) light_kernel<kVertex, kSmallCap, false><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
+      else light_kernel<kEdge, kSmallCap, false><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
       BFC_LAUNCH_CHECK();
     }
     if (n_large > 0) {
       const unsigned grid = light_grid(n_large);
       const int4* l = llist + n_small;
-      if (mode == kTotal) light_kernel<kTotal, kLightCap><<<grid, kLightNT, 0, s>>>(p, l, n_large);
-      else if (mode == kVertex) light_kernel<kVertex, kLightCap><<<grid, kLightNT, 0, s>>>(p, l, n_large);
-      else light_kernel<kEdge, kLightCap><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+      if (g->light_packed) {
+        if (mode == kTotal) light_kernel<kTotal, kLightPackedCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+        else if (mode == kVertex) light_kernel<kVertex, kLightPackedCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+        else light_kernel<kEdge, kLightPackedCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+      } else {
+        if (mode == kTotal) light_kernel<kTotal, kLightCap, false><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+        else if (mode == kVertex) light_kernel<kVertex, kLightCap, false><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+        else light_kernel<kEdge, kLightCap, false><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+      }
       BFC_LAUNCH_CHECK();
     }
   }

@@ -131,7 +131,7 @@ struct Schedule {
 };
 
 struct Tuning {
-  int32_t light_max_wedges = 1024;
+  int32_t light_max_wedges = 2048;  // used up to light_max_cap()
   int32_t dense_min_ratio = 4;
   int32_t window_mode = 1;  // 1 auto, 2 dense only, 3 hash only
   int32_t hash_window_wedges = 8192;
@@ -170,6 +170,10 @@ struct bfc_graph_s {
   // build status (int32 [8]) and schedule totals (int64 [16] from byte 64),
   // read back once when the build is complete
   bfc::DevBuf info;
+  // light tables pack (end + 1) << 12 | count when every layer has fewer
+  // than 2^20 vertices; light starts then go up to 2048 wedges, else 1024
+  bool light_packed = false;
+  int32_t light_max_cap() const { return light_packed ? 2048 : 1024; }
   int64_t rows_max[2] = {0, 0};  // window-table rows allocated per layer
   std::vector<int64_t> graph_wedges;
   // captured total count

@@ -94,6 +94,8 @@ def hub_oracle(hub_graph):
 
 TUNINGS = {
     "default": {},
+    # wavefront starts up to 1024 wedges only (the limit of unpacked tables)
+    "light-1024": {"light_max_wedges": 1024},
     "all-workgroup": {"light_max_wedges": 1},
     "dense-windows": {"light_max_wedges": 16, "window_mode": 2},
     "hash-windows": {"light_max_wedges": 16, "window_mode": 3},
