@@ -14,6 +14,8 @@ The arithmetic lives in ``oracle.c`` (plain C, OpenMP over start vertices):
   the priority of Definition 3 (the denominator of the wedges/s metric)
 * ``vp_count_wedge`` -- Algorithm 2's count_wedge map for one start vertex
 * ``priorities``     -- Definition 3's priority as a rank in [0, n)
+* ``caterpillars``   -- Section 1: the three-paths C_G, sum over edges (u, v) of
+  (d_u - 1)(d_v - 1), the denominator of the clustering coefficient 4 B_G / C_G
 
 Vertices carry the global ids of Section 2: lower v -> v, upper u -> |L| + u.
 """
@@ -69,6 +71,8 @@ def _load():
     lib.orc_vp_wedges.restype = i32
     lib.orc_vp_count_wedge.argtypes = [vp, i64, i64, i64, i64, vp, vp, i64]
     lib.orc_vp_count_wedge.restype = i64
+    lib.orc_caterpillars.argtypes = [vp, i64, i64, i64, vp]
+    lib.orc_caterpillars.restype = i32
     lib.orc_max_threads.argtypes = []
     lib.orc_max_threads.restype = i32
     _lib = lib
@@ -193,6 +197,20 @@ def priorities(g) -> np.ndarray:
     out = np.zeros(g.n_upper + g.n_lower, dtype=np.int64)
     _check(_load().orc_priorities(p, e.shape[0], g.n_upper, g.n_lower, out.ctypes.data), "priorities")
     return out
+
+
+def caterpillars(g) -> int:
+    """C_G: three-paths, sum over edges (u, v) of (d_u - 1)(d_v - 1) (Section 1)."""
+    e, p = _edges(g)
+    out = ctypes.c_int64(0)
+    _check(_load().orc_caterpillars(p, e.shape[0], g.n_upper, g.n_lower, ctypes.byref(out)), "caterpillars")
+    return int(out.value)
+
+
+def clustering_coefficient(g) -> float:
+    """Bipartite clustering coefficient 4 B_G / C_G (Section 1); 0 without three-paths."""
+    c = caterpillars(g)
+    return 4.0 * total(g) / c if c else 0.0
 
 
 def vp_wedges(g, per_start: bool = False, nthreads: int | None = None):

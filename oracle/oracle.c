@@ -13,6 +13,9 @@
  *                                        of (|N(u) & N(w)| - 1)
  *   processed wedges of BFC-VP (Algorithm 2 with Definition 3): the number of
  *   wedges (u, v, w) with p(v) < p(u) and p(w) < p(u).
+ *   caterpillars (Section 1, bipartite clustering coefficient 4 B_G / C_G):
+ *   the three-paths (x, y, z, t); each has one middle edge (y, z), whose ends
+ *   extend it in (d_y - 1)(d_z - 1) ways, so C_G = sum over edges of that.
  *
  * Intersections are full (no priority filter); each start vertex gets a dense
  * int32 counter over its own layer.  All sums are int64; C(c,2) is c(c-1)/2.
@@ -443,6 +446,23 @@ int64_t orc_vp_count_wedge(const int32_t* edges, int64_t m, int64_t nU, int64_t 
   free(p); free(c);
   free_graph(&g);
   return k;
+}
+
+/* C_G = sum over edges (u, v) of (d_u - 1)(d_v - 1) (caterpillars). */
+int orc_caterpillars(const int32_t* edges, int64_t m, int64_t nU, int64_t nL, int64_t* out) {
+  if (!out) return -1;
+  bigraph g;
+  int rc = load_graph(&g, edges, m, nU, nL);
+  if (rc) return rc;
+  int64_t c = 0;
+  for (int64_t i = 0; i < m; ++i) {
+    const int64_t du = g.up.off[edges[2 * i] + 1] - g.up.off[edges[2 * i]];
+    const int64_t dv = g.lo.off[edges[2 * i + 1] + 1] - g.lo.off[edges[2 * i + 1]];
+    c += (du - 1) * (dv - 1);
+  }
+  free_graph(&g);
+  *out = c;
+  return 0;
 }
 
 int orc_max_threads(void) { return omp_get_max_threads(); }

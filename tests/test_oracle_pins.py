@@ -257,3 +257,47 @@ def test_generator_determinism_and_shape():
     c = gg.chung_lu(11, 3000, 2000, 30000, 2.1, 2.1, 500.0, blocks=2, block=20, density=0.9)
     keys = c.edges[:, 0].astype(np.int64) * c.n_lower + c.edges[:, 1]
     assert len(np.unique(keys)) == c.m == 30000
+
+
+def brute_three_paths(g):
+    """Three-paths by enumeration: walks x-y-z-t over four distinct vertices,
+    each path counted once (a walk and its reverse are the same path)."""
+    nb = {}
+    for u, v in g.edges.tolist():
+        a, b = ("U", u), ("L", v)
+        nb.setdefault(a, set()).add(b)
+        nb.setdefault(b, set()).add(a)
+    walks = 0
+    for x in nb:
+        for y in nb[x]:
+            for z in nb[y]:
+                if z == x:
+                    continue
+                for t in nb[z]:
+                    if t != y and t != x:
+                        walks += 1
+    assert walks % 2 == 0
+    return walks // 2
+
+
+def test_caterpillars_equal_three_path_enumeration():
+    for g in tiny_graphs(200, seed0=9100):
+        assert oracle.caterpillars(g) == brute_three_paths(g)
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (1, 5), (2, 2), (2, 3), (3, 7), (13, 4)])
+def test_caterpillars_complete_bipartite(a, b):
+    # every edge of K_{a,b} is the middle of (a - 1)(b - 1) three-paths
+    g = gg.complete_bipartite(a, b)
+    assert oracle.caterpillars(g) == a * b * (a - 1) * (b - 1)
+    if a >= 2 and b >= 2:
+        # 4 C(a,2) C(b,2) = a b (a - 1)(b - 1): complete bipartite graphs have coefficient 1
+        assert oracle.clustering_coefficient(g) == 1.0
+
+
+@pytest.mark.parametrize("k", [2, 3, 5])
+def test_caterpillars_even_cycles_and_forests(k):
+    # in C_{2k} every edge's ends have degree 2: one three-path per edge
+    assert oracle.caterpillars(gg.even_cycle(k)) == 2 * k
+    g = gg.random_forest(k, 200, 150)
+    assert oracle.clustering_coefficient(g) == 0.0
