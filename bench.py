@@ -79,6 +79,15 @@ def heavy_traffic(workload: str, tuned: bool):
     return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
 
 
+def golden_caterpillars(name: str):
+    path = os.path.join(ROOT, "tests", "golden", "caterpillars.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(name)
+    return rec["caterpillars"] if rec else None
+
+
 def golden_total(name: str):
     path = os.path.join(ROOT, "tests", "golden", "workloads.json")
     if not os.path.exists(path):
@@ -332,6 +341,7 @@ def main() -> int:
         tc = time.perf_counter() - tb
         kt = h.kernel_times() if timing else None
         si = h.schedule_info()
+        si["caterpillars"] = h.caterpillars()
         h.close()
         return tot, wed, tc, kt, si
 
@@ -388,6 +398,9 @@ def main() -> int:
             "step": "bfc_build + bfc_count_total on device-resident edges",
             "exact_vs_oracle": bool(gold),
             "tuning": tuning or "default",
+            "caterpillars": si["caterpillars"],
+            "clustering_coefficient": 4.0 * tot0 / si["caterpillars"] if si["caterpillars"] else 0.0,
+            "caterpillars_exact_vs_oracle": golden_caterpillars(args.workload) == si["caterpillars"],
         },
         "count_ms": count_ms,
         "build_ms": ms_step - count_ms,

@@ -103,6 +103,23 @@ bfc_status bfc_count_per_vertex(bfc_graph g, void* stream, int64_t* upper_dev, i
 bfc_status bfc_count_per_edge(bfc_graph g, void* stream, int64_t* edge_dev);
 
 /*
+ * Caterpillars C_G (Section 1): the three-paths of the graph, walks x-y-z-t
+ * over four distinct vertices, each path counted once.  A three-path has one
+ * middle edge (y, z) and extends it in (d_y - 1)(d_z - 1) ways, so C_G is the
+ * sum of that over the edges.  bfc_build computes it with the per-start
+ * wedge counts; for a batch handle it is the sum over the graphs.  Writes
+ * the int64 value to *caterpillars_host (exact while the sum fits in int64).
+ */
+bfc_status bfc_caterpillars(bfc_graph g, int64_t* caterpillars_host);
+
+/*
+ * Bipartite clustering coefficient 4 B_G / C_G (Section 1; 0 when the graph
+ * has no three-path).  Runs bfc_count_total on `stream` under the same rules
+ * and waits for it; writes the coefficient (double) to *coefficient_host.
+ */
+bfc_status bfc_clustering_coefficient(bfc_graph g, void* stream, double* coefficient_host);
+
+/*
  * Batched form: G independent graphs built into one handle and counted by
  * one set of kernel launches.  Graph g's edges are rows
  * [edge_offsets[g], edge_offsets[g+1]) of edges_dev, with its own 0-based

@@ -32,7 +32,7 @@ EXPORTS = [
     "bfc_graph_info", "bfc_estimate_device_bytes", "bfc_destroy", "bfc_set_tuning", "bfc_get_tuning",
     "bfc_last_error", "bfc_version", "bfc_get_schedule_info", "bfc_set_kernel_timing", "bfc_get_kernel_times",
     "bfc_build_batch", "bfc_count_total_batch", "bfc_batch_wedges", "bfc_graph_capture_total", "bfc_graph_replay",
-    "bfc_graph_count",
+    "bfc_graph_count", "bfc_caterpillars", "bfc_clustering_coefficient",
 ]
 
 
@@ -91,6 +91,8 @@ def load(path: str | None = None):
         "bfc_graph_capture_total": ([vp, vp, vp], i32),
         "bfc_graph_replay": ([vp, vp], i32),
         "bfc_graph_count": ([vp, pi32], i32),
+        "bfc_caterpillars": ([vp, pi64], i32),
+        "bfc_clustering_coefficient": ([vp, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "bfc_last_error": ([], ctypes.c_char_p),
         "bfc_version": ([], ctypes.c_char_p),
     }
@@ -182,6 +184,18 @@ class Graph:
         out = torch.empty(self.m, dtype=torch.int64, device=self.device)
         _check(load().bfc_count_per_edge(self._h, _stream(stream), _ptr(out)))
         return out
+
+    def caterpillars(self) -> int:
+        """C_G: the graph's three-paths, computed by the build."""
+        c = ctypes.c_int64(0)
+        _check(load().bfc_caterpillars(self._h, ctypes.byref(c)))
+        return int(c.value)
+
+    def clustering_coefficient(self, stream=None) -> float:
+        """4 B_G / C_G (runs the total count)."""
+        c = ctypes.c_double(0.0)
+        _check(load().bfc_clustering_coefficient(self._h, _stream(stream), ctypes.byref(c)))
+        return float(c.value)
 
     def count_total_batch(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """Per-graph totals (int64 CUDA tensor [graphs]); asynchronous."""

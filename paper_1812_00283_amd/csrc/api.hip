@@ -305,6 +305,27 @@ bfc_status bfc_count_per_vertex(bfc_graph g, void* stream, int64_t* upper_dev, i
   });
 }
 
+bfc_status bfc_caterpillars(bfc_graph g, int64_t* caterpillars_host) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!caterpillars_host) throw Error{BFC_ERR_INVALID_ARGUMENT, "caterpillars_host is null"};
+    *caterpillars_host = h->caterpillars;
+  });
+}
+
+bfc_status bfc_clustering_coefficient(bfc_graph g, void* stream, double* coefficient_host) {
+  int64_t total = 0;
+  if (coefficient_host) {
+    const bfc_status st = bfc_count_total(g, stream, &total, nullptr);
+    if (st != BFC_OK) return st;
+  }
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!coefficient_host) throw Error{BFC_ERR_INVALID_ARGUMENT, "coefficient_host is null"};
+    *coefficient_host = h->caterpillars > 0 ? 4.0 * (double)total / (double)h->caterpillars : 0.0;
+  });
+}
+
 bfc_status bfc_count_per_edge(bfc_graph g, void* stream, int64_t* edge_dev) {
   return guard([&] {
     bfc_graph_s* h = checked(g);

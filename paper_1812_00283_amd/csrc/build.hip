@@ -273,13 +273,16 @@ __global__ void transpose_unpack_kernel(const uint32_t* __restrict__ key, const 
 // Arc-parallel over the side's CSR, whose starts ascend: a wavefront sums
 // its 64 arcs per run of equal start (segmented scan) and the run's last
 // lane adds the sums with one atomic each (lo and work start at zero).
+// With cat non-null it also adds the caterpillars (three-paths) of the
+// graph, sum over its edges of (d_u - 1)(d_v - 1) (Section 1), to *cat.
 __global__ void start_stats_kernel(int64_t m, int x, const int32_t* __restrict__ src,
                                    const int32_t* __restrict__ adj, const int32_t* __restrict__ rev,
                                    const int32_t* __restrict__ off_self, const int32_t* __restrict__ off_other,
-                                   int32_t* __restrict__ lo,
-                                   unsigned long long* __restrict__ work) {
+                                   int32_t* __restrict__ lo, unsigned long long* __restrict__ work,
+                                   unsigned long long* __restrict__ cat) {
   const int lane = __lane_id();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long paths = 0;
   for (int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~63ll; b < m; b += stride) {
     const int64_t k = b + lane;
     int32_t r = -1, f = 0;
@@ -289,6 +292,7 @@ __global__ void start_stats_kernel(int64_t m, int x, const int32_t* __restrict__
       const int32_t v = adj[k];
       const int32_t ov = off_other[v];
       const int32_t ds = off_self[r + 1] - off_self[r], dv = off_other[v + 1] - ov;
+      paths += (unsigned long long)(uint32_t)(ds - 1) * (uint32_t)(dv - 1);  // degrees >= 1: a 32x32-bit product
       if (x == 0 ? dv <= ds : dv < ds) {
         f = 1;
         w = (unsigned long long)(rev[k] - ov);
@@ -315,6 +319,10 @@ __global__ void start_stats_kernel(int64_t m, int x, const int32_t* __restrict__
         atomicAdd(&work[r], sw);
       }
     }
+  }
+  if (cat) {
+    paths = wave_sum(paths);
+    if (lane == 0 && paths) atomicAdd(cat, paths);
   }
 }
 
@@ -585,7 +593,10 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
       start_stats_kernel<<<(unsigned)grid, 256, 0, s>>>(m, x, src[x].as<int32_t>(), sd.adj.as<int32_t>(),
                                                         sd.rev.as<int32_t>(), sd.off.as<int32_t>(),
                                                         g->side[1 - x].off.as<int32_t>(), sd.lo.as<int32_t>(),
-                                                        sd.work.as<unsigned long long>());
+                                                        sd.work.as<unsigned long long>(),
+                                                        x == 0 ? reinterpret_cast<unsigned long long*>(
+                                                                     g->info.as<char>() + kInfoCaterpillars)
+                                                               : nullptr);
       BFC_LAUNCH_CHECK();
     }
   }
@@ -832,6 +843,8 @@ void finish_schedule(bfc_graph_s* g, hipStream_t s) {
   int64_t t[16];
   BFC_HIP(hipMemcpyAsync(st, g->info.p, sizeof(st), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipMemcpyAsync(t, g->info.as<char>() + 64, sizeof(t), hipMemcpyDeviceToHost, s));
+  int64_t cat = 0;
+  BFC_HIP(hipMemcpyAsync(&cat, g->info.as<char>() + kInfoCaterpillars, sizeof(cat), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
   if (st[1]) throw Error{BFC_ERR_DUPLICATE_EDGE, "the edge list repeats an (upper, lower) pair"};
   const int32_t nn[2] = {g->side[0].n, g->side[1].n};
@@ -853,6 +866,7 @@ void finish_schedule(bfc_graph_s* g, hipStream_t s) {
   sc.n_heavy = (int32_t)t[9];
   sc.light_max = g->tune.light_max_wedges < g->light_max_cap() ? g->tune.light_max_wedges : g->light_max_cap();
   sc.medium_max = g->tune.medium_max_wedges;
+  g->caterpillars = cat;
   trim(sc.light, sizeof(int4) * (size_t)sc.n_light, s);
   trim(sc.heavy, sizeof(int4) * (size_t)sc.n_heavy, s);
 }
