@@ -37,9 +37,9 @@ DEFAULT_WORKLOAD = "chunglu-1m-500k-20m"
 # hash to the value they were measured with (any change voids the figure).
 HEAVY_TRAFFIC = {
     "workload": DEFAULT_WORKLOAD,
-    "sources_sha256": "fa0c9f0e7eb171b0dae2737eb69189d2ad6206095485f772cb6c2d6c63aa69a4",
-    "fetch_kib": 17197687.4,
-    "write_kib": 1671001.3,
+    "sources_sha256": "a3f3c840e091567286ab019dc9f9c44630f45c52b9c8b2567f8adba28b5a6bb9",
+    "fetch_kib": 17114805.9,
+    "write_kib": 887130.4,
     "fetch_factor": 2.0,
     "write_factor": 1.0,
 }

@@ -268,18 +268,22 @@ __global__ void transpose_unpack_kernel(const uint32_t* __restrict__ key, const 
 // priority, a prefix of N(r): deg(v) <= deg(r) across the layers, ties to
 // the lower layer) and work[r] = the wedges Algorithm 2 walks from r, the
 // sum over middles of v's neighbours below r (rev[k] - off_other[v]).
+constexpr int kCatSlots = 64;
+
 // Degrees are differences of adjacent CSR offsets, so the other layer's
 // offset and degree come from one cache line per arc.
 // Arc-parallel over the side's CSR, whose starts ascend: a wavefront sums
 // its 64 arcs per run of equal start (segmented scan) and the run's last
 // lane adds the sums with one atomic each (lo and work start at zero).
 // With cat non-null it also adds the caterpillars (three-paths) of the
-// graph, sum over its edges of (d_u - 1)(d_v - 1) (Section 1), to *cat.
+// graph, sum over its edges of (d_u - 1)(d_v - 1) (Section 1), into
+// cat[0 .. kCatSlots): one atomic per workgroup, spread over the slots.
 __global__ void start_stats_kernel(int64_t m, int x, const int32_t* __restrict__ src,
                                    const int32_t* __restrict__ adj, const int32_t* __restrict__ rev,
                                    const int32_t* __restrict__ off_self, const int32_t* __restrict__ off_other,
                                    int32_t* __restrict__ lo, unsigned long long* __restrict__ work,
                                    unsigned long long* __restrict__ cat) {
+  __shared__ unsigned long long s_paths[4];
   const int lane = __lane_id();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   unsigned long long paths = 0;
@@ -290,12 +294,13 @@ __global__ void start_stats_kernel(int64_t m, int x, const int32_t* __restrict__
     if (k < m) {
       r = src[k];
       const int32_t v = adj[k];
+      const int32_t rk = rev[k];
       const int32_t ov = off_other[v];
       const int32_t ds = off_self[r + 1] - off_self[r], dv = off_other[v + 1] - ov;
       paths += (unsigned long long)(uint32_t)(ds - 1) * (uint32_t)(dv - 1);  // degrees >= 1: a 32x32-bit product
       if (x == 0 ? dv <= ds : dv < ds) {
         f = 1;
-        w = (unsigned long long)(rev[k] - ov);
+        w = (unsigned long long)(rk - ov);
       }
     }
     // run boundaries: a lane heads a run when its start differs from the lane below
@@ -322,7 +327,12 @@ __global__ void start_stats_kernel(int64_t m, int x, const int32_t* __restrict__
   }
   if (cat) {
     paths = wave_sum(paths);
-    if (lane == 0 && paths) atomicAdd(cat, paths);
+    if (lane == 0) s_paths[threadIdx.x >> 6] = paths;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned long long b = s_paths[0] + s_paths[1] + s_paths[2] + s_paths[3];
+      if (b) atomicAdd(&cat[blockIdx.x % kCatSlots], b);
+    }
   }
 }
 
@@ -422,8 +432,8 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
 
   // status: [0] id out of range, [1] duplicate edge, [2 + o] first table row of layer o,
   // [4 + x] largest degree of layer x
-  g->info.alloc(256, s);
-  BFC_HIP(hipMemsetAsync(g->info.p, 0, 256, s));
+  g->info.alloc(kInfoBytes, s);
+  BFC_HIP(hipMemsetAsync(g->info.p, 0, kInfoBytes, s));
   DevBuf& status = g->info;
   TmpBuf deg[2];
   for (int x = 0; x < 2; ++x) {
@@ -843,8 +853,8 @@ void finish_schedule(bfc_graph_s* g, hipStream_t s) {
   int64_t t[16];
   BFC_HIP(hipMemcpyAsync(st, g->info.p, sizeof(st), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipMemcpyAsync(t, g->info.as<char>() + 64, sizeof(t), hipMemcpyDeviceToHost, s));
-  int64_t cat = 0;
-  BFC_HIP(hipMemcpyAsync(&cat, g->info.as<char>() + kInfoCaterpillars, sizeof(cat), hipMemcpyDeviceToHost, s));
+  int64_t cat_slots[kCatSlots];
+  BFC_HIP(hipMemcpyAsync(cat_slots, g->info.as<char>() + kInfoCaterpillars, sizeof(cat_slots), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
   if (st[1]) throw Error{BFC_ERR_DUPLICATE_EDGE, "the edge list repeats an (upper, lower) pair"};
   const int32_t nn[2] = {g->side[0].n, g->side[1].n};
@@ -866,6 +876,8 @@ void finish_schedule(bfc_graph_s* g, hipStream_t s) {
   sc.n_heavy = (int32_t)t[9];
   sc.light_max = g->tune.light_max_wedges < g->light_max_cap() ? g->tune.light_max_wedges : g->light_max_cap();
   sc.medium_max = g->tune.medium_max_wedges;
+  int64_t cat = 0;
+  for (int i = 0; i < kCatSlots; ++i) cat += cat_slots[i];
   g->caterpillars = cat;
   trim(sc.light, sizeof(int4) * (size_t)sc.n_light, s);
   trim(sc.heavy, sizeof(int4) * (size_t)sc.n_heavy, s);

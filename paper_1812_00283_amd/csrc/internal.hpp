@@ -19,9 +19,10 @@ constexpr int kWinShift = 15;
 // Medium heavy starts (256-thread workgroups) have at most this many middles.
 constexpr int32_t kMediumMaxPre = 512;
 constexpr int32_t kWinMinDegree = 64;
-// byte offset of the caterpillar count in a graph's info block (past the
-// status words and the schedule totals)
+// byte offset of the caterpillar partial sums (64 int64 slots) in a graph's
+// info block (past the status words and the schedule totals), and its size
 constexpr int kInfoCaterpillars = 192;
+constexpr int kInfoBytes = kInfoCaterpillars + 64 * 8;
 // Light starts of at most this many wedges use the small-table kernel.
 constexpr int32_t kSmallMax = 256;
 
@@ -171,7 +172,7 @@ struct bfc_graph_s {
   bfc::DevBuf gid[2];
   bfc::DevBuf grank[2];   // per layer: first rank of each graph (G + 1), batches only
   // build status (int32 [8]) and schedule totals (int64 [16] from byte 64),
-  // the caterpillar count (int64 at byte kInfoCaterpillars), read back once
+  // the caterpillar partial sums (from byte kInfoCaterpillars), read back once
   // when the build is complete
   bfc::DevBuf info;
   int64_t caterpillars = 0;  // three-paths, sum over edges of (d_u - 1)(d_v - 1)
