@@ -646,7 +646,7 @@ constexpr int kClassifyNT = 256;
 __global__ __launch_bounds__(kClassifyNT) void classify_kernel(const int64_t* __restrict__ work0, const int32_t* __restrict__ lo0, int32_t n0,
                                 const int64_t* __restrict__ work1, const int32_t* __restrict__ lo1, int32_t n1,
                                 int64_t light_max, int32_t KU, int32_t KL, int64_t* __restrict__ is_light,
-                                int32_t* __restrict__ is_heavy, unsigned long long* __restrict__ sums) {
+                                int64_t* __restrict__ is_heavy, unsigned long long* __restrict__ sums) {
   const int64_t n = (int64_t)n0 + n1;
   unsigned long long s_all = 0, s_lw = 0, s_hw = 0, s_lm = 0, s_hm = 0, max_w = 0;
   int32_t max_pre = 0;
@@ -657,9 +657,11 @@ __global__ __launch_bounds__(kClassifyNT) void classify_kernel(const int64_t* __
     const bool heavy = w > light_max || (in_block && w >= 2);
     const bool light = w >= 2 && !heavy;
     s_all += (unsigned long long)w;
-    // light starts: small ones count in the low word, the others in the high word
-    is_light[i] = light ? (w <= kSmallMax ? 1ll : (1ll << 32)) : 0ll;
-    is_heavy[i] = heavy ? 1 : 0;
+    // light starts: small ones count in is_light's low word, mid ones in its
+    // high word, large ones in is_heavy's high word (heavy starts: low word)
+    const bool large = light && w > kLightMidMax;
+    is_light[i] = light && !large ? (w <= kSmallMax ? 1ll : (1ll << 32)) : 0ll;
+    is_heavy[i] = heavy ? 1ll : (large ? (1ll << 32) : 0ll);
     if (light) { s_lw += (unsigned long long)w; s_lm += (unsigned long long)pre; }
     if (heavy) {
       s_hw += (unsigned long long)w;
@@ -713,8 +715,8 @@ __global__ __launch_bounds__(kClassifyNT) void classify_kernel(const int64_t* __
 // when it has at most medium_max wedges and kMediumMaxPre middles and lies
 // outside the dense block; the key orders big starts first, each class by
 // decreasing work.  n_medium counts the medium starts.
-__global__ void compact_kernel(const int64_t* __restrict__ is_light, const int32_t* __restrict__ is_heavy,
-                               const int64_t* __restrict__ pos_light, const int32_t* __restrict__ pos_heavy,
+__global__ void compact_kernel(const int64_t* __restrict__ is_light, const int64_t* __restrict__ is_heavy,
+                               const int64_t* __restrict__ pos_light, const int64_t* __restrict__ pos_heavy,
                                int32_t n0, int32_t n1, const int64_t* __restrict__ work0,
                                const int64_t* __restrict__ work1, const int32_t* __restrict__ lo0,
                                const int32_t* __restrict__ lo1, const int32_t* __restrict__ off0,
@@ -723,8 +725,9 @@ __global__ void compact_kernel(const int64_t* __restrict__ is_light, const int32
                                uint32_t* __restrict__ heavy_key, unsigned long long* __restrict__ n_medium,
                                long long* __restrict__ counts) {
   const int64_t n = (int64_t)n0 + n1;
-  // the small light starts come first, then the other light starts
+  // the small light starts come first, then the mid ones, then the large ones
   const int32_t n_small = (int32_t)(pos_light[n] & 0xFFFFFFFFll);
+  const int32_t n_mid = (int32_t)(pos_light[n] >> 32);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     counts[0] = pos_light[n];
     counts[1] = pos_heavy[n];
@@ -732,24 +735,28 @@ __global__ void compact_kernel(const int64_t* __restrict__ is_light, const int32
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t code = i < n0 ? (int32_t)i : (int32_t)((1u << 30) | (uint32_t)(i - n0));
     const int64_t fl = is_light[i];
-    if (fl) {
+    const int64_t fh = is_heavy[i];
+    if (fl || (fh >> 32)) {
       const int64_t pl = pos_light[i];
-      const int32_t at = (fl & 0xFFFFFFFFll) ? (int32_t)(pl & 0xFFFFFFFFll) : n_small + (int32_t)(pl >> 32);
+      const int32_t at = (fl & 0xFFFFFFFFll)   ? (int32_t)(pl & 0xFFFFFFFFll)
+                         : fl                  ? n_small + (int32_t)(pl >> 32)
+                                               : n_small + n_mid + (int32_t)(pos_heavy[i] >> 32);
       const int32_t base = i < n0 ? off0[i] : off1[i - n0];
       const int32_t pre = i < n0 ? lo0[i] : lo1[i - n0];
       const int32_t w = (int32_t)(i < n0 ? work0[i] : work1[i - n0]);
       light[at] = make_int4(code, base, pre, w);
     }
     bool med = false;
-    if (is_heavy[i]) {
+    if (fh & 0xFFFFFFFFll) {
       const int64_t w = i < n0 ? work0[i] : work1[i - n0];
       const int32_t pre = i < n0 ? lo0[i] : lo1[i - n0];
       const bool in_block = i < n0 ? i > (int64_t)n0 - KU : (i - n0) > (int64_t)n1 - KL;
       med = medium_max > 0 && w <= medium_max && pre <= kMediumMaxPre && !in_block;
       // ascending keys: big starts by decreasing work (steps of 2^(1/512)), then medium ones
       const int32_t lg = (int32_t)(512.0f * log2f((float)w));
-      heavy[pos_heavy[i]] = code;
-      heavy_key[pos_heavy[i]] = (med ? 0x8000u : 0u) | (uint32_t)(32767 - (lg < 32767 ? lg : 32767));
+      const int32_t at = (int32_t)(pos_heavy[i] & 0xFFFFFFFFll);
+      heavy[at] = code;
+      heavy_key[at] = (med ? 0x8000u : 0u) | (uint32_t)(32767 - (lg < 32767 ? lg : 32767));
     }
     const uint64_t mb = __ballot(med);
     if (__lane_id() == 0 && mb) atomicAdd(n_medium, (unsigned long long)__popcll(mb));
@@ -758,12 +765,12 @@ __global__ void compact_kernel(const int64_t* __restrict__ is_light, const int32
 
 // Heavy list entries {code, off[rank], lo[rank], wedges (clamped to int32)}
 // in the sorted order of the codes.
-__global__ void heavy_entries_kernel(const uint32_t* __restrict__ codes, const int32_t* __restrict__ n_dev,
+__global__ void heavy_entries_kernel(const uint32_t* __restrict__ codes, const int64_t* __restrict__ n_dev,
                                      const int32_t* __restrict__ off0,
                                      const int32_t* __restrict__ off1, const int32_t* __restrict__ lo0,
                                      const int32_t* __restrict__ lo1, const int64_t* __restrict__ work0,
                                      const int64_t* __restrict__ work1, int4* __restrict__ out) {
-  const int32_t n = *n_dev;
+  const int32_t n = (int32_t)(*n_dev & 0xFFFFFFFFll);  // heavy starts: the low word
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t code = (int32_t)codes[i];
     const int x = (int)((uint32_t)code >> 30);
@@ -780,14 +787,14 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   const int32_t n0 = g->side[0].n, n1 = g->side[1].n;
   const int64_t n = (int64_t)n0 + n1;
   // totals go to g->info from byte 64: [0..7] the classify sums, [7] medium
-  // starts, [8] light counts (small | other << 32), [9] heavy starts
+  // starts, [8] light counts (small | mid << 32), [9] heavy | large light << 32
   unsigned long long* sums = reinterpret_cast<unsigned long long*>(g->info.as<char>() + 64);
   BFC_HIP(hipMemsetAsync(sums, 0, 16 * sizeof(int64_t), s));
   TmpBuf flags_l, flags_h, pos_l, pos_h;
   flags_l.alloc(sizeof(int64_t) * (size_t)n, s);
-  flags_h.alloc(sizeof(int32_t) * (size_t)n, s);
+  flags_h.alloc(sizeof(int64_t) * (size_t)n, s);
   pos_l.alloc(sizeof(int64_t) * (size_t)(n + 1), s);
-  pos_h.alloc(sizeof(int32_t) * (size_t)(n + 1), s);
+  pos_h.alloc(sizeof(int64_t) * (size_t)(n + 1), s);
   const int64_t light_max =
       g->tune.light_max_wedges < g->light_max_cap() ? g->tune.light_max_wedges : g->light_max_cap();
   const int32_t K = g->tune.dense_block;
@@ -797,12 +804,12 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   if (n > 0) {
     classify_kernel<<<grid_1d(n) < 1024 ? grid_1d(n) : 1024, kClassifyNT, 0, s>>>(g->side[0].work.as<int64_t>(), g->side[0].lo.as<int32_t>(), n0,
                                                 g->side[1].work.as<int64_t>(), g->side[1].lo.as<int32_t>(), n1,
-                                                light_max, KU, KL, flags_l.as<int64_t>(), flags_h.as<int32_t>(),
+                                                light_max, KU, KL, flags_l.as<int64_t>(), flags_h.as<int64_t>(),
                                                 sums);
     BFC_LAUNCH_CHECK();
   }
   exclusive_scan_i64(flags_l.as<int64_t>(), pos_l.as<int64_t>(), n, pos_l.as<int64_t>() + n, s);
-  exclusive_scan_i32(flags_h.as<int32_t>(), pos_h.as<int32_t>(), n, pos_h.as<int32_t>() + n, s);
+  exclusive_scan_i64(flags_h.as<int64_t>(), pos_h.as<int64_t>(), n, pos_h.as<int64_t>() + n, s);
   // the list sizes are known once the build is read back: size the lists
   // for every start (finish_schedule trims them)
   sc.light.alloc(sizeof(int4) * (size_t)n, s);
@@ -814,8 +821,8 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   hval_tmp.alloc(sizeof(uint32_t) * (size_t)n, s);
   if (n > 0) {
     BFC_HIP(hipMemsetAsync(hkey.p, 0xFF, sizeof(uint32_t) * (size_t)n, s));  // past the heavy starts: key 0xFFFF...
-    compact_kernel<<<grid_1d(n), 256, 0, s>>>(flags_l.as<int64_t>(), flags_h.as<int32_t>(), pos_l.as<int64_t>(),
-                                               pos_h.as<int32_t>(), n0, n1, g->side[0].work.as<int64_t>(),
+    compact_kernel<<<grid_1d(n), 256, 0, s>>>(flags_l.as<int64_t>(), flags_h.as<int64_t>(), pos_l.as<int64_t>(),
+                                               pos_h.as<int64_t>(), n0, n1, g->side[0].work.as<int64_t>(),
                                                g->side[1].work.as<int64_t>(), g->side[0].lo.as<int32_t>(),
                                                g->side[1].lo.as<int32_t>(), g->side[0].off.as<int32_t>(),
                                                g->side[1].off.as<int32_t>(), (int64_t)g->tune.medium_max_wedges, KU,
@@ -827,7 +834,7 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
       radix_sort_u32(hkey.as<uint32_t>(), hcode.as<uint32_t>(), hkey_tmp.as<uint32_t>(), hval_tmp.as<uint32_t>(), n,
                      16, s);
     heavy_entries_kernel<<<grid_1d(n), 256, 0, s>>>(
-        hcode.as<uint32_t>(), pos_h.as<int32_t>() + n, g->side[0].off.as<int32_t>(), g->side[1].off.as<int32_t>(),
+        hcode.as<uint32_t>(), pos_h.as<int64_t>() + n, g->side[0].off.as<int32_t>(), g->side[1].off.as<int32_t>(),
         g->side[0].lo.as<int32_t>(), g->side[1].lo.as<int32_t>(), g->side[0].work.as<int64_t>(),
         g->side[1].work.as<int64_t>(), sc.heavy.as<int4>());
     BFC_LAUNCH_CHECK();
@@ -872,8 +879,9 @@ void finish_schedule(bfc_graph_s* g, hipStream_t s) {
   sc.max_start_wedges = t[6];
   sc.n_medium = (int32_t)t[7];
   sc.n_small = (int32_t)(t[8] & 0xFFFFFFFFll);
-  sc.n_light = sc.n_small + (int32_t)(t[8] >> 32);
-  sc.n_heavy = (int32_t)t[9];
+  sc.n_mid = (int32_t)(t[8] >> 32);
+  sc.n_light = sc.n_small + sc.n_mid + (int32_t)(t[9] >> 32);
+  sc.n_heavy = (int32_t)(t[9] & 0xFFFFFFFFll);
   sc.light_max = g->tune.light_max_wedges < g->light_max_cap() ? g->tune.light_max_wedges : g->light_max_cap();
   sc.medium_max = g->tune.medium_max_wedges;
   int64_t cat = 0;

@@ -293,18 +293,19 @@ __device__ __forceinline__ int32_t wave_packed_get(const uint32_t* tab, uint32_t
 }
 
 // ------------------------------------------------------------ light
-// Light starts come in two classes by wedge count: up to kSmallMax wedges
-// (a 512-entry table per wavefront, so a CU holds 32 wavefronts) and the
-// rest up to light_max: 2048 wedges in packed 4,096-entry tables where the
-// layers allow packing, else 1024 wedges in 2,048-entry tables (both 16 KB,
-// 8 wavefronts per CU).  A table has at least twice as many entries as its
-// start has wedges.
+// Light starts come in three classes by wedge count: up to kSmallMax wedges
+// (a 512-entry table per wavefront, so a CU holds 32 wavefronts), up to
+// kLightMidMax (2,048 entries: packed, 8 KB, about 20 wavefronts per CU, or
+// key and count, 16 KB, 8 per CU) and, where the layers allow packing, up to
+// light_max = 2048 (packed 4,096 entries, 16 KB, 8 per CU).  A table has at
+// least twice as many entries as its start has wedges.
 constexpr int kLightNT = 256;
 constexpr int kLightWaves = kLightNT / 64;
-constexpr int kLightCap = 2048;        // unpacked: light_max <= kLightCap / 2
+constexpr int kLightCap = 2048;        // mid class: kLightMidMax <= kLightCap / 2
 constexpr int kLightPackedCap = 4096;  // packed: light_max <= kLightPackedCap / 2
 constexpr int kSmallCap = 2 * kSmallMax;
 static_assert(kLightPackedCap / 2 < (1 << kLightCountBits), "packed counts must fit");
+static_assert(kLightMidMax <= kLightCap / 2, "mid starts must fit the mid table");
 
 // Each entry of the light list is {code, first slot of N(r), middles, wedges}.
 template <int kMode, int kCap, bool kPacked>
@@ -1560,13 +1561,13 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   dense_block(g, s);
   if (g->timing) BFC_HIP(hipEventRecord(tc.ev[1], s));
   {
-    // the light list holds the small starts, then the others
+    // the light list holds the small starts, then the mid ones, then the large ones
     const int4* llist = g->sched.light.as<int4>();
     auto light_grid = [&](int32_t n) {
       int64_t grid = ((int64_t)n + kLightWaves - 1) / kLightWaves;
       return (unsigned)(grid > (int64_t)cus * 16 ? (int64_t)cus * 16 : grid);
     };
-    const int32_t n_small = sc.n_small, n_large = sc.n_light - sc.n_small;
+    const int32_t n_small = sc.n_small, n_mid = sc.n_mid, n_large = sc.n_light - sc.n_small - sc.n_mid;
     if (n_small > 0) {
       const unsigned grid = light_grid(n_small);
       if (mode == kTotal) light_kernel<kTotal, kSmallCap, false><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
@@ -1574,18 +1575,27 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
       else light_kernel<kEdge, kSmallCap, false><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
       BFC_LAUNCH_CHECK();
     }
-    if (n_large > 0) {
-      const unsigned grid = light_grid(n_large);
+    if (n_mid > 0) {
+      const unsigned grid = light_grid(n_mid);
       const int4* l = llist + n_small;
       if (g->light_packed) {
-        if (mode == kTotal) light_kernel<kTotal, kLightPackedCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_large);
-        else if (mode == kVertex) light_kernel<kVertex, kLightPackedCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_large);
-        else light_kernel<kEdge, kLightPackedCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+        if (mode == kTotal) light_kernel<kTotal, kLightCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_mid);
+        else if (mode == kVertex) light_kernel<kVertex, kLightCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_mid);
+        else light_kernel<kEdge, kLightCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_mid);
       } else {
-        if (mode == kTotal) light_kernel<kTotal, kLightCap, false><<<grid, kLightNT, 0, s>>>(p, l, n_large);
-        else if (mode == kVertex) light_kernel<kVertex, kLightCap, false><<<grid, kLightNT, 0, s>>>(p, l, n_large);
-        else light_kernel<kEdge, kLightCap, false><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+        if (mode == kTotal) light_kernel<kTotal, kLightCap, false><<<grid, kLightNT, 0, s>>>(p, l, n_mid);
+        else if (mode == kVertex) light_kernel<kVertex, kLightCap, false><<<grid, kLightNT, 0, s>>>(p, l, n_mid);
+        else light_kernel<kEdge, kLightCap, false><<<grid, kLightNT, 0, s>>>(p, l, n_mid);
       }
+      BFC_LAUNCH_CHECK();
+    }
+    if (n_large > 0) {
+      // only where the tables pack (light_max above 1024)
+      const unsigned grid = light_grid(n_large);
+      const int4* l = llist + n_small + n_mid;
+      if (mode == kTotal) light_kernel<kTotal, kLightPackedCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+      else if (mode == kVertex) light_kernel<kVertex, kLightPackedCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_large);
+      else light_kernel<kEdge, kLightPackedCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_large);
       BFC_LAUNCH_CHECK();
     }
   }

@@ -23,8 +23,11 @@ constexpr int32_t kWinMinDegree = 64;
 // info block (past the status words and the schedule totals), and its size
 constexpr int kInfoCaterpillars = 192;
 constexpr int kInfoBytes = kInfoCaterpillars + 64 * 8;
-// Light starts of at most this many wedges use the small-table kernel.
+// Light starts of at most kSmallMax wedges use the small-table kernel, those
+// of at most kLightMidMax the mid-table one, the rest (to light_max) the
+// large-table one.
 constexpr int32_t kSmallMax = 256;
+constexpr int32_t kLightMidMax = 1024;
 
 // ------------------------------------------------------------ errors
 struct Error {
@@ -120,7 +123,8 @@ struct Side {
 
 struct Schedule {
   int32_t n_light = 0;   // starts counted by one wavefront
-  int32_t n_small = 0;   // of those, the first n_small have at most kSmallMax wedges
+  int32_t n_small = 0;   // of those, the first n_small have at most kSmallMax wedges,
+  int32_t n_mid = 0;     // the next n_mid at most kLightMidMax, the rest more
   int32_t n_heavy = 0;   // starts counted by one workgroup
   int32_t n_medium = 0;  // of those, the last n_medium use the 256-thread shape
   DevBuf light;          // int4 {code (side << 30 | rank), off[rank], lo[rank], wedges}
