@@ -16,6 +16,9 @@ The arithmetic lives in ``oracle.c`` (plain C, OpenMP over start vertices):
 * ``priorities``     -- Definition 3's priority as a rank in [0, n)
 * ``caterpillars``   -- Section 1: the three-paths C_G, sum over edges (u, v) of
   (d_u - 1)(d_v - 1), the denominator of the clustering coefficient 4 B_G / C_G
+* ``k_wing``         -- Section 1: the k-wing, the largest subgraph whose every edge
+  lies in at least k butterflies, by the peeling the paper describes (remove the
+  edge with the fewest butterflies while below k, updating the others' counts)
 
 Vertices carry the global ids of Section 2: lower v -> v, upper u -> |L| + u.
 """
@@ -73,6 +76,8 @@ def _load():
     lib.orc_vp_count_wedge.restype = i64
     lib.orc_caterpillars.argtypes = [vp, i64, i64, i64, vp]
     lib.orc_caterpillars.restype = i32
+    lib.orc_k_wing.argtypes = [vp, i64, i64, i64, i64, i32, vp, vp, vp]
+    lib.orc_k_wing.restype = i32
     lib.orc_max_threads.argtypes = []
     lib.orc_max_threads.restype = i32
     _lib = lib
@@ -205,6 +210,22 @@ def caterpillars(g) -> int:
     out = ctypes.c_int64(0)
     _check(_load().orc_caterpillars(p, e.shape[0], g.n_upper, g.n_lower, ctypes.byref(out)), "caterpillars")
     return int(out.value)
+
+
+def k_wing(g, k: int, nthreads: int | None = None) -> tuple[np.ndarray, np.ndarray, int]:
+    """The k-wing of Section 1 by sequential peeling.
+
+    Returns (in_wing bool [m], butterflies of each edge within the k-wing
+    (0 outside it) int64 [m], number of edges removed)."""
+    e, p = _edges(g)
+    m = e.shape[0]
+    mask = np.zeros(m, dtype=np.uint8)
+    cnt = np.zeros(m, dtype=np.int64)
+    removed = ctypes.c_int64(0)
+    _check(_load().orc_k_wing(p, m, g.n_upper, g.n_lower, int(k), threads(nthreads),
+                              mask.ctypes.data if m else None, cnt.ctypes.data if m else None,
+                              ctypes.byref(removed)), "k_wing")
+    return mask.astype(bool), cnt, int(removed.value)
 
 
 def clustering_coefficient(g) -> float:

@@ -466,3 +466,149 @@ int orc_caterpillars(const int32_t* edges, int64_t m, int64_t nU, int64_t nL, in
 }
 
 int orc_max_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------- k-wing */
+
+/* The k-wing (Section 1, computing k-wing in bipartite graphs): the largest
+ * subgraph in which every edge lies in at least k butterflies.  Following the
+ * peeling the paper describes: count the butterflies of every edge (Eq. 8),
+ * then repeatedly remove the remaining edge with the fewest butterflies while
+ * that number is below k.  Removing e = (u, v) destroys exactly the
+ * butterflies (u, v, u2, v2) with u2 in N(v), v2 in N(u) and (u2, v2) a
+ * remaining edge; each of its three other edges loses one.  Edges below k wait
+ * in a binary min-heap on (count, edge index) with a position index, so a
+ * count that drops moves its edge up in place.
+ *
+ * Output: in_wing[i] = 1 for the input edges of the k-wing, else 0; counts[i]
+ * (may be NULL) the butterflies of edge i within the k-wing, 0 outside it.
+ * *removed_out (may be NULL) receives the number of removed edges. */
+typedef struct {
+  int32_t* heap;   /* edge indices */
+  int32_t* pos;    /* heap position of each edge, -1 when absent */
+  int64_t n;
+  const int64_t* key;
+} wing_heap;
+
+static int heap_less(const wing_heap* h, int32_t a, int32_t b) {
+  return h->key[a] < h->key[b] || (h->key[a] == h->key[b] && a < b);
+}
+
+static void heap_up(wing_heap* h, int64_t i) {
+  int32_t e = h->heap[i];
+  while (i > 0) {
+    int64_t p = (i - 1) / 2;
+    if (!heap_less(h, e, h->heap[p])) break;
+    h->heap[i] = h->heap[p];
+    h->pos[h->heap[i]] = (int32_t)i;
+    i = p;
+  }
+  h->heap[i] = e;
+  h->pos[e] = (int32_t)i;
+}
+
+static void heap_down(wing_heap* h, int64_t i) {
+  int32_t e = h->heap[i];
+  for (;;) {
+    int64_t c = 2 * i + 1;
+    if (c >= h->n) break;
+    if (c + 1 < h->n && heap_less(h, h->heap[c + 1], h->heap[c])) ++c;
+    if (!heap_less(h, h->heap[c], e)) break;
+    h->heap[i] = h->heap[c];
+    h->pos[h->heap[i]] = (int32_t)i;
+    i = c;
+  }
+  h->heap[i] = e;
+  h->pos[e] = (int32_t)i;
+}
+
+static void heap_push_or_raise(wing_heap* h, int32_t e) {
+  if (h->pos[e] >= 0) { heap_up(h, h->pos[e]); return; }
+  h->heap[h->n] = e;
+  heap_up(h, h->n++);
+}
+
+static int32_t heap_pop(wing_heap* h) {
+  int32_t top = h->heap[0];
+  h->pos[top] = -1;
+  if (--h->n > 0) {
+    h->heap[0] = h->heap[h->n];
+    heap_down(h, 0);
+  }
+  return top;
+}
+
+typedef struct { int32_t nbr; int32_t eid; } nbr_eid;
+
+static int cmp_nbr_eid(const void* a, const void* b) {
+  int32_t x = ((const nbr_eid*)a)->nbr, y = ((const nbr_eid*)b)->nbr;
+  return (x > y) - (x < y);
+}
+
+int orc_k_wing(const int32_t* edges, int64_t m, int64_t nU, int64_t nL, int64_t k, int nthreads,
+               uint8_t* in_wing, int64_t* counts, int64_t* removed_out) {
+  if (!in_wing && m > 0) return -1;
+  bigraph g;
+  int rc = load_graph(&g, edges, m, nU, nL);
+  if (rc) return rc;
+  int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+  uint8_t* alive = (uint8_t*)malloc((size_t)(m > 0 ? m : 1));
+  wing_heap h = {(int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)),
+                 (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)), 0, NULL};
+  /* both layers' lists sorted by neighbour, with edge indices */
+  nbr_eid* su = (nbr_eid*)malloc(sizeof(nbr_eid) * (size_t)(m > 0 ? m : 1));
+  nbr_eid* sl = (nbr_eid*)malloc(sizeof(nbr_eid) * (size_t)(m > 0 ? m : 1));
+  if (!cnt || !alive || !h.heap || !h.pos || !su || !sl) { rc = -3; goto done; }
+  rc = edge_counts(&g.up, &g.lo, cnt, nthreads > 0 ? nthreads : 1);
+  if (rc) goto done;
+  for (int64_t a = 0; a < m; ++a) {
+    su[a].nbr = g.up.nbr[a]; su[a].eid = g.up.eid[a];
+    sl[a].nbr = g.lo.nbr[a]; sl[a].eid = g.lo.eid[a];
+  }
+  for (int64_t x = 0; x < nU; ++x)
+    qsort(su + g.up.off[x], (size_t)(g.up.off[x + 1] - g.up.off[x]), sizeof(nbr_eid), cmp_nbr_eid);
+  for (int64_t x = 0; x < nL; ++x)
+    qsort(sl + g.lo.off[x], (size_t)(g.lo.off[x + 1] - g.lo.off[x]), sizeof(nbr_eid), cmp_nbr_eid);
+  h.key = cnt;
+  for (int64_t i = 0; i < m; ++i) {
+    alive[i] = 1;
+    h.pos[i] = -1;
+    if (cnt[i] < k) heap_push_or_raise(&h, (int32_t)i);
+  }
+  int64_t removed = 0;
+  while (h.n > 0) {
+    const int32_t e = heap_pop(&h);  /* the remaining edge with the fewest butterflies, below k */
+    const int32_t u = edges[2 * e], v = edges[2 * e + 1];
+    alive[e] = 0;
+    ++removed;
+    /* every butterfly (u, v, u2, v2) still present loses e */
+    for (int64_t b = g.lo.off[v]; b < g.lo.off[v + 1]; ++b) {
+      const int32_t u2 = sl[b].nbr, e1 = sl[b].eid;   /* e1 = (u2, v) */
+      if (u2 == u || !alive[e1]) continue;
+      for (int64_t c = g.up.off[u]; c < g.up.off[u + 1]; ++c) {
+        const int32_t v2 = su[c].nbr, e2 = su[c].eid;  /* e2 = (u, v2) */
+        if (v2 == v || !alive[e2]) continue;
+        int64_t lo = g.up.off[u2], hi = g.up.off[u2 + 1];
+        while (lo < hi) {
+          int64_t mid = lo + (hi - lo) / 2;
+          if (su[mid].nbr < v2) lo = mid + 1; else hi = mid;
+        }
+        if (lo == g.up.off[u2 + 1] || su[lo].nbr != v2) continue;
+        const int32_t e3 = su[lo].eid;                 /* e3 = (u2, v2) */
+        if (!alive[e3]) continue;
+        const int32_t hit[3] = {e1, e2, e3};
+        for (int t = 0; t < 3; ++t) {
+          if (--cnt[hit[t]] < k) heap_push_or_raise(&h, hit[t]);
+        }
+      }
+    }
+  }
+  for (int64_t i = 0; i < m; ++i) {
+    in_wing[i] = alive[i];
+    if (counts) counts[i] = alive[i] ? cnt[i] : 0;
+  }
+  if (removed_out) *removed_out = removed;
+done:
+  free(cnt); free(alive); free(h.heap); free(h.pos); free(su); free(sl);
+  free_graph(&g);
+  return rc;
+}

@@ -301,3 +301,127 @@ def test_caterpillars_even_cycles_and_forests(k):
     assert oracle.caterpillars(gg.even_cycle(k)) == 2 * k
     g = gg.random_forest(k, 200, 150)
     assert oracle.clustering_coefficient(g) == 0.0
+
+
+# ---------------------------------------------------------------- k-wing
+
+def brute_k_wing(g, k):
+    """The k-wing by its definition (Section 1): the largest edge subset in which
+    every edge lies in at least k butterflies of the subset.  Subsets with that
+    property are closed under union (counts only grow with more edges), so the
+    k-wing is the union of all of them; enumerated over every subset."""
+    m = g.m
+    edges = list(map(tuple, g.edges.tolist()))
+    idx = {e: i for i, e in enumerate(edges)}
+    flies = []
+    for u, w in itertools.combinations(range(g.n_upper), 2):
+        for v, x in itertools.combinations(range(g.n_lower), 2):
+            four = [(u, v), (u, x), (w, v), (w, x)]
+            if all(e in idx for e in four):
+                flies.append([idx[e] for e in four])
+    union = 0
+    for s in range(1 << m):
+        c = [0] * m
+        for f in flies:
+            if all(s >> i & 1 for i in f):
+                for i in f:
+                    c[i] += 1
+        if all(c[i] >= k for i in range(m) if s >> i & 1):
+            union |= s
+    mask = np.array([bool(union >> i & 1) for i in range(m)])
+    cnt = np.zeros(m, np.int64)
+    for f in flies:
+        if all(mask[i] for i in f):
+            for i in f:
+                cnt[i] += 1
+    return mask, cnt
+
+
+def small_wing_graphs(count, seed0):
+    rng = np.random.default_rng(seed0)
+    made = 0
+    i = 0
+    while made < count:
+        i += 1
+        g = gg.random_small(seed0 + i, int(rng.integers(2, 5)), int(rng.integers(2, 6)),
+                            float(rng.choice([0.5, 0.7, 0.9, 1.0])))
+        if 0 < g.m <= 13:
+            made += 1
+            yield g
+
+
+def test_k_wing_equals_definition_by_enumeration():
+    for g in small_wing_graphs(60, 7300):
+        top = int(oracle.edge_counts(g).max()) if g.m else 0
+        for k in range(0, top + 2):
+            mask, cnt = brute_k_wing(g, k)
+            o_mask, o_cnt, removed = oracle.k_wing(g, k)
+            np.testing.assert_array_equal(o_mask, mask)
+            np.testing.assert_array_equal(o_cnt, cnt)
+            assert removed == g.m - int(mask.sum())
+
+
+def _disjoint_union(parts):
+    es, ou, ol = [], 0, 0
+    for g in parts:
+        es.append(g.edges + np.array([ou, ol], np.int32))
+        ou += g.n_upper
+        ol += g.n_lower
+    return gg.Graph(np.ascontiguousarray(np.concatenate(es)), ou, ol, "union")
+
+
+def test_k_wing_bicliques_and_pendants():
+    # K_{3,3}: 4 butterflies per edge; K_{4,5}: 12; a path hanging off K_{4,5}
+    # and a tree lie in none
+    k33, k45 = gg.complete_bipartite(3, 3), gg.complete_bipartite(4, 5)
+    tree = gg.random_forest(3, 30, 20)
+    g = _disjoint_union([k33, k45, tree])
+    # a two-edge path from K_{4,5}'s first upper vertex through a new lower
+    # vertex to a new upper vertex
+    extra = np.array([[k33.n_upper, g.n_lower], [g.n_upper, g.n_lower]], np.int32)
+    g = gg.Graph(np.ascontiguousarray(np.concatenate([g.edges, extra])), g.n_upper + 1, g.n_lower + 1, "g")
+    n33, n45 = k33.m, k45.m
+    for k, keep33, keep45 in [(1, True, True), (4, True, True), (5, False, True), (12, False, True),
+                              (13, False, False)]:
+        mask, cnt, removed = oracle.k_wing(g, k)
+        assert mask[:n33].all() == keep33 and (not mask[:n33].any()) == (not keep33)
+        assert mask[n33:n33 + n45].all() == keep45 and (not mask[n33:n33 + n45].any()) == (not keep45)
+        assert not mask[n33 + n45:].any()
+        assert (cnt[:n33] == (4 if keep33 else 0)).all() and (cnt[n33:n33 + n45] == (12 if keep45 else 0)).all()
+        assert removed == g.m - int(mask.sum())
+    mask, cnt, removed = oracle.k_wing(g, 0)
+    assert mask.all() and removed == 0
+    np.testing.assert_array_equal(cnt, oracle.edge_counts(g))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_k_wing_even_cycles_and_forests(k):
+    # C_4 is one butterfly; longer even cycles and forests have none
+    mask, cnt, _ = oracle.k_wing(gg.even_cycle(2), k)
+    assert mask.all() == (k <= 1) and (cnt == (1 if k <= 1 else 0)).all()
+    for g in (gg.even_cycle(5), gg.random_forest(k, 300, 200)):
+        mask, cnt, removed = oracle.k_wing(g, k)
+        assert not mask.any() and removed == g.m
+
+
+@pytest.mark.parametrize("seed,k", [(41, 3), (42, 10), (43, 40)])
+def test_k_wing_equals_batch_peeling_on_medium_graphs(seed, k):
+    """Every edge below k in a graph containing the k-wing lies outside it, so
+    removing all of them at once and recounting (Eq. 8) until none is below k
+    reaches the same subgraph as removing them one at a time."""
+    g = gg.chung_lu(seed, 1500, 1200, 12000, 2.1, 2.2, 300.0, blocks=2, block=12, density=0.8)
+    keep = np.arange(g.m)
+    while True:
+        sub = gg.Graph(np.ascontiguousarray(g.edges[keep]), g.n_upper, g.n_lower, "sub")
+        c = oracle.edge_counts(sub)
+        if (c >= k).all():
+            break
+        keep = keep[c >= k]
+    mask, cnt, removed = oracle.k_wing(g, k)
+    want = np.zeros(g.m, bool)
+    want[keep] = True
+    np.testing.assert_array_equal(mask, want)
+    full = np.zeros(g.m, np.int64)
+    full[keep] = c
+    np.testing.assert_array_equal(cnt, full)
+    assert 0 < mask.sum() < g.m
