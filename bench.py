@@ -37,9 +37,9 @@ DEFAULT_WORKLOAD = "chunglu-1m-500k-20m"
 # hash to the value they were measured with (any change voids the figure).
 HEAVY_TRAFFIC = {
     "workload": DEFAULT_WORKLOAD,
-    "sources_sha256": "a3f3c840e091567286ab019dc9f9c44630f45c52b9c8b2567f8adba28b5a6bb9",
-    "fetch_kib": 17114805.9,
-    "write_kib": 887130.4,
+    "sources_sha256": "5aab9259654873ec80ad0d04da652134f6ea0815fa3d9ea7dc3c622ec8b0acda",
+    "fetch_kib": 16912209.2,
+    "write_kib": 887343.2,
     "fetch_factor": 2.0,
     "write_factor": 1.0,
 }
