@@ -120,6 +120,27 @@ bfc_status bfc_caterpillars(bfc_graph g, int64_t* caterpillars_host);
 bfc_status bfc_clustering_coefficient(bfc_graph g, void* stream, double* coefficient_host);
 
 /*
+ * k-wing (Section 1, computing k-wing in bipartite graphs): the largest
+ * subgraph in which every edge lies in at least k butterflies, as the peeling
+ * the paper describes defines it.  Edges below k in a subgraph that contains
+ * the k-wing are outside it, so each round counts every remaining edge
+ * exactly (bfc_count_per_edge), removes all edges below k at once and
+ * rebuilds the rest, until no edge is below k.
+ *   edges_dev, m, n_upper, n_lower  as in bfc_build (same checks and errors)
+ *   k               the threshold; k <= 0 keeps every edge
+ *   in_wing_dev     device uint8 [m]: 1 for the input edges of the k-wing, else 0
+ *   counts_dev      device int64 [m] or NULL: butterflies of each edge within
+ *                   the k-wing, 0 for the edges outside it
+ *   wing_edges_host, rounds_host  may be NULL: edges in the k-wing, count rounds
+ * Outputs are in the input edge order.  Blocking: returns after the outputs
+ * are written (waits on `stream`, once per round).  Device memory: one build
+ * of the remaining edges at a time plus 28 bytes per input edge.
+ */
+bfc_status bfc_k_wing(const int32_t* edges_dev, int64_t m, int32_t n_upper, int32_t n_lower, int64_t k,
+                      void* stream, uint8_t* in_wing_dev, int64_t* counts_dev, int64_t* wing_edges_host,
+                      int32_t* rounds_host);
+
+/*
  * Batched form: G independent graphs built into one handle and counted by
  * one set of kernel launches.  Graph g's edges are rows
  * [edge_offsets[g], edge_offsets[g+1]) of edges_dev, with its own 0-based

@@ -32,7 +32,7 @@ EXPORTS = [
     "bfc_graph_info", "bfc_estimate_device_bytes", "bfc_destroy", "bfc_set_tuning", "bfc_get_tuning",
     "bfc_last_error", "bfc_version", "bfc_get_schedule_info", "bfc_set_kernel_timing", "bfc_get_kernel_times",
     "bfc_build_batch", "bfc_count_total_batch", "bfc_batch_wedges", "bfc_graph_capture_total", "bfc_graph_replay",
-    "bfc_graph_count", "bfc_caterpillars", "bfc_clustering_coefficient",
+    "bfc_graph_count", "bfc_caterpillars", "bfc_clustering_coefficient", "bfc_k_wing",
 ]
 
 
@@ -93,6 +93,7 @@ def load(path: str | None = None):
         "bfc_graph_count": ([vp, pi32], i32),
         "bfc_caterpillars": ([vp, pi64], i32),
         "bfc_clustering_coefficient": ([vp, vp, ctypes.POINTER(ctypes.c_double)], i32),
+        "bfc_k_wing": ([vp, i64, i32, i32, i64, vp, vp, vp, pi64, pi32], i32),
         "bfc_last_error": ([], ctypes.c_char_p),
         "bfc_version": ([], ctypes.c_char_p),
     }
@@ -285,6 +286,23 @@ def build_batch(edges: torch.Tensor, edge_offsets, n_upper, n_lower, stream=None
     """Batched build: graph g owns edge rows [edge_offsets[g], edge_offsets[g+1])."""
     return Graph(edges, int(sum(int(x) for x in n_upper)), int(sum(int(x) for x in n_lower)), stream,
                  _batch=(edge_offsets, n_upper, n_lower))
+
+
+def k_wing(edges: torch.Tensor, n_upper: int, n_lower: int, k: int, stream=None, counts: bool = True):
+    """The k-wing (``bfc_k_wing``): (in_wing bool [m], butterflies of each edge
+    within the k-wing int64 [m] or None, wing edges, count rounds)."""
+    if not isinstance(edges, torch.Tensor) or edges.dtype != torch.int32 or not edges.is_cuda:
+        raise TypeError("edges must be an int32 CUDA tensor of shape [m, 2]")
+    if edges.dim() != 2 or edges.shape[1] != 2:
+        raise ValueError("edges must have shape [m, 2]")
+    edges = edges.contiguous()
+    m = int(edges.shape[0])
+    mask = torch.empty(m, dtype=torch.uint8, device=edges.device)
+    cnt = torch.empty(m, dtype=torch.int64, device=edges.device) if counts else None
+    w, r = ctypes.c_int64(0), ctypes.c_int32(0)
+    _check(load().bfc_k_wing(_ptr(edges), m, int(n_upper), int(n_lower), int(k), _stream(stream), _ptr(mask),
+                             _ptr(cnt), ctypes.byref(w), ctypes.byref(r)))
+    return mask.bool(), cnt, int(w.value), int(r.value)
 
 
 def count_total(g: Graph, stream=None) -> tuple[int, int]:

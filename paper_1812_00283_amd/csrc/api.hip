@@ -4,6 +4,7 @@
 #include <string>
 
 #include "internal.hpp"
+#include "wing.hpp"
 
 namespace {
 thread_local std::string g_last_error;
@@ -92,6 +93,44 @@ struct CountSection {
 
 }  // namespace
 
+namespace bfc {
+
+bfc_graph_s* new_graph(const int32_t* edges_dev, int64_t m, int32_t n_upper, int32_t n_lower, hipStream_t s) {
+  if (m < 0 || n_upper < 0 || n_lower < 0) throw Error{BFC_ERR_INVALID_ARGUMENT, "negative size"};
+  if (m > 0 && !edges_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "edges_dev is null"};
+  if (m >= (int64_t(1) << 30) || n_upper >= (1 << 30) || n_lower >= (1 << 30))
+    throw Error{BFC_ERR_TOO_LARGE, "m and each layer size must be below 2^30"};
+  if (m > (int64_t)n_upper * (int64_t)n_lower)
+    throw Error{BFC_ERR_DUPLICATE_EDGE, "more edges than (upper, lower) pairs: some pair repeats"};
+  bfc_graph_s* g = new bfc_graph_s();
+  try {
+    BFC_HIP(hipGetDevice(&g->device));
+    BFC_HIP(hipEventCreateWithFlags(&g->done, hipEventDisableTiming));
+    g->m = m;
+    g->n_upper = n_upper;
+    g->n_lower = n_lower;
+    build_graph(g, edges_dev, s);
+    build_schedule(g, s);
+    finish_schedule(g, s);
+    prepare_count(g, s);
+  } catch (...) {
+    // let queued build work finish before its buffers return to the cache
+    (void)hipStreamSynchronize(s);
+    (void)hipGetLastError();
+    if (g->done) (void)hipEventDestroy(g->done);
+    delete g;
+    throw;
+  }
+  return g;
+}
+
+void delete_idle_graph(bfc_graph_s* g) {
+  if (g->done) (void)hipEventDestroy(g->done);
+  delete g;
+}
+
+}  // namespace bfc
+
 using namespace bfc;
 
 extern "C" {
@@ -118,33 +157,7 @@ bfc_status bfc_build(const int32_t* edges_dev, int64_t m, int32_t n_upper, int32
   if (out) *out = nullptr;
   return guard([&] {
     if (!out) throw Error{BFC_ERR_INVALID_ARGUMENT, "out is null"};
-    if (m < 0 || n_upper < 0 || n_lower < 0) throw Error{BFC_ERR_INVALID_ARGUMENT, "negative size"};
-    if (m > 0 && !edges_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "edges_dev is null"};
-    if (m >= (int64_t(1) << 30) || n_upper >= (1 << 30) || n_lower >= (1 << 30))
-      throw Error{BFC_ERR_TOO_LARGE, "m and each layer size must be below 2^30"};
-    if (m > (int64_t)n_upper * (int64_t)n_lower)
-      throw Error{BFC_ERR_DUPLICATE_EDGE, "more edges than (upper, lower) pairs: some pair repeats"};
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    bfc_graph_s* g = new bfc_graph_s();
-    try {
-      BFC_HIP(hipGetDevice(&g->device));
-      BFC_HIP(hipEventCreateWithFlags(&g->done, hipEventDisableTiming));
-      g->m = m;
-      g->n_upper = n_upper;
-      g->n_lower = n_lower;
-      build_graph(g, edges_dev, s);
-      build_schedule(g, s);
-      finish_schedule(g, s);
-      prepare_count(g, s);
-    } catch (...) {
-      // let queued build work finish before its buffers return to the cache
-      (void)hipStreamSynchronize(s);
-      (void)hipGetLastError();
-      if (g->done) (void)hipEventDestroy(g->done);
-      delete g;
-      throw;
-    }
-    *out = g;
+    *out = new_graph(edges_dev, m, n_upper, n_lower, static_cast<hipStream_t>(stream));
   });
 }
 
@@ -335,6 +348,19 @@ bfc_status bfc_count_per_edge(bfc_graph g, void* stream, int64_t* edge_dev) {
     CountSection cs(h, s);
     count(h, kEdge, nullptr, edge_dev, nullptr, s);
     cs.finish();
+  });
+}
+
+bfc_status bfc_k_wing(const int32_t* edges_dev, int64_t m, int32_t n_upper, int32_t n_lower, int64_t k,
+                      void* stream, uint8_t* in_wing_dev, int64_t* counts_dev, int64_t* wing_edges_host,
+                      int32_t* rounds_host) {
+  return guard([&] {
+    if (m > 0 && !in_wing_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "in_wing_dev is null"};
+    int64_t w = 0;
+    int32_t r = 0;
+    k_wing(edges_dev, m, n_upper, n_lower, k, static_cast<hipStream_t>(stream), in_wing_dev, counts_dev, &w, &r);
+    if (wing_edges_host) *wing_edges_host = w;
+    if (rounds_host) *rounds_host = r;
   });
 }
 
