@@ -274,6 +274,46 @@ def bench_serve(args) -> int:
     return 0
 
 
+def bench_kwing(args) -> int:
+    """k-wing (Section 1) of the default workload: each step is one
+    bfc_k_wing call (rounds of exact per-edge counting, removal of the edges
+    below k and rebuild) on edges already in HBM."""
+    import torch
+
+    import graphgen as gg
+    from paper_1812_00283_amd import bfc
+
+    bfc.load()
+    t = time.perf_counter()
+    g = gg.workload(DEFAULT_WORKLOAD)
+    log(f"generated {DEFAULT_WORKLOAD}: m={g.m} in {time.perf_counter() - t:.1f}s")
+    edges = torch.from_numpy(np.ascontiguousarray(g.edges)).cuda()
+    stream = torch.cuda.current_stream()
+    times, ref = [], None
+    for i in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mask, cnt, w, r = bfc.k_wing(edges, g.n_upper, g.n_lower, args.k, stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        key = (w, r, int(cnt.sum().item()))
+        ref = key if ref is None else ref
+        assert key == ref, "k-wing results differ between steps"
+        if i >= args.warmup:
+            times.append(dt)
+        log(f"k-wing step {i}: {1e3 * dt:.1f} ms, {w} of {g.m} edges in the {args.k}-wing after {r} rounds")
+    ok = bool((cnt[mask] >= args.k).all().item()) and not bool(cnt[~mask].any().item())
+    s = float(np.mean(times))
+    print(json.dumps({
+        "metric": "k-wing input edges/s", "value": g.m / s, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * s, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"kwing-{DEFAULT_WORKLOAD}", "k": args.k, "m": g.m, "wing_edges": ref[0],
+                   "rounds": ref[1], "wing_butterfly_edge_sum": ref[2], "threshold_property": ok},
+    }), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,11 +328,14 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="prefix of the arrival trace to serve")
     ap.add_argument("--serve-max-edges", type=int, default=50_000_000)
     ap.add_argument("--serve-budget-gb", type=float, default=0.0)
+    ap.add_argument("--k", type=int, default=10000, help="threshold of the k-wing workload")
     args = ap.parse_args()
     if args.workload == "batch" and args.gpus == 1:
         return bench_batch(args)
     if args.workload == "serve" and args.gpus == 1:
         return bench_serve(args)
+    if args.workload == "kwing" and args.gpus == 1:
+        return bench_kwing(args)
     if args.copy_probe:
         import torch
 

@@ -92,3 +92,50 @@ def test_empty_degenerate_and_errors(gpu_lib):
     g = gg.complete_bipartite(4, 4)
     mask, cnt, w, r = gpu_lib.k_wing(to_dev(g), 4, 4, 9, counts=False)
     assert cnt is None and w == 16 and bool(mask.all())
+
+
+def _csr(src, dst, n):
+    order = np.lexsort((dst, src))
+    off = np.zeros(n + 1, np.int64)
+    np.add.at(off, src + 1, 1)
+    return np.cumsum(off), dst[order]
+
+
+def test_full_size_workload_properties(gpu_lib):
+    """chunglu-1m-500k-20m at k = 10,000 (the benchmark's k-wing workload)."""
+    k = 10_000
+    g = gg.workload("chunglu-1m-500k-20m")
+    mask, cnt, w, r = gpu_wing(gpu_lib, g, k)
+    assert 0 < w < g.m and r > 1 and w == int(mask.sum())
+    # every edge of the k-wing is in at least k of its butterflies; no count outside it
+    assert (cnt[mask] >= k).all() and not cnt[~mask].any()
+    we = g.edges[mask]
+    wing = gg.Graph(np.ascontiguousarray(we), g.n_upper, g.n_lower, "wing")
+    du = np.bincount(we[:, 0], minlength=g.n_upper).astype(np.int64)
+    dl = np.bincount(we[:, 1], minlength=g.n_lower).astype(np.int64)
+    # cost of one Eq. 8 evaluation on the wing: the upper degrees summed over N(v)
+    reach = np.bincount(we[:, 1], weights=du[we[:, 0]], minlength=g.n_lower)
+    rng = np.random.default_rng(12)
+    idx = np.flatnonzero(mask)
+    cheap = idx[reach[g.edges[idx, 1]] <= 2_000_000]
+    sample = rng.choice(cheap, size=min(150, len(cheap)), replace=False)
+    with oracle.Single(wing) as one:
+        for i in sample:
+            u, v = (int(x) for x in g.edges[i])
+            assert one.edge(u, v) == cnt[i], (i, u, v)
+    # maximality of the k-wing: an edge outside it, added back alone, lies in
+    # fewer than k butterflies of the wing plus itself (else the union would
+    # be a larger subgraph with every edge at k or more)
+    uoff, unbr = _csr(we[:, 0], we[:, 1], g.n_upper)
+    loff, lnbr = _csr(we[:, 1], we[:, 0], g.n_lower)
+    out = np.flatnonzero(~mask)
+    e_out = g.edges[out]
+    cost = dl[e_out[:, 1]] * np.maximum(du[e_out[:, 0]], 1)
+    pick = rng.choice(out[cost <= 400_000], size=150, replace=False)
+    for i in pick:
+        u, v = (int(x) for x in g.edges[i])
+        nu = unbr[uoff[u]:uoff[u + 1]]
+        c = 0
+        for u2 in lnbr[loff[v]:loff[v + 1]]:
+            c += np.intersect1d(nu, unbr[uoff[u2]:uoff[u2 + 1]], assume_unique=True).size
+        assert c < k, (i, u, v, c)
