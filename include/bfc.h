@@ -120,6 +120,22 @@ bfc_status bfc_caterpillars(bfc_graph g, int64_t* caterpillars_host);
 bfc_status bfc_clustering_coefficient(bfc_graph g, void* stream, double* coefficient_host);
 
 /*
+ * B_G by sorting vertex pairs (Section 7, Algorithm 6, with device memory in
+ * the place of disk): every wedge Algorithm 2 processes gives the pair
+ * (end, start); equal pairs are brought together by a radix sort and every
+ * run of c equal pairs adds C(c, 2) (Lemma 1).  Pairs are emitted, sorted and
+ * counted in chunks of consecutive start ranks of one layer holding at most
+ * max_pairs pairs (<= 0 or above 2^31: 2^31) plus the wedges of one start;
+ * the call needs 16 bytes of device memory per pair of its largest chunk.
+ *   total_host   B_G (int64)
+ *   chunks_host  may be NULL: the number of chunks
+ * Same result as bfc_count_total.  Blocking: waits on `stream` (not for
+ * stream capture).  BFC_ERR_TOO_LARGE if one start has 2^31 or more wedges.
+ */
+bfc_status bfc_count_total_sorted(bfc_graph g, void* stream, int64_t max_pairs, int64_t* total_host,
+                                  int64_t* chunks_host);
+
+/*
  * k-wing (Section 1, computing k-wing in bipartite graphs): the largest
  * subgraph in which every edge lies in at least k butterflies, as the peeling
  * the paper describes defines it.  Edges below k in a subgraph that contains

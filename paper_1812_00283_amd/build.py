@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbfc.so")
-SOURCES = ["alloc.hip", "primitives.hip", "build.hip", "count.hip", "dense.hip", "wing.hip", "api.hip"]
+SOURCES = ["alloc.hip", "primitives.hip", "build.hip", "count.hip", "dense.hip", "sorted.hip", "wing.hip", "api.hip"]
 ARCH = "gfx950"
 
 

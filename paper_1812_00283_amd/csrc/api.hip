@@ -4,6 +4,7 @@
 #include <string>
 
 #include "internal.hpp"
+#include "sorted.hpp"
 #include "wing.hpp"
 
 namespace {
@@ -347,6 +348,20 @@ bfc_status bfc_count_per_edge(bfc_graph g, void* stream, int64_t* edge_dev) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     CountSection cs(h, s);
     count(h, kEdge, nullptr, edge_dev, nullptr, s);
+    cs.finish();
+  });
+}
+
+bfc_status bfc_count_total_sorted(bfc_graph g, void* stream, int64_t max_pairs, int64_t* total_host,
+                                  int64_t* chunks_host) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!total_host) throw Error{BFC_ERR_INVALID_ARGUMENT, "total_host is null"};
+    DeviceScope ds(h->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    CountSection cs(h, s);
+    if (cs.capturing) throw Error{BFC_ERR_INVALID_ARGUMENT, "the sorted count waits on the stream: not capturable"};
+    count_total_sorted(h, max_pairs, s, total_host, chunks_host);
     cs.finish();
   });
 }
