@@ -12,6 +12,8 @@ The arithmetic lives in ``oracle.c`` (plain C, OpenMP over start vertices):
 * ``vertex_one`` / ``edge_one`` -- the same two formulas for a single vertex or edge
 * ``vp_wedges``      -- the number of wedges Algorithm 2 (BFC-VP) processes under
   the priority of Definition 3 (the denominator of the wedges/s metric)
+* ``vpp_wedges``     -- the number of wedges Algorithm 3 (BFC-VP++) processes (the
+  end outranks start and middle); equal to ``vp_wedges`` by Lemma 3
 * ``vp_count_wedge`` -- Algorithm 2's count_wedge map for one start vertex
 * ``priorities``     -- Definition 3's priority as a rank in [0, n)
 * ``caterpillars``   -- Section 1: the three-paths C_G, sum over edges (u, v) of
@@ -72,6 +74,8 @@ def _load():
     lib.orc_priorities.restype = i32
     lib.orc_vp_wedges.argtypes = [vp, i64, i64, i64, i32, vp, vp]
     lib.orc_vp_wedges.restype = i32
+    lib.orc_vpp_wedges.argtypes = [vp, i64, i64, i64, i32, vp, vp]
+    lib.orc_vpp_wedges.restype = i32
     lib.orc_vp_count_wedge.argtypes = [vp, i64, i64, i64, i64, vp, vp, i64]
     lib.orc_vp_count_wedge.restype = i64
     lib.orc_caterpillars.argtypes = [vp, i64, i64, i64, vp]
@@ -241,6 +245,17 @@ def vp_wedges(g, per_start: bool = False, nthreads: int | None = None):
     per = np.zeros(g.n_upper + g.n_lower, dtype=np.int64) if per_start else None
     _check(_load().orc_vp_wedges(p, e.shape[0], g.n_upper, g.n_lower, threads(nthreads), ctypes.addressof(out),
                                  per.ctypes.data if per is not None else None), "vp_wedges")
+    return (int(out.value), per) if per_start else int(out.value)
+
+
+def vpp_wedges(g, per_start: bool = False, nthreads: int | None = None):
+    """Wedges Algorithm 3 (BFC-VP++) processes: end above both start and middle.
+    With per_start, also each start's count by global id (lower v -> v, upper u -> |L| + u)."""
+    e, p = _edges(g)
+    out = ctypes.c_int64(0)
+    per = np.zeros(g.n_upper + g.n_lower, dtype=np.int64) if per_start else None
+    _check(_load().orc_vpp_wedges(p, e.shape[0], g.n_upper, g.n_lower, threads(nthreads), ctypes.byref(out),
+                                  per.ctypes.data if per_start and per.size else None), "vpp_wedges")
     return (int(out.value), per) if per_start else int(out.value)
 
 

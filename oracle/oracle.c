@@ -12,7 +12,8 @@
  *   per edge    (Section 6.1, Eq. 8): B_(u,v) = sum over w in N(v), w != u,
  *                                        of (|N(u) & N(w)| - 1)
  *   processed wedges of BFC-VP (Algorithm 2 with Definition 3): the number of
- *   wedges (u, v, w) with p(v) < p(u) and p(w) < p(u).
+ *   wedges (u, v, w) with p(v) < p(u) and p(w) < p(u); of BFC-VP++
+ *   (Algorithm 3): those with p(w) > p(u) and p(w) > p(v).
  *   caterpillars (Section 1, bipartite clustering coefficient 4 B_G / C_G):
  *   the three-paths (x, y, z, t); each has one middle edge (y, z), whose ends
  *   extend it in (d_y - 1)(d_z - 1) ways, so C_G = sum over edges of that.
@@ -399,6 +400,49 @@ int orc_vp_wedges(const int32_t* edges, int64_t m, int64_t nU, int64_t nL, int n
         if (p[mid_off + v] >= p[x]) continue;
         for (int64_t b = M->off[v]; b < M->off[v + 1]; ++b)
           if (p[end_off + M->nbr[b]] < p[x]) ++w_here;
+      }
+      if (per_start) per_start[x] = w_here;
+      sum += w_here;
+    }
+  }
+  free(p);
+  free_graph(&g);
+  if (!rc) *total = sum;
+  return rc;
+}
+
+/*
+ * Wedges processed by BFC-VP++ (Algorithm 3): for every start u, every
+ * neighbour v (no priority test on the middle), every neighbour w of v with
+ * p(w) > p(u) and p(w) > p(v): the end outranks both other vertices.
+ * Lemma 3 states that this equals the count of Algorithm 2.  per_start
+ * (nullable, [nL + nU] by global id) receives each start's count.
+ */
+int orc_vpp_wedges(const int32_t* edges, int64_t m, int64_t nU, int64_t nL, int nthreads, int64_t* total,
+                   int64_t* per_start) {
+  bigraph g;
+  int rc = load_graph(&g, edges, m, nU, nL);
+  if (rc) return rc;
+  int64_t n = nU + nL;
+  int64_t* p = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!p) { free_graph(&g); return -3; }
+  rc = priorities(&g, p);
+  int64_t sum = 0;
+  if (!rc) {
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : sum) num_threads(nthreads)
+    for (int64_t x = 0; x < n; ++x) {
+      int upper = x >= nL;
+      const side_csr* S = upper ? &g.up : &g.lo;
+      const side_csr* M = upper ? &g.lo : &g.up;
+      int64_t s = upper ? x - nL : x;
+      int64_t mid_off = upper ? 0 : nL;
+      int64_t end_off = upper ? nL : 0;
+      int64_t w_here = 0;
+      for (int64_t a = S->off[s]; a < S->off[s + 1]; ++a) {
+        int64_t v = S->nbr[a];
+        int64_t top = p[mid_off + v] > p[x] ? p[mid_off + v] : p[x];
+        for (int64_t b = M->off[v]; b < M->off[v + 1]; ++b)
+          if (p[end_off + M->nbr[b]] > top) ++w_here;
       }
       if (per_start) per_start[x] = w_here;
       sum += w_here;

@@ -187,6 +187,31 @@ def test_vp_wedges_closed_form_and_bounds(seed):
     assert tot == w == int(per.sum())
 
 
+@pytest.mark.parametrize("seed", range(30))
+def test_vpp_wedges_lemma3_and_enumeration(seed):
+    """Algorithm 3's wedges: the end outranks start and middle.  Per middle x
+    they are the pairs of neighbours u < w with w above x, the same
+    h_x (d_x - 1) - h_x (h_x - 1) / 2 as Algorithm 2 (Lemma 3); per start they
+    are enumerated here from the numpy ranks."""
+    rng = np.random.default_rng(100 + seed)
+    g = gg.random_small(100 + seed, int(rng.integers(2, 25)), int(rng.integers(2, 25)), float(rng.uniform(0.1, 0.8)))
+    w, rank = _wedge_closed_form(g)
+    tot, per = oracle.vpp_wedges(g, per_start=True)
+    assert tot == w == oracle.vp_wedges(g) == int(per.sum())
+    nL = g.n_lower
+    nb = {}
+    for u, v in g.edges.tolist():
+        nb.setdefault(nL + u, []).append(v)
+        nb.setdefault(v, []).append(nL + u)
+    want = np.zeros(nL + g.n_upper, np.int64)
+    for x, mids in nb.items():
+        for v in mids:
+            for y in nb[v]:
+                if rank[y] > rank[x] and rank[y] > rank[v]:
+                    want[x] += 1
+    np.testing.assert_array_equal(per, want)
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_sum_rules_and_invariances(seed):
     g = gg.random_small(500 + seed, 30, 45, 0.3)
