@@ -121,19 +121,28 @@ bfc_status bfc_clustering_coefficient(bfc_graph g, void* stream, double* coeffic
 
 /*
  * B_G by sorting vertex pairs (Section 7, Algorithm 6, with device memory in
- * the place of disk): every wedge Algorithm 2 processes gives the pair
- * (end, start); equal pairs are brought together by a radix sort and every
- * run of c equal pairs adds C(c, 2) (Lemma 1).  Pairs are emitted, sorted and
- * counted in chunks of consecutive start ranks of one layer holding at most
- * max_pairs pairs (<= 0 or above 2^31: 2^31) plus the wedges of one start;
- * the call needs 16 bytes of device memory per pair of its largest chunk.
+ * the place of disk): every processed wedge gives the pair (end, start);
+ * equal pairs are brought together by a radix sort and every run of c equal
+ * pairs adds C(c, 2) (Lemma 1).
+ *   direction    0: the wedges of Algorithm 2 (BFC-VP: the start outranks the
+ *                middle and the end); 1: those of Algorithm 3 (BFC-VP++,
+ *                Section 5: the end outranks the start and the middle).  Both
+ *                give B_G over the same number of wedges (Lemma 3, Theorem 4).
+ *   max_pairs    pairs per chunk: chunks are consecutive start ranks of one
+ *                layer holding at most max_pairs pairs (<= 0 or above 2^31:
+ *                2^31) plus the wedges of one start; the call needs 16 bytes
+ *                of device memory per pair of its largest chunk plus 16 per
+ *                middle arc of it
  *   total_host   B_G (int64)
+ *   pairs_host   may be NULL: the number of pairs (processed wedges)
  *   chunks_host  may be NULL: the number of chunks
  * Same result as bfc_count_total.  Blocking: waits on `stream` (not for
- * stream capture).  BFC_ERR_TOO_LARGE if one start has 2^31 or more wedges.
+ * stream capture).  BFC_ERR_TOO_LARGE if one start has so many wedges that
+ * its chunk would hold 2^32 pairs or more; BFC_ERR_INVALID_ARGUMENT for
+ * another direction.
  */
-bfc_status bfc_count_total_sorted(bfc_graph g, void* stream, int64_t max_pairs, int64_t* total_host,
-                                  int64_t* chunks_host);
+bfc_status bfc_count_total_sorted(bfc_graph g, void* stream, int32_t direction, int64_t max_pairs,
+                                  int64_t* total_host, int64_t* pairs_host, int64_t* chunks_host);
 
 /*
  * k-wing (Section 1, computing k-wing in bipartite graphs): the largest

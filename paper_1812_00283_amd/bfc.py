@@ -95,7 +95,7 @@ def load(path: str | None = None):
         "bfc_caterpillars": ([vp, pi64], i32),
         "bfc_clustering_coefficient": ([vp, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "bfc_k_wing": ([vp, i64, i32, i32, i64, vp, vp, vp, pi64, pi32], i32),
-        "bfc_count_total_sorted": ([vp, vp, i64, pi64, pi64], i32),
+        "bfc_count_total_sorted": ([vp, vp, i32, i64, pi64, pi64, pi64], i32),
         "bfc_last_error": ([], ctypes.c_char_p),
         "bfc_version": ([], ctypes.c_char_p),
     }
@@ -188,12 +188,13 @@ class Graph:
         _check(load().bfc_count_per_edge(self._h, _stream(stream), _ptr(out)))
         return out
 
-    def count_total_sorted(self, max_pairs: int = 0, stream=None) -> tuple[int, int]:
-        """(B_G, chunks) by Algorithm 6's pair sort (``bfc_count_total_sorted``)."""
-        t, c = ctypes.c_int64(0), ctypes.c_int64(0)
-        _check(load().bfc_count_total_sorted(self._h, _stream(stream), int(max_pairs), ctypes.byref(t),
-                                             ctypes.byref(c)))
-        return int(t.value), int(c.value)
+    def count_total_sorted(self, max_pairs: int = 0, stream=None, direction: int = 0) -> tuple[int, int, int]:
+        """(B_G, pairs, chunks) by Algorithm 6's pair sort (``bfc_count_total_sorted``)
+        over the wedges of Algorithm 2 (direction 0) or Algorithm 3 (direction 1)."""
+        t, p, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(load().bfc_count_total_sorted(self._h, _stream(stream), int(direction), int(max_pairs),
+                                             ctypes.byref(t), ctypes.byref(p), ctypes.byref(c)))
+        return int(t.value), int(p.value), int(c.value)
 
     def caterpillars(self) -> int:
         """C_G: the graph's three-paths, computed by the build."""

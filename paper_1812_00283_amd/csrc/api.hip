@@ -352,16 +352,17 @@ bfc_status bfc_count_per_edge(bfc_graph g, void* stream, int64_t* edge_dev) {
   });
 }
 
-bfc_status bfc_count_total_sorted(bfc_graph g, void* stream, int64_t max_pairs, int64_t* total_host,
-                                  int64_t* chunks_host) {
+bfc_status bfc_count_total_sorted(bfc_graph g, void* stream, int32_t direction, int64_t max_pairs,
+                                  int64_t* total_host, int64_t* pairs_host, int64_t* chunks_host) {
   return guard([&] {
     bfc_graph_s* h = checked(g);
     if (!total_host) throw Error{BFC_ERR_INVALID_ARGUMENT, "total_host is null"};
+    if (direction != 0 && direction != 1) throw Error{BFC_ERR_INVALID_ARGUMENT, "direction must be 0 or 1"};
     DeviceScope ds(h->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     CountSection cs(h, s);
     if (cs.capturing) throw Error{BFC_ERR_INVALID_ARGUMENT, "the sorted count waits on the stream: not capturable"};
-    count_total_sorted(h, max_pairs, s, total_host, chunks_host);
+    count_total_sorted(h, direction, max_pairs, s, total_host, pairs_host, chunks_host);
     cs.finish();
   });
 }

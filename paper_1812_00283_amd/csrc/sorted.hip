@@ -14,6 +14,13 @@
 // sort on the end bits alone (the build's sort) leaves each end's pairs in
 // start order, so equal pairs end up adjacent.  The runs are then counted
 // in one pass.
+//
+// The same machinery runs the wedges of Algorithm 3 (BFC-VP++, Section 5):
+// there the end outranks both the start and the middle, every neighbour of a
+// start is a middle, and the ends of middle v are the suffix of N(v) above
+// max(p(start), p(v)): past the start's own slot when v ranks below the
+// start, else past v's lower-priority prefix.  Same wedge count (Lemma 3),
+// same pairs-and-runs count (Theorem 4).
 #include "sorted.hpp"
 
 namespace bfc {
@@ -48,26 +55,63 @@ __global__ void chunk_bounds_kernel(const int64_t* __restrict__ offs, const int3
 }
 
 // The middle arcs of the chunk's starts as one dense list: arc q of start r
-// (its j-th neighbour, j < lo[r]) sits at q = moff[r] - q0 + j and records
-// its slice of ends (first slot, length) and r - r0.  One wavefront per start.
+// (its j-th middle) sits at q = moff[r] - q0 + j and records its slice of
+// ends (first slot, length) and r - r0.  One wavefront per start.
+// Algorithm 2 (kPlus false): the middles are the prefix lo[r] of N(r) and the
+// ends of middle v are N(v) below r.  Algorithm 3 (kPlus true, moff = off_x):
+// every neighbour is a middle and the ends are the suffix of N(v) above both.
+template <bool kPlus>
 __global__ void mid_fill_kernel(const int32_t* __restrict__ off_x, const int32_t* __restrict__ adj_x,
                                 const int32_t* __restrict__ rev_x, const int32_t* __restrict__ lo_x,
-                                const int32_t* __restrict__ off_o, const int32_t* __restrict__ moff, int32_t r0,
-                                int32_t r1, int64_t* __restrict__ qlen, int32_t* __restrict__ qbeg,
+                                const int32_t* __restrict__ off_o, const int32_t* __restrict__ lo_o,
+                                const int32_t* __restrict__ moff, int32_t r0, int32_t r1,
+                                int64_t* __restrict__ qlen, int32_t* __restrict__ qbeg,
                                 int32_t* __restrict__ qsrc) {
   const int lane = threadIdx.x & 63;
   const int32_t q0 = moff[r0];
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < r1 - r0; w += waves) {
     const int32_t r = r0 + (int32_t)w;
-    const int32_t a0 = off_x[r], nm = lo_x[r], qb = moff[r] - q0;
+    const int32_t a0 = off_x[r], lo = lo_x[r], qb = moff[r] - q0;
+    const int32_t nm = kPlus ? off_x[r + 1] - a0 : lo;
     for (int32_t j = lane; j < nm; j += 64) {
       const int32_t a = a0 + j;
-      const int32_t beg = off_o[adj_x[a]];
-      qlen[qb + j] = rev_x[a] - beg;
+      const int32_t v = adj_x[a];
+      int32_t beg, len;
+      if (kPlus) {
+        beg = j < lo ? rev_x[a] + 1 : off_o[v] + lo_o[v];
+        len = off_o[v + 1] - beg;
+      } else {
+        beg = off_o[v];
+        len = rev_x[a] - beg;
+      }
+      qlen[qb + j] = len;
       qbeg[qb + j] = beg;
       qsrc[qb + j] = r - r0;
     }
+  }
+}
+
+// W of every start under Algorithm 3: the sum of its middles' suffix
+// lengths.  One wavefront per start.
+__global__ void vpp_work_kernel(const int32_t* __restrict__ off_x, const int32_t* __restrict__ adj_x,
+                                const int32_t* __restrict__ rev_x, const int32_t* __restrict__ lo_x,
+                                const int32_t* __restrict__ off_o, const int32_t* __restrict__ lo_o, int32_t n,
+                                int64_t* __restrict__ work) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < n; w += waves) {
+    const int32_t r = (int32_t)w;
+    const int32_t a0 = off_x[r], lo = lo_x[r], d = off_x[r + 1] - a0;
+    unsigned long long t = 0;
+    for (int32_t j = lane; j < d; j += 64) {
+      const int32_t a = a0 + j;
+      const int32_t v = adj_x[a];
+      const int32_t beg = j < lo ? rev_x[a] + 1 : off_o[v] + lo_o[v];
+      t += (unsigned long long)(off_o[v + 1] - beg);
+    }
+    for (int s = 32; s > 0; s >>= 1) t += __shfl_down(t, s, 64);
+    if (lane == 0) work[r] = (int64_t)t;
   }
 }
 
@@ -211,16 +255,16 @@ __global__ __launch_bounds__(kRunNT) void run_count_kernel(const uint64_t* __res
 
 }  // namespace
 
-void count_total_sorted(bfc_graph_s* g, int64_t max_pairs, hipStream_t s, int64_t* total_host,
-                        int64_t* chunks_host) {
-  constexpr int64_t kMaxChunk = int64_t(1) << 31;
+void count_total_sorted(bfc_graph_s* g, int direction, int64_t max_pairs, hipStream_t s, int64_t* total_host,
+                        int64_t* pairs_host, int64_t* chunks_host) {
+  // the radix sort ranks keys with 32-bit offsets
+  constexpr int64_t kMaxChunk = int64_t(1) << 31, kSortLimit = int64_t(1) << 32;
+  const bool plus = direction == 1;
   if (max_pairs <= 0 || max_pairs > kMaxChunk) max_pairs = kMaxChunk;
-  if (g->sched.max_start_wedges >= kMaxChunk)
-    throw Error{BFC_ERR_TOO_LARGE, "a start has 2^31 or more wedges: beyond one sorted chunk"};
   TmpBuf tot;
   tot.alloc(sizeof(int64_t), s);
   zero_u64(tot.p, 1, s);
-  int64_t chunks = 0;
+  int64_t chunks = 0, all_pairs = 0;
   TmpBuf keys, ktmp, qlen, qbeg, qsrc;
   size_t key_cap = 0, q_cap = 0;
   for (int x = 0; x < 2; ++x) {
@@ -228,23 +272,39 @@ void count_total_sorted(bfc_graph_s* g, int64_t max_pairs, hipStream_t s, int64_
     const Side& O = g->side[x ^ 1];
     const int32_t n = S.n;
     if (n == 0) continue;
-    // per start: first pair (prefix of W) and first middle arc (prefix of lo)
-    TmpBuf offs, moff;
+    // per start: first pair (prefix of W) and first middle arc (prefix of lo,
+    // or the CSR offsets when every neighbour is a middle)
+    TmpBuf offs, moff_buf, work_plus;
     offs.alloc(sizeof(int64_t) * ((size_t)n + 1), s);
-    moff.alloc(sizeof(int32_t) * ((size_t)n + 1), s);
-    exclusive_scan_i64(S.work.as<int64_t>(), offs.as<int64_t>(), n, offs.as<int64_t>() + n, s);
-    exclusive_scan_i32(S.lo.as<int32_t>(), moff.as<int32_t>(), n, moff.as<int32_t>() + n, s);
+    const int64_t* work = S.work.as<int64_t>();
+    if (plus) {
+      work_plus.alloc(sizeof(int64_t) * (size_t)n, s);
+      const int64_t wg = ((int64_t)n + 3) / 4;
+      vpp_work_kernel<<<(unsigned)(wg < 65536 ? wg : 65536), 256, 0, s>>>(
+          S.off.as<int32_t>(), S.adj.as<int32_t>(), S.rev.as<int32_t>(), S.lo.as<int32_t>(), O.off.as<int32_t>(),
+          O.lo.as<int32_t>(), n, work_plus.as<int64_t>());
+      BFC_LAUNCH_CHECK();
+      work = work_plus.as<int64_t>();
+    }
+    exclusive_scan_i64(work, offs.as<int64_t>(), n, offs.as<int64_t>() + n, s);
+    const int32_t* moff = S.off.as<int32_t>();
+    if (!plus) {
+      moff_buf.alloc(sizeof(int32_t) * ((size_t)n + 1), s);
+      exclusive_scan_i32(S.lo.as<int32_t>(), moff_buf.as<int32_t>(), n, moff_buf.as<int32_t>() + n, s);
+      moff = moff_buf.as<int32_t>();
+    }
     int64_t pairs = 0;
     BFC_HIP(hipMemcpyAsync(&pairs, offs.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     BFC_HIP(hipStreamSynchronize(s));
+    all_pairs += pairs;
     if (pairs == 0) continue;
     const int32_t nch = (int32_t)((pairs + max_pairs - 1) / max_pairs);
     TmpBuf bnd, fst, mst;
     bnd.alloc(sizeof(int32_t) * ((size_t)nch + 1), s);
     fst.alloc(sizeof(int64_t) * ((size_t)nch + 1), s);
     mst.alloc(sizeof(int32_t) * ((size_t)nch + 1), s);
-    chunk_bounds_kernel<<<grid_for(nch + 1, 256), 256, 0, s>>>(offs.as<int64_t>(), moff.as<int32_t>(), n, max_pairs,
-                                                                nch, bnd.as<int32_t>(), fst.as<int64_t>(),
+    chunk_bounds_kernel<<<grid_for(nch + 1, 256), 256, 0, s>>>(offs.as<int64_t>(), moff, n, max_pairs, nch,
+                                                                bnd.as<int32_t>(), fst.as<int64_t>(),
                                                                 mst.as<int32_t>());
     BFC_LAUNCH_CHECK();
     std::vector<int32_t> b(nch + 1), mq(nch + 1);
@@ -254,6 +314,9 @@ void count_total_sorted(bfc_graph_s* g, int64_t max_pairs, hipStream_t s, int64_
     BFC_HIP(hipMemcpyAsync(mq.data(), mst.p, sizeof(int32_t) * (nch + 1), hipMemcpyDeviceToHost, s));
     BFC_HIP(hipStreamSynchronize(s));
     const int ebits = bits_for((uint64_t)n - 1);
+    for (int32_t c = 0; c < nch; ++c)
+      if (f[c + 1] - f[c] >= kSortLimit)
+        throw Error{BFC_ERR_TOO_LARGE, "a start has so many wedges that its chunk holds 2^32 pairs or more"};
     for (int32_t c = 0; c < nch; ++c) {
       const int32_t r0 = b[c], r1 = b[c + 1];
       const int64_t np = f[c + 1] - f[c];
@@ -270,10 +333,16 @@ void count_total_sorted(bfc_graph_s* g, int64_t max_pairs, hipStream_t s, int64_
         qsrc.alloc(sizeof(int32_t) * ((size_t)nq + 1), s);
         q_cap = (size_t)nq + 1;
       }
-      const int64_t fill_grid = ((int64_t)(r1 - r0) + 3) / 4;
-      mid_fill_kernel<<<(unsigned)(fill_grid < 65536 ? fill_grid : 65536), 256, 0, s>>>(
-          S.off.as<int32_t>(), S.adj.as<int32_t>(), S.rev.as<int32_t>(), S.lo.as<int32_t>(), O.off.as<int32_t>(),
-          moff.as<int32_t>(), r0, r1, qlen.as<int64_t>(), qbeg.as<int32_t>(), qsrc.as<int32_t>());
+      const int64_t fg = ((int64_t)(r1 - r0) + 3) / 4;
+      const unsigned fill_grid = (unsigned)(fg < 65536 ? fg : 65536);
+      if (plus)
+        mid_fill_kernel<true><<<fill_grid, 256, 0, s>>>(
+            S.off.as<int32_t>(), S.adj.as<int32_t>(), S.rev.as<int32_t>(), S.lo.as<int32_t>(), O.off.as<int32_t>(),
+            O.lo.as<int32_t>(), moff, r0, r1, qlen.as<int64_t>(), qbeg.as<int32_t>(), qsrc.as<int32_t>());
+      else
+        mid_fill_kernel<false><<<fill_grid, 256, 0, s>>>(
+            S.off.as<int32_t>(), S.adj.as<int32_t>(), S.rev.as<int32_t>(), S.lo.as<int32_t>(), O.off.as<int32_t>(),
+            O.lo.as<int32_t>(), moff, r0, r1, qlen.as<int64_t>(), qbeg.as<int32_t>(), qsrc.as<int32_t>());
       BFC_LAUNCH_CHECK();
       exclusive_scan_i64(qlen.as<int64_t>(), qlen.as<int64_t>(), nq, nullptr, s);
       pair_emit_kernel<<<grid_for(np, kEmitTile), kEmitNT, 0, s>>>(qlen.as<int64_t>(), qbeg.as<int32_t>(),
@@ -292,6 +361,7 @@ void count_total_sorted(bfc_graph_s* g, int64_t max_pairs, hipStream_t s, int64_
   BFC_HIP(hipMemcpyAsync(&v, tot.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
   *total_host = v;
+  if (pairs_host) *pairs_host = all_pairs;
   if (chunks_host) *chunks_host = chunks;
 }
 
