@@ -140,4 +140,22 @@ void cache_free_idle(void* p) {
   g_free.emplace(std::make_pair(b.device, b.size), std::make_pair(p, b));
 }
 
+// Per-thread pinned host buffer for small device-to-host read-backs: a copy
+// into pinned memory is one transfer, where a pageable destination adds a
+// staged copy and a wait of its own.  Grown on demand, kept until the
+// process ends (a few KB per calling thread).
+void* pinned_stage(size_t bytes) {
+  thread_local void* buf = nullptr;
+  thread_local size_t cap = 0;
+  if (bytes > cap) {
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    cap = 0;
+    const size_t want = bytes < 4096 ? 4096 : bytes;
+    BFC_HIP(hipHostMalloc(&buf, want, hipHostMallocDefault));
+    cap = want;
+  }
+  return buf;
+}
+
 }  // namespace bfc

@@ -176,11 +176,12 @@ bfc_status bfc_count_total(bfc_graph g, void* stream, int64_t* total_host, int64
       count(h, kTotal, tot.as<int64_t>(), nullptr, nullptr, s);
       cs.finish();
     }
-    int64_t v = 0;
-    int32_t st = 0;
-    BFC_HIP(hipMemcpyAsync(&v, tot.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    BFC_HIP(hipMemcpyAsync(&st, count_status(h), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int64_t* rb = static_cast<int64_t*>(pinned_stage(2 * sizeof(int64_t)));
+    BFC_HIP(hipMemcpyAsync(rb, tot.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    BFC_HIP(hipMemcpyAsync(rb + 1, count_status(h), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BFC_HIP(hipStreamSynchronize(s));
+    const int64_t v = rb[0];
+    const int32_t st = *reinterpret_cast<const int32_t*>(rb + 1);
     if (st) throw Error{BFC_ERR_DEVICE, "internal error: a counting window could not be sized"};
     *total_host = v;
     if (wedges_host) *wedges_host = h->sched.wedges;

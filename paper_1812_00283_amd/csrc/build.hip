@@ -475,8 +475,8 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
     max_kernel<<<(unsigned)grid, 256, 0, s>>>(deg[x].as<int32_t>(), n[x], status.as<int32_t>() + 4 + x);
     BFC_LAUNCH_CHECK();
   }
-  int32_t st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  BFC_HIP(hipMemcpyAsync(st, status.p, sizeof(st), hipMemcpyDeviceToHost, s));
+  int32_t* st = static_cast<int32_t*>(pinned_stage(8 * sizeof(int32_t)));
+  BFC_HIP(hipMemcpyAsync(st, status.p, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
   if (st[0]) throw Error{BFC_ERR_VERTEX_OUT_OF_RANGE, "an edge has an upper id outside [0,n_upper) or a lower id outside [0,n_lower)"};
 
@@ -856,13 +856,14 @@ void trim(DevBuf& b, size_t bytes, hipStream_t s) {
 
 void finish_schedule(bfc_graph_s* g, hipStream_t s) {
   Schedule& sc = g->sched;
-  int32_t st[16];
-  int64_t t[16];
-  BFC_HIP(hipMemcpyAsync(st, g->info.p, sizeof(st), hipMemcpyDeviceToHost, s));
-  BFC_HIP(hipMemcpyAsync(t, g->info.as<char>() + 64, sizeof(t), hipMemcpyDeviceToHost, s));
-  int64_t cat_slots[kCatSlots];
-  BFC_HIP(hipMemcpyAsync(cat_slots, g->info.as<char>() + kInfoCaterpillars, sizeof(cat_slots), hipMemcpyDeviceToHost, s));
+  // the whole info block in one read-back: status words, schedule totals,
+  // caterpillar slots
+  char* info = static_cast<char*>(pinned_stage(kInfoBytes));
+  BFC_HIP(hipMemcpyAsync(info, g->info.p, kInfoBytes, hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
+  const int32_t* st = reinterpret_cast<const int32_t*>(info);
+  const int64_t* t = reinterpret_cast<const int64_t*>(info + 64);
+  const int64_t* cat_slots = reinterpret_cast<const int64_t*>(info + kInfoCaterpillars);
   if (st[1]) throw Error{BFC_ERR_DUPLICATE_EDGE, "the edge list repeats an (upper, lower) pair"};
   const int32_t nn[2] = {g->side[0].n, g->side[1].n};
   for (int o = 0; o < 2; ++o) {

@@ -57,6 +57,9 @@ void set_error(bfc_status s, const std::string& what);
 void* cache_alloc(size_t bytes, hipStream_t s);
 void cache_free(void* p, hipStream_t s);
 void cache_free_idle(void* p);
+// A pinned host buffer of at least `bytes` owned by the calling thread, for
+// read-backs that the thread waits for before its next call.
+void* pinned_stage(size_t bytes);
 
 // A device buffer owned by a graph handle.  Work on a handle is ordered
 // (each count call waits for the previous one), so a buffer replaced by a
