@@ -37,9 +37,9 @@ DEFAULT_WORKLOAD = "chunglu-1m-500k-20m"
 # hash to the value they were measured with (any change voids the figure).
 HEAVY_TRAFFIC = {
     "workload": DEFAULT_WORKLOAD,
-    "sources_sha256": "5aab9259654873ec80ad0d04da652134f6ea0815fa3d9ea7dc3c622ec8b0acda",
-    "fetch_kib": 16912209.2,
-    "write_kib": 887343.2,
+    "sources_sha256": "faf2e798b838f9d56d16b787094a3e0b21016d4cb4aa90a03d8573d57754fc41",
+    "fetch_kib": 17201684.2,
+    "write_kib": 887527.3,
     "fetch_factor": 2.0,
     "write_factor": 1.0,
 }
@@ -98,6 +98,39 @@ def golden_total(name: str):
     return (rec["total"], rec["vp_wedges"], rec["edges_sha256"]) if rec else None
 
 
+def measured_copy_gbs(gib: int = 4, reps: int = 5) -> float:
+    """Device-to-device copy bandwidth on this GPU (bytes read + written per
+    second, best of `reps` copies of `gib` GiB), reported beside the published
+    HBM peak."""
+    import torch
+
+    n = gib * (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1000.0)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * gib * (1 << 30) / best / 1e9
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(g, wedges: int, target_s: float = 15.0) -> dict:
     """The oracle (Lemma 1 Eq. 1 from the layer of the sum-of-squares rule) on a
     random sample of its start vertices, scaled to the whole graph by the
@@ -143,6 +176,9 @@ def cpu_baseline(g, wedges: int, target_s: float = 15.0) -> dict:
         "value": wedges / est_full,
         "unit": "wedges/s",
         "cores": threads,
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
+        "oracle_counter_steps": total_cost,
         "kind": "oracle",
         "sample": (f"Eq. 1 walk from {k} of {n_side} {'upper' if side == 0 else 'lower'} starts "
                    f"(random, {100 * share:.1f}% of the oracle's {total_cost:.3g} counter steps) in {ts:.1f} s; "
@@ -516,6 +552,8 @@ def main() -> int:
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": hk_bytes,
             "avg_launch_ms": hk_ms,
+            "copy_measured": measured_copy_gbs(),
+            "copy_measured_unit": "GB/s, best device-to-device copy of 4 GiB (read + write bytes), after the timed steps",
         },
     }
     if not args.no_cpu_baseline:
