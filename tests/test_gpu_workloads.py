@@ -4,7 +4,9 @@ The oracle's results for these graphs are stored in golden/workloads.json by
 golden/make_golden.py (which calls only the oracle): totals, |W|, and SHA-256
 digests of the full per-vertex and per-edge int64 arrays.  The GPU outputs are
 hashed the same way, so every element is compared.  A few vertices and edges
-are also recomputed live by the oracle one at a time (Eq. 1 and Eq. 8).
+are also recomputed live by the oracle one at a time (Eq. 1 and Eq. 8).  On
+the 200M-edge graph the sort-based count (both wedge directions) is checked
+against the stored total and |W| as well.
 """
 import hashlib
 import json
@@ -37,7 +39,7 @@ def digest(t: torch.Tensor) -> str:
     return hashlib.sha256(t.cpu().numpy().astype("<i8").tobytes()).hexdigest()
 
 
-def run_workload(gpu_lib, name, per_vertex=True, per_edge=True, live_samples=8):
+def run_workload(gpu_lib, name, per_vertex=True, per_edge=True, live_samples=8, sorted_count=False):
     rec = golden(name)
     g = gg.workload(name)
     print(f"{name}: generated m={g.m}", flush=True)
@@ -47,6 +49,14 @@ def run_workload(gpu_lib, name, per_vertex=True, per_edge=True, live_samples=8):
         print(f"{name}: total={tot} wedges={wed}", flush=True)
         assert tot == rec["total"]
         assert wed == rec["vp_wedges"]
+        if sorted_count:
+            # Algorithm 6's pair sort over the wedges of Algorithm 2 and of
+            # Algorithm 3: same total, |W| pairs in both (Lemma 3), in many
+            # memory-bounded chunks
+            for d in (0, 1):
+                st, pairs, chunks = h.count_total_sorted(direction=d)
+                print(f"{name}: sorted direction {d}: total={st} pairs={pairs} chunks={chunks}", flush=True)
+                assert st == rec["total"] and pairs == rec["vp_wedges"] and chunks > 2
         if per_vertex:
             up, lo = h.count_per_vertex()
             torch.cuda.synchronize()
@@ -85,4 +95,4 @@ def test_chunglu_1m_500k_20m(gpu_lib):
 
 
 def test_chunglu_16m_4m_200m_planted(gpu_lib):
-    run_workload(gpu_lib, "chunglu-16m-4m-200m-planted", live_samples=4)
+    run_workload(gpu_lib, "chunglu-16m-4m-200m-planted", live_samples=4, sorted_count=True)
