@@ -479,6 +479,8 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
   BFC_HIP(hipMemcpyAsync(st, status.p, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   BFC_HIP(hipStreamSynchronize(s));
   if (st[0]) throw Error{BFC_ERR_VERTEX_OUT_OF_RANGE, "an edge has an upper id outside [0,n_upper) or a lower id outside [0,n_lower)"};
+  g->max_deg[0] = st[4];
+  g->max_deg[1] = st[5];
 
   // ---- priorities: stable sort of each layer's ids by degree
   TmpBuf rank_of[2], deg_rank[2];

@@ -48,6 +48,7 @@ struct CountParams {
   unsigned long long* total;
   unsigned long long* vout[2];
   unsigned long long* acc[2];
+  uint32_t* acc32[2];          // per-edge: 32-bit accumulators when every B_e fits (else null)
   int32_t* cursor;
   int64_t cursor_stride;
   unsigned int* ticket;
@@ -84,6 +85,14 @@ __device__ __forceinline__ SideView pick(const CountParams& p, int x) {
 }
 
 __device__ __forceinline__ unsigned long long* pick_ptr(unsigned long long* const* a, int x) { return x ? a[1] : a[0]; }
+
+// Adds d to per-arc accumulator i of side x.  Every partial sum is at most
+// its edge's B_e <= (d_u - 1)(d_v - 1), so while the largest degrees keep
+// that below 2^32 the accumulators are 32-bit words: half the atomic traffic.
+__device__ __forceinline__ void acc_add(const CountParams& p, int x, int64_t i, unsigned long long d) {
+  if (p.acc32[0]) atomicAdd(&(x ? p.acc32[1] : p.acc32[0])[i], (uint32_t)d);
+  else atomicAdd(&(x ? p.acc[1] : p.acc[0])[i], d);
+}
 
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x *= 0x9E3779B1u;
@@ -375,8 +384,6 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
       // second pass: every wedge (r, v, w) adds count_w - 1 to the middle v
       // (Lemma 1) and, per edge, to the arcs (r, v) and (v, w) (Algorithm 4)
       unsigned long long* vmid = pick_ptr(p.vout, 1 - x);
-      unsigned long long* acc_s = pick_ptr(p.acc, x);
-      unsigned long long* acc_o = pick_ptr(p.acc, 1 - x);
       for (int32_t j0 = 0; j0 < pre; j0 += 64) {
         const int32_t j = j0 + lane;
         int32_t cs = 0, len = 0, v = 0;
@@ -390,14 +397,14 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
           const int32_t c = kPacked ? wave_packed_get(ptab, mask, w) : hash_get(keys, cnt, mask, w);
           if (c > 1) {
             const unsigned long long d = (unsigned long long)(c - 1);
-            if (kMode == kEdge) atomicAdd(&acc_o[slot], d);
+            if (kMode == kEdge) acc_add(p, 1 - x, slot, d);
             atomicAdd(&dsum[mid], d);
           }
         });
         __builtin_amdgcn_wave_barrier();
         const unsigned long long d = dsum[lane];
         if (d) {
-          if (kMode == kEdge) atomicAdd(&acc_s[base + j], d);
+          if (kMode == kEdge) acc_add(p, x, base + j, d);
           else atomicAdd(&vmid[O.id_of[v]], d);
           dsum[lane] = 0;
         }
@@ -1197,8 +1204,6 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
       // ---- pass 2 (per-vertex / per-edge): count - 1 to both edges of every
       // wedge; also advances the cursors past this window
       if (mode != kTotal) {
-        unsigned long long* acc_s = pick_ptr(p.acc, x);
-        unsigned long long* acc_o = pick_ptr(p.acc, 1 - x);
         unsigned long long* vmid = pick_ptr(p.vout, 1 - x);
         int32_t* se = segbuf;
         int32_t* sd = segbuf + kS2 + 1;
@@ -1230,7 +1235,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
                                            : hash_get(table, table + cap, cap - 1, w));
                      if (c > 1) {
                        const unsigned long long d = (unsigned long long)(c - 1);
-                       if (mode == kEdge) atomicAdd(&acc_o[slot], d);
+                       if (mode == kEdge) acc_add(p, 1 - x, slot, d);
                        if (sg != cur) {
                          if (run) atomicAdd(&sdel[cur], run);
                          cur = sg;
@@ -1246,7 +1251,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
             const unsigned long long d = sdel[i];
             if (d) {
               const int32_t k = base + sj[i];
-              if (mode == kEdge) atomicAdd(&acc_s[k], d);
+              if (mode == kEdge) acc_add(p, x, k, d);
               else atomicAdd(&vmid[O.id_of[S.adj[k]]], d);
             }
           }
@@ -1421,6 +1426,13 @@ __global__ void fold_edges_kernel(const int32_t* __restrict__ edge0, const int32
     out[edge0[k]] = acc0[k] + acc1[rev0[k]];
 }
 
+__global__ void fold_edges32_kernel(const int32_t* __restrict__ edge0, const int32_t* __restrict__ rev0,
+                                    const uint32_t* __restrict__ acc0, const uint32_t* __restrict__ acc1, int64_t m,
+                                    unsigned long long* __restrict__ out) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
+    out[edge0[k]] = (unsigned long long)acc0[k] + acc1[rev0[k]];
+}
+
 int num_cus() {
   int dev = 0;
   BFC_HIP(hipGetDevice(&dev));
@@ -1537,9 +1549,15 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   } else if (mode == kEdge) {
     const size_t need = sizeof(int64_t) * 2 * (size_t)(g->m > 0 ? g->m : 1);
     if (g->acc.bytes < need) g->acc.alloc(need, s);
-    zero_u64(g->acc.p, 2 * g->m, s);
-    p.acc[0] = g->acc.as<unsigned long long>();
-    p.acc[1] = g->acc.as<unsigned long long>() + g->m;
+    if (g->edge_acc32()) {
+      zero_u64(g->acc.p, g->m, s);  // 2m 32-bit words
+      p.acc32[0] = g->acc.as<uint32_t>();
+      p.acc32[1] = g->acc.as<uint32_t>() + g->m;
+    } else {
+      zero_u64(g->acc.p, 2 * g->m, s);
+      p.acc[0] = g->acc.as<unsigned long long>();
+      p.acc[1] = g->acc.as<unsigned long long>() + g->m;
+    }
   }
   const DenseBlock& d = g->dense;
   p.dtop[0] = g->side[0].n - d.KU;
@@ -1625,9 +1643,14 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   if (mode == kEdge && g->m > 0) {
     int64_t grid = (g->m + 255) / 256;
     if (grid > 65536) grid = 65536;
-    fold_edges_kernel<<<(unsigned)grid, 256, 0, s>>>(g->edge0.as<int32_t>(), g->side[0].rev.as<int32_t>(),
-                                                     p.acc[0], p.acc[1], g->m,
-                                                     reinterpret_cast<unsigned long long*>(out0));
+    if (p.acc32[0])
+      fold_edges32_kernel<<<(unsigned)grid, 256, 0, s>>>(g->edge0.as<int32_t>(), g->side[0].rev.as<int32_t>(),
+                                                         p.acc32[0], p.acc32[1], g->m,
+                                                         reinterpret_cast<unsigned long long*>(out0));
+    else
+      fold_edges_kernel<<<(unsigned)grid, 256, 0, s>>>(g->edge0.as<int32_t>(), g->side[0].rev.as<int32_t>(),
+                                                       p.acc[0], p.acc[1], g->m,
+                                                       reinterpret_cast<unsigned long long*>(out0));
     BFC_LAUNCH_CHECK();
   }
   if (g->timing) {

@@ -188,6 +188,14 @@ struct bfc_graph_s {
   bool light_packed = false;
   int32_t light_max_cap() const { return light_packed ? 2048 : 1024; }
   int64_t rows_max[2] = {0, 0};  // window-table rows allocated per layer
+  int32_t max_deg[2] = {0, 0};   // largest degree per layer
+  // per-edge counts accumulate in 32-bit words while every B_e fits:
+  // B_e <= (d_u - 1)(d_v - 1) <= (max_deg[0] - 1)(max_deg[1] - 1) < 2^32
+  bool edge_acc32() const {
+    const uint64_t a = max_deg[0] > 1 ? (uint64_t)(max_deg[0] - 1) : 0;
+    const uint64_t b = max_deg[1] > 1 ? (uint64_t)(max_deg[1] - 1) : 0;
+    return a * b < (uint64_t(1) << 32);
+  }
   std::vector<int64_t> graph_wedges;
   // captured total count
   hipGraph_t cap_graph = nullptr;

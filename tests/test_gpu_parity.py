@@ -201,3 +201,21 @@ def test_input_errors(gpu_lib):
     # the library stays usable after errors
     tot, *_ = gpu_all(gpu_lib, gg.complete_bipartite(4, 4))
     assert tot == 36
+
+
+def test_per_edge_wide_accumulators(gpu_lib):
+    """Two hubs of degree 70,000 in opposite layers: (d_u - 1)(d_v - 1) can
+    reach 2^32, so per-edge counts use 64-bit accumulators (every other graph
+    here fits the 32-bit ones)."""
+    rng = np.random.default_rng(123)
+    pairs = {(0, v) for v in range(70_000)} | {(u, 0) for u in range(70_000)}
+    for u in range(1, 300):
+        for v in rng.choice(np.arange(1, 300), 15, replace=False):
+            pairs.add((u, int(v)))
+    e = np.array(sorted(pairs), np.int32)
+    e = e[rng.permutation(len(e))]
+    g = gg.Graph(np.ascontiguousarray(e), 70_000, 70_000, "two-hubs")
+    du = np.bincount(e[:, 0], minlength=g.n_upper)
+    dl = np.bincount(e[:, 1], minlength=g.n_lower)
+    assert (int(du.max()) - 1) * (int(dl.max()) - 1) >= 1 << 32
+    check_against_oracle(gpu_lib, g)
