@@ -37,9 +37,9 @@ DEFAULT_WORKLOAD = "chunglu-1m-500k-20m"
 # hash to the value they were measured with (any change voids the figure).
 HEAVY_TRAFFIC = {
     "workload": DEFAULT_WORKLOAD,
-    "sources_sha256": "faf2e798b838f9d56d16b787094a3e0b21016d4cb4aa90a03d8573d57754fc41",
-    "fetch_kib": 17201684.2,
-    "write_kib": 887527.3,
+    "sources_sha256": "fc69c66c19a324f836b2e67c3bbe0c61ceb06ada1107234b104bf20b142aa281",
+    "fetch_kib": 17073321.6,
+    "write_kib": 887864.0,
     "fetch_factor": 2.0,
     "write_factor": 1.0,
 }
@@ -408,6 +408,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--steps-only", action="store_true",
+                    help="time the steps only: no per-vertex / per-edge counts and no copy measurement afterwards "
+                         "(for profiler runs whose kernels should all be steps)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (calibrates HBM counters)")
     ap.add_argument("--tuning", default="", help='JSON dict of bfc_set_tuning fields, e.g. {"window_mode": 3}')
@@ -503,6 +506,29 @@ def main() -> int:
 
     ms_step = 1000.0 * elapsed / args.steps
     wedges = wed0
+
+    # per-vertex and per-edge counts (Lemma 1, Algorithm 4) on one more
+    # handle, after the timed steps: median of three calls each
+    def timed_calls(fn, n=3):
+        ts = []
+        for _ in range(n):
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - tb)
+        return 1000.0 * float(np.median(ts))
+
+    vertex_ms = edge_ms = None
+    if not args.steps_only:
+        with bfc.Graph(edges, g.n_upper, g.n_lower, stream) as h:
+            if tuning:
+                h.set_tuning(**tuning)
+            vertex_ms = timed_calls(lambda: h.count_per_vertex(stream))
+            edge_ms = timed_calls(lambda: h.count_per_edge(stream))
+    # algorithmic bytes of a whole total count (4 per wedge, 16 per arc, 8 per
+    # vertex) twice (two walks) plus 40 per edge (accumulators and output)
+    per_edge_bytes = 2 * (4 * wedges + 16 * g.m + 8 * (g.n_upper + g.n_lower)) + 40 * g.m
     hk_ms = float(np.mean(heavy_ms))
     hk_bytes = heavy_kernel_bytes(si)
     achieved = hk_bytes / (hk_ms / 1000.0) / 1e9 if hk_ms > 0 else 0.0
@@ -538,6 +564,11 @@ def main() -> int:
         "count_ms": count_ms,
         "build_ms": ms_step - count_ms,
         "count_only_wedges_per_s": wedges / (count_ms / 1000.0),
+        "per_vertex_count_ms": vertex_ms,
+        "per_edge_count_ms": edge_ms,
+        "per_edge_roofline": None if edge_ms is None else {
+            "algorithmic_bytes": per_edge_bytes, "achieved_GBps": per_edge_bytes / edge_ms / 1e6,
+            "frac": per_edge_bytes / edge_ms / 1e6 / HBM_PEAK_GBS},
         "edges_per_s": g.m / (ms_step / 1000.0),
         "kernels_ms": {"heavy": hk_ms, "light": float(np.mean(light_ms))},
         "schedule": si,
@@ -552,7 +583,7 @@ def main() -> int:
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": hk_bytes,
             "avg_launch_ms": hk_ms,
-            "copy_measured": measured_copy_gbs(),
+            "copy_measured": None if args.steps_only else measured_copy_gbs(),
             "copy_measured_unit": "GB/s, best device-to-device copy of 4 GiB (read + write bytes), after the timed steps",
         },
     }
