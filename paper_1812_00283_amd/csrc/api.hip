@@ -96,13 +96,17 @@ struct CountSection {
 
 namespace bfc {
 
-bfc_graph_s* new_graph(const int32_t* edges_dev, int64_t m, int32_t n_upper, int32_t n_lower, hipStream_t s) {
+void check_graph_args(const int32_t* edges_dev, int64_t m, int32_t n_upper, int32_t n_lower) {
   if (m < 0 || n_upper < 0 || n_lower < 0) throw Error{BFC_ERR_INVALID_ARGUMENT, "negative size"};
   if (m > 0 && !edges_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "edges_dev is null"};
   if (m >= (int64_t(1) << 30) || n_upper >= (1 << 30) || n_lower >= (1 << 30))
     throw Error{BFC_ERR_TOO_LARGE, "m and each layer size must be below 2^30"};
   if (m > (int64_t)n_upper * (int64_t)n_lower)
     throw Error{BFC_ERR_DUPLICATE_EDGE, "more edges than (upper, lower) pairs: some pair repeats"};
+}
+
+bfc_graph_s* new_graph(const int32_t* edges_dev, int64_t m, int32_t n_upper, int32_t n_lower, hipStream_t s) {
+  check_graph_args(edges_dev, m, n_upper, n_lower);
   bfc_graph_s* g = new bfc_graph_s();
   try {
     BFC_HIP(hipGetDevice(&g->device));
@@ -372,6 +376,7 @@ bfc_status bfc_k_wing(const int32_t* edges_dev, int64_t m, int32_t n_upper, int3
                       void* stream, uint8_t* in_wing_dev, int64_t* counts_dev, int64_t* wing_edges_host,
                       int32_t* rounds_host) {
   return guard([&] {
+    check_graph_args(edges_dev, m, n_upper, n_lower);  // before any device work
     if (m > 0 && !in_wing_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "in_wing_dev is null"};
     int64_t w = 0;
     int32_t r = 0;

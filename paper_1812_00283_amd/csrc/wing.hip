@@ -81,6 +81,7 @@ void k_wing(const int32_t* edges, int64_t m, int32_t n_upper, int32_t n_lower, i
             uint8_t* in_wing, int64_t* counts, int64_t* wing_edges, int32_t* rounds) {
   *wing_edges = 0;
   *rounds = 0;
+  check_graph_args(edges, m, n_upper, n_lower);
   if (m > 0) {
     wing_clear_kernel<<<grid_of(m), 256, 0, s>>>(in_wing, counts, m);
     BFC_LAUNCH_CHECK();

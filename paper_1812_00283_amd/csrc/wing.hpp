@@ -5,6 +5,9 @@
 
 namespace bfc {
 
+// bfc_build's argument checks (sizes, null edges, more edges than pairs);
+// throws Error.  They touch no device state.
+void check_graph_args(const int32_t* edges, int64_t m, int32_t n_upper, int32_t n_lower);
 // A graph handle built from device edges with bfc_build's checks and steps
 // (throws Error: invalid argument, id out of range, duplicate edge, ...).
 bfc_graph_s* new_graph(const int32_t* edges, int64_t m, int32_t n_upper, int32_t n_lower, hipStream_t s);

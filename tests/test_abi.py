@@ -73,3 +73,13 @@ def test_argument_errors_need_no_device(lib):
     assert b"pairs" in lib.bfc_last_error()
     tun = bfc.Tuning()
     assert lib.bfc_set_tuning(None, ctypes.byref(tun)) == 1
+    # the later entry points check their arguments before any device work
+    c = ctypes.c_int64()
+    d = ctypes.c_double()
+    assert lib.bfc_caterpillars(None, ctypes.byref(c)) == 1
+    assert lib.bfc_clustering_coefficient(None, None, ctypes.byref(d)) == 1
+    assert lib.bfc_count_total_sorted(None, None, 0, 0, ctypes.byref(t), None, None) == 1
+    w, r = ctypes.c_int64(), ctypes.c_int32()
+    assert lib.bfc_k_wing(vp(8), 10, 5, 5, 1, None, None, None, ctypes.byref(w), ctypes.byref(r)) == 1  # null mask
+    assert lib.bfc_k_wing(vp(8), 1 << 30, 1 << 20, 1 << 20, 1, None, vp(8), None, ctypes.byref(w), ctypes.byref(r)) == 4
+    assert lib.bfc_k_wing(vp(8), 26, 5, 5, 1, None, vp(8), None, ctypes.byref(w), ctypes.byref(r)) == 3
