@@ -65,7 +65,8 @@ int64_t bfc_graph_s::device_bytes() const {
     const bfc::Side& s = side[x];
     b += s.off.bytes + s.adj.bytes + s.rev.bytes + s.lo.bytes + s.id_of.bytes + s.work.bytes;
   }
-  b += edge0.bytes + wt[0].bytes + wt[1].bytes + sched.light.bytes + sched.heavy.bytes + scratch.bytes + acc.bytes;
+  b += edge0.bytes + wt[0].bytes + wt[1].bytes + sched.light.bytes + sched.heavy.bytes + scratch.bytes + acc.bytes +
+       vacc.bytes;
   return b;
 }
 
@@ -152,8 +153,8 @@ int64_t bfc_estimate_device_bytes(int64_t m, int32_t n_upper, int32_t n_lower) {
   const int64_t resident = m * 4 * 5 + m * 4 + n * (4 + 4 + 4 + 8) + 2 * 4 * (int64_t)2 + 4096;
   // build peak: resident + sort buffers (2 x (8 + 4) bytes per edge) + slots
   const int64_t build_peak = resident + m * (24 + 8) + n * 16;
-  // per-edge counting: 2 int64 accumulators per edge
-  const int64_t edge_peak = resident + m * 16;
+  // per-edge and per-vertex counting: 2 accumulators per edge, 1 per vertex
+  const int64_t edge_peak = resident + m * 16 + n * 8;
   return build_peak > edge_peak ? build_peak : edge_peak;
 }
 
@@ -317,8 +318,6 @@ bfc_status bfc_count_per_vertex(bfc_graph g, void* stream, int64_t* upper_dev, i
     DeviceScope ds(h->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     CountSection cs(h, s);
-    zero_i64(upper_dev, h->n_upper, s);
-    zero_i64(lower_dev, h->n_lower, s);
     count(h, kVertex, nullptr, upper_dev, lower_dev, s);
     cs.finish();
   });

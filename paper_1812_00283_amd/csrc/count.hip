@@ -46,7 +46,7 @@ struct CountParams {
   int32_t n_list;
   int32_t mode;
   unsigned long long* total;
-  unsigned long long* vout[2];
+  unsigned long long* vout[2];  // per-vertex: accumulators by rank, per layer
   unsigned long long* acc[2];
   uint32_t* acc32[2];          // per-edge: 32-bit accumulators when every B_e fits (else null)
   int32_t* cursor;
@@ -376,10 +376,10 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
           const uint32_t word = ptab[h];
           const int32_t c = kPacked ? (int32_t)(word & kLightCountMask) : cnt[h];
           const int32_t key = kPacked ? (int32_t)(word >> kLightCountBits) : keys[h];
-          if (c > 1) atomicAdd(&vs[S.id_of[key - 1]], choose2(c));
+          if (c > 1) atomicAdd(&vs[key - 1], choose2(c));
         }
         a = wave_sum(a);
-        if (lane == 0 && a) atomicAdd(&vs[S.id_of[r]], a);
+        if (lane == 0 && a) atomicAdd(&vs[r], a);
       }
       // second pass: every wedge (r, v, w) adds count_w - 1 to the middle v
       // (Lemma 1) and, per edge, to the arcs (r, v) and (v, w) (Algorithm 4)
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
         const unsigned long long d = dsum[lane];
         if (d) {
           if (kMode == kEdge) acc_add(p, x, base + j, d);
-          else atomicAdd(&vmid[O.id_of[v]], d);
+          else atomicAdd(&vmid[v], d);
           dsum[lane] = 0;
         }
         __builtin_amdgcn_wave_barrier();
@@ -1252,7 +1252,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
             if (d) {
               const int32_t k = base + sj[i];
               if (mode == kEdge) acc_add(p, x, k, d);
-              else atomicAdd(&vmid[O.id_of[S.adj[k]]], d);
+              else atomicAdd(&vmid[S.adj[k]], d);
             }
           }
           __syncthreads();
@@ -1328,17 +1328,17 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
               if (c0 > 1) {
                 const unsigned long long cc = choose2(c0);
                 start_acc += cc;
-                if (mode == kVertex) atomicAdd(&vs[S.id_of[lo_w + 2 * i]], cc);
+                if (mode == kVertex) atomicAdd(&vs[lo_w + 2 * i], cc);
               }
               if (c1 > 1) {
                 const unsigned long long cc = choose2(c1);
                 start_acc += cc;
-                if (mode == kVertex) atomicAdd(&vs[S.id_of[lo_w + 2 * i + 1]], cc);
+                if (mode == kVertex) atomicAdd(&vs[lo_w + 2 * i + 1], cc);
               }
             } else if ((int32_t)word > 1) {
               const unsigned long long cc = choose2((int32_t)word);
               start_acc += cc;
-              if (mode == kVertex) atomicAdd(&vs[S.id_of[lo_w + i]], cc);
+              if (mode == kVertex) atomicAdd(&vs[lo_w + i], cc);
             }
           }
           t4[i4] = make_uint4(0u, 0u, 0u, 0u);
@@ -1368,7 +1368,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
             if (c > 1) {
               const unsigned long long cc = choose2(c);
               start_acc += cc;
-              if (mode == kVertex) atomicAdd(&vs[S.id_of[lo_w - 1 + (int32_t)(word >> kPackBits)]], cc);
+              if (mode == kVertex) atomicAdd(&vs[lo_w - 1 + (int32_t)(word >> kPackBits)], cc);
             }
             pt[h] = 0u;
           }
@@ -1381,7 +1381,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
             if (c > 1) {
               const unsigned long long cc = choose2(c);
               start_acc += cc;
-              if (mode == kVertex) atomicAdd(&vs[S.id_of[key - 1]], cc);
+              if (mode == kVertex) atomicAdd(&vs[key - 1], cc);
             }
             table[h] = 0;
             table[cap + h] = 0;
@@ -1401,7 +1401,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     }
     if (mode == kVertex) {
       const unsigned long long sa = block_sum<unsigned long long, kNT>(start_acc, s_red64);
-      if (t == 0 && sa) atomicAdd(&pick_ptr(p.vout, x)[S.id_of[r]], sa);
+      if (t == 0 && sa) atomicAdd(&pick_ptr(p.vout, x)[r], sa);
     } else if (mode == kTotal && p.gtotal) {
       const unsigned long long sa = block_sum<unsigned long long, kNT>(start_acc, s_red64);
       if (t == 0 && sa) atomicAdd(&p.gtotal[graph_index(p, x, r)], sa);
@@ -1424,6 +1424,14 @@ __global__ void fold_edges_kernel(const int32_t* __restrict__ edge0, const int32
                                   unsigned long long* __restrict__ out) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
     out[edge0[k]] = acc0[k] + acc1[rev0[k]];
+}
+
+// B_x of every vertex of one layer, from its rank-indexed accumulator to its
+// input id.
+__global__ void vertex_out_kernel(const unsigned long long* __restrict__ by_rank, const int32_t* __restrict__ id_of,
+                                  int32_t n, unsigned long long* __restrict__ out) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    out[id_of[r]] = by_rank[r];
 }
 
 __global__ void fold_edges32_kernel(const int32_t* __restrict__ edge0, const int32_t* __restrict__ rev0,
@@ -1544,8 +1552,15 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     p.gid[1] = g->gid[1].as<int32_t>();
   }
   if (mode == kVertex) {
-    p.vout[0] = reinterpret_cast<unsigned long long*>(out0);
-    p.vout[1] = reinterpret_cast<unsigned long long*>(out1);
+    // accumulate by rank (an end's counter and its accumulator share an
+    // index, so neighbouring counters add to neighbouring words), then
+    // write each vertex's sum to its input id
+    const int64_t nv = (int64_t)g->side[0].n + g->side[1].n;
+    const size_t need = sizeof(int64_t) * (size_t)(nv > 0 ? nv : 1);
+    if (g->vacc.bytes < need) g->vacc.alloc(need, s);
+    zero_u64(g->vacc.p, nv, s);
+    p.vout[0] = g->vacc.as<unsigned long long>();
+    p.vout[1] = g->vacc.as<unsigned long long>() + g->side[0].n;
   } else if (mode == kEdge) {
     const size_t need = sizeof(int64_t) * 2 * (size_t)(g->m > 0 ? g->m : 1);
     if (g->acc.bytes < need) g->acc.alloc(need, s);
@@ -1640,6 +1655,16 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     BFC_LAUNCH_CHECK();
   }
   if (g->timing) BFC_HIP(hipEventRecord(tc.ev[3], s));
+  if (mode == kVertex) {
+    for (int x = 0; x < 2; ++x) {
+      const int32_t n = g->side[x].n;
+      if (n == 0) continue;
+      const int64_t grid = (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
+      vertex_out_kernel<<<(unsigned)grid, 256, 0, s>>>(p.vout[x], g->side[x].id_of.as<int32_t>(), n,
+                                                       reinterpret_cast<unsigned long long*>(x ? out1 : out0));
+      BFC_LAUNCH_CHECK();
+    }
+  }
   if (mode == kEdge && g->m > 0) {
     int64_t grid = (g->m + 255) / 256;
     if (grid > 65536) grid = 65536;

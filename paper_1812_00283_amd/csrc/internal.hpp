@@ -206,6 +206,7 @@ struct bfc_graph_s {
   bfc::DevBuf scratch;    // per-workgroup cursors and the work ticket of the count kernels
   size_t scratch_bytes = 0;
   bfc::DevBuf acc;        // int64 [2m] per-arc accumulators of the per-edge count (allocated on first use)
+  bfc::DevBuf vacc;       // int64 [n_upper + n_lower] per-rank accumulators of the per-vertex count
   int device = 0;
   // count calls share scratch: they are serialised on the device with `done`
   std::mutex mu;
@@ -256,9 +257,9 @@ void build_schedule(bfc_graph_s* g, hipStream_t s);
 void finish_schedule(bfc_graph_s* g, hipStream_t s);
 
 enum CountMode { kTotal = 0, kVertex = 1, kEdge = 2 };
-// Runs the wedge kernels.  kTotal: adds B_G into total_dev.  kVertex: adds
-// per-vertex counts into out0 (upper, by id) and out1 (lower, by id), which
-// must be zeroed.  kEdge: writes per-edge counts into out0 (int64 [m]).
+// Runs the wedge kernels.  kTotal: adds B_G into total_dev.  kVertex: writes
+// per-vertex counts into out0 (upper, by id) and out1 (lower, by id).
+// kEdge: writes per-edge counts into out0 (int64 [m]).
 // gtotals (kTotal only): per-graph totals [n_graphs] instead of total_dev.
 void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, int64_t* out1, hipStream_t s,
            int64_t* gtotals = nullptr);
