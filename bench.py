@@ -37,9 +37,9 @@ DEFAULT_WORKLOAD = "chunglu-1m-500k-20m"
 # hash to the value they were measured with (any change voids the figure).
 HEAVY_TRAFFIC = {
     "workload": DEFAULT_WORKLOAD,
-    "sources_sha256": "fc69c66c19a324f836b2e67c3bbe0c61ceb06ada1107234b104bf20b142aa281",
-    "fetch_kib": 17073321.6,
-    "write_kib": 887864.0,
+    "sources_sha256": "ee2bc77abb89dff7504f7fd41b40b41508f3b5a72a09a2acf2c77b8dc76cc3e9",
+    "fetch_kib": 17075036.9,
+    "write_kib": 885903.2,
     "fetch_factor": 2.0,
     "write_factor": 1.0,
 }
