@@ -120,7 +120,7 @@ bfc_status bfc_caterpillars(bfc_graph g, int64_t* caterpillars_host);
 bfc_status bfc_clustering_coefficient(bfc_graph g, void* stream, double* coefficient_host);
 
 /*
- * B_G by sorting vertex pairs (Section 7, Algorithm 6, with device memory in
+ * B_G by sorting vertex pairs (Section 6.3, Algorithm 6, with device memory in
  * the place of disk): every processed wedge gives the pair (end, start);
  * equal pairs are brought together by a radix sort and every run of c equal
  * pairs adds C(c, 2) (Lemma 1).

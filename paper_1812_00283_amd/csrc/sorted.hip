@@ -1,4 +1,4 @@
-// Sort-based total count: the external-memory algorithm of Section 7
+// Sort-based total count: the external-memory algorithm of Section 6.3
 // (Algorithm 6) with HBM in the place of disk.
 //
 // Algorithm 6 emits, for every wedge (u, v, w) whose end w has the highest
