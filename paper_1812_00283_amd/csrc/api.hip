@@ -148,9 +148,10 @@ const char* bfc_version(void) { return "bfc-mi355x 0.1 (gfx950)"; }
 int64_t bfc_estimate_device_bytes(int64_t m, int32_t n_upper, int32_t n_lower) {
   if (m < 0 || n_upper < 0 || n_lower < 0) return 0;
   const int64_t n = (int64_t)n_upper + n_lower;
-  // resident: 2 sides x (adj + rev) + edge0 + per-vertex arrays + window
-  // tables (at most 2 bytes per edge each)
-  const int64_t resident = m * 4 * 5 + m * 4 + n * (4 + 4 + 4 + 8) + 2 * 4 * (int64_t)2 + 4096;
+  // resident: 2 sides x (adj + rev) + edge0 + per-vertex arrays and the two
+  // start lists (16 bytes per vertex each) + window tables (at most 2 bytes
+  // per edge each)
+  const int64_t resident = m * 4 * 5 + m * 4 + n * (4 + 4 + 4 + 8 + 32) + 2 * 4 * (int64_t)2 + 4096;
   // build peak: resident + sort buffers (2 x (8 + 4) bytes per edge) + slots
   const int64_t build_peak = resident + m * (24 + 8) + n * 16;
   // per-edge and per-vertex counting: 2 accumulators per edge, 1 per vertex

@@ -812,8 +812,9 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   }
   exclusive_scan_i64(flags_l.as<int64_t>(), pos_l.as<int64_t>(), n, pos_l.as<int64_t>() + n, s);
   exclusive_scan_i64(flags_h.as<int64_t>(), pos_h.as<int64_t>(), n, pos_h.as<int64_t>() + n, s);
-  // the list sizes are known once the build is read back: size the lists
-  // for every start (finish_schedule trims them)
+  // the list sizes are known only once the build is read back: each list
+  // holds every start (32 bytes per vertex for both; shrinking them would
+  // take a copy and a wait at the end of every build)
   sc.light.alloc(sizeof(int4) * (size_t)n, s);
   sc.heavy.alloc(sizeof(int4) * (size_t)n, s);
   TmpBuf hkey, hkey_tmp, hval_tmp, hcode;
@@ -845,15 +846,6 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
 
 namespace {
 // Replaces b's block by a copy of its first `bytes` bytes (stream-ordered).
-void trim(DevBuf& b, size_t bytes, hipStream_t s) {
-  if (bytes == 0) bytes = 256;
-  if (bytes >= b.bytes) return;
-  void* p = cache_alloc(bytes, s);
-  BFC_HIP(hipMemcpyAsync(p, b.p, bytes, hipMemcpyDeviceToDevice, s));
-  cache_free(b.p, s);
-  b.p = p;
-  b.bytes = bytes;
-}
 }  // namespace
 
 void finish_schedule(bfc_graph_s* g, hipStream_t s) {
@@ -890,8 +882,6 @@ void finish_schedule(bfc_graph_s* g, hipStream_t s) {
   int64_t cat = 0;
   for (int i = 0; i < kCatSlots; ++i) cat += cat_slots[i];
   g->caterpillars = cat;
-  trim(sc.light, sizeof(int4) * (size_t)sc.n_light, s);
-  trim(sc.heavy, sizeof(int4) * (size_t)sc.n_heavy, s);
 }
 
 // ---------------------------------------------------------------- batches
