@@ -172,6 +172,12 @@ def cpu_baseline(g, wedges: int, target_s: float = 15.0) -> dict:
         k = k2
     share = float(csum[k - 1]) / total_cost
     est_full = ts / share
+    # the same walk on one thread, over a slice of about 3 s of one thread's work
+    k1 = min(n_side, int(np.searchsorted(csum, rate / threads * 3.0)) + 1)
+    t = time.perf_counter()
+    oracle.vertex_counts_subset(g, side, order[:k1], 1)
+    t1 = time.perf_counter() - t
+    share1 = float(csum[k1 - 1]) / total_cost
     return {
         "value": wedges / est_full,
         "unit": "wedges/s",
@@ -179,6 +185,8 @@ def cpu_baseline(g, wedges: int, target_s: float = 15.0) -> dict:
         "cpu_model": cpu_model(),
         "host_cpus": os.cpu_count(),
         "oracle_counter_steps": total_cost,
+        "single_thread": {"value": wedges / (t1 / share1), "unit": "wedges/s",
+                          "sample": f"{k1} starts, {100 * share1:.2f}% of the counter steps, in {t1:.1f} s"},
         "kind": "oracle",
         "sample": (f"Eq. 1 walk from {k} of {n_side} {'upper' if side == 0 else 'lower'} starts "
                    f"(random, {100 * share:.1f}% of the oracle's {total_cost:.3g} counter steps) in {ts:.1f} s; "
@@ -564,6 +572,11 @@ def main() -> int:
         "count_ms": count_ms,
         "build_ms": ms_step - count_ms,
         "count_only_wedges_per_s": wedges / (count_ms / 1000.0),
+        "count_phase_roofline": {
+            "algorithmic_bytes": 4 * wedges + 16 * g.m + 8 * (g.n_upper + g.n_lower),
+            "achieved_GBps": (4 * wedges + 16 * g.m + 8 * (g.n_upper + g.n_lower)) / count_ms / 1e6,
+            "frac": (4 * wedges + 16 * g.m + 8 * (g.n_upper + g.n_lower)) / count_ms / 1e6 / HBM_PEAK_GBS,
+            "note": "whole count phase (light + heavy kernels), 4|W| + 16m + 8n over bfc_count_total's time"},
         "per_vertex_count_ms": vertex_ms,
         "per_edge_count_ms": edge_ms,
         "per_edge_roofline": None if edge_ms is None else {
