@@ -78,6 +78,32 @@ def test_single_queries_equal_brute_force():
                 assert s.edge(u, v) == be[i]
 
 
+def test_vertex_subset_equals_brute_force():
+    """Eq. 1 for a listed subset of one layer (the walk the CPU baseline
+    times): every listed vertex, in any order, repeated or not, gets the
+    brute-force B_x of Def. 2, and an out-of-range id is refused."""
+    rng = np.random.default_rng(4242)
+    for g in tiny_graphs(120, seed0=9100):
+        _, bu, bl, _ = brute(g)
+        for side, ref in ((0, bu), (1, bl)):
+            n = len(ref)
+            k = int(rng.integers(1, 2 * n + 1))
+            xs = rng.integers(0, n, size=k)  # with repeats, unsorted
+            np.testing.assert_array_equal(oracle.vertex_counts_subset(g, side, xs, 1), ref[xs])
+            np.testing.assert_array_equal(oracle.vertex_counts_subset(g, side, xs[::-1], 3), ref[xs[::-1]])
+            assert len(oracle.vertex_counts_subset(g, side, np.zeros(0, np.int64))) == 0
+            with pytest.raises(RuntimeError):
+                oracle.vertex_counts_subset(g, side, np.array([n]))
+
+
+@pytest.mark.parametrize("a,b", [(3, 7), (40, 25)])
+def test_vertex_subset_complete_bipartite(a, b):
+    g = gg.complete_bipartite(a, b)
+    c2 = lambda k: k * (k - 1) // 2
+    assert (oracle.vertex_counts_subset(g, 0, np.arange(a)[::-1]) == (a - 1) * c2(b)).all()
+    assert (oracle.vertex_counts_subset(g, 1, np.arange(b)) == (b - 1) * c2(a)).all()
+
+
 @pytest.mark.parametrize("a,b", [(1, 1), (1, 5), (2, 2), (2, 3), (3, 7), (6, 6), (13, 4), (40, 25)])
 def test_complete_bipartite_closed_form(a, b):
     g = gg.complete_bipartite(a, b)
