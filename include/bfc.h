@@ -90,7 +90,8 @@ bfc_status bfc_count_total_async(bfc_graph g, void* stream, int64_t* total_dev);
  * wedges adds c-1 to its middle.
  *   upper_dev  device int64 [n_upper], B_u by upper id (overwritten).
  *   lower_dev  device int64 [n_lower], B_v by lower id (overwritten).
- * Asynchronous on `stream`.
+ * Asynchronous on `stream`: an internal failure of its kernels is reported
+ * by the next call on the handle that waits (bfc_sync, bfc_count_total).
  */
 bfc_status bfc_count_per_vertex(bfc_graph g, void* stream, int64_t* upper_dev, int64_t* lower_dev);
 
@@ -98,9 +99,22 @@ bfc_status bfc_count_per_vertex(bfc_graph g, void* stream, int64_t* upper_dev, i
  * B_e for every edge (Eq. 8 evaluated as in Algorithm 4): a second walk over
  * the same wedges adds count - 1 to both of each wedge's edges.
  *   edge_dev  device int64 [m], B_e in the input order of bfc_build (overwritten).
- * Asynchronous on `stream`.
+ * Asynchronous on `stream`, reported like bfc_count_per_vertex.
  */
 bfc_status bfc_count_per_edge(bfc_graph g, void* stream, int64_t* edge_dev);
+
+/*
+ * Waits on `stream` (after the handle's previous count call, whatever its
+ * stream) until every count queued on the handle has finished, and reports
+ * whether any of them failed internally.  The count kernels flag a start
+ * whose end range could not be cut into windows that fit on chip (which the
+ * window halving rules out; the flag guards against a logic error): that
+ * start's wedges were skipped, so the outputs of that call are inexact.  The
+ * flag is sticky: from then on bfc_sync and bfc_count_total on the handle
+ * return BFC_ERR_DEVICE.  Not for use while `stream` is being captured
+ * (BFC_ERR_INVALID_ARGUMENT).
+ */
+bfc_status bfc_sync(bfc_graph g, void* stream);
 
 /*
  * Caterpillars C_G (Section 1): the three-paths of the graph, walks x-y-z-t
@@ -197,6 +211,9 @@ bfc_status bfc_batch_wedges(bfc_graph g, int64_t* wedges_host);
  * allocates nothing and records no memset nodes.  totals_dev must stay valid
  * while the capture is in use.  `stream` must be a created stream (the
  * default stream cannot be captured): BFC_ERR_INVALID_ARGUMENT otherwise.
+ * bfc_set_tuning discards the capture (its kernels hold the old schedule):
+ * bfc_graph_replay then returns BFC_ERR_INVALID_ARGUMENT until the next
+ * bfc_graph_capture_total.
  */
 bfc_status bfc_graph_capture_total(bfc_graph g, void* stream, int64_t* totals_dev);
 bfc_status bfc_graph_replay(bfc_graph g, void* stream);
@@ -215,6 +232,39 @@ int64_t bfc_estimate_device_bytes(int64_t m, int32_t n_upper, int32_t n_lower);
 
 /* Frees the handle and its device memory.  NULL is a no-op. */
 bfc_status bfc_destroy(bfc_graph g);
+
+/*
+ * Device memory.  The library takes its device buffers (graph arrays,
+ * schedules, scratch and temporaries) from an internal cache: a freed buffer
+ * is kept with the stream and an event of its last use and handed out again,
+ * so repeated builds and counts make no allocator calls once warm.  The
+ * cache gets new blocks from hipMalloc, or, after bfc_set_allocator, from
+ * the caller's functions (for example a framework's caching allocator, so
+ * the library's memory is counted in that framework's pool):
+ *   alloc_fn(bytes, stream, ctx)  returns `bytes` of device memory on the
+ *                 current device, usable by work queued on `stream` (a
+ *                 hipStream_t), or NULL when it has none;
+ *   free_fn(p, stream, ctx)       takes back a block alloc_fn returned; the
+ *                 library calls it only once all work using p has completed.
+ * Both NULL restores hipMalloc / hipFree; one NULL is BFC_ERR_INVALID_ARGUMENT.
+ * Process-wide.  Before switching, every idle cached block goes back to the
+ * allocator that made it; blocks still in use go back to theirs when freed.
+ * When an allocation fails the cache returns its idle blocks and retries once;
+ * if that fails too the call returns BFC_ERR_OUT_OF_MEMORY (a failed build
+ * leaves *out NULL and writes nothing).  Not to be called while other
+ * threads are inside library calls.
+ */
+typedef void* (*bfc_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*bfc_free_fn)(void* p, void* stream, void* ctx);
+bfc_status bfc_set_allocator(bfc_alloc_fn alloc_fn, bfc_free_fn free_fn, void* ctx);
+
+/* Returns every idle cached block to its allocator (blocks whose last use
+ * has not completed stay); returns the number of bytes released. */
+int64_t bfc_trim_cache(void);
+
+/* Bytes held in idle cached blocks (device memory the library holds beyond
+ * its live handles and calls in progress). */
+int64_t bfc_cached_bytes(void);
 
 /*
  * Tuning knobs for one handle.  None of them changes any count; they choose

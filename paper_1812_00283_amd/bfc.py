@@ -33,8 +33,13 @@ EXPORTS = [
     "bfc_last_error", "bfc_version", "bfc_get_schedule_info", "bfc_set_kernel_timing", "bfc_get_kernel_times",
     "bfc_build_batch", "bfc_count_total_batch", "bfc_batch_wedges", "bfc_graph_capture_total", "bfc_graph_replay",
     "bfc_graph_count", "bfc_caterpillars", "bfc_clustering_coefficient", "bfc_k_wing",
-    "bfc_count_total_sorted",
+    "bfc_count_total_sorted", "bfc_sync", "bfc_set_allocator", "bfc_trim_cache", "bfc_cached_bytes",
 ]
+
+# Signatures of the allocator functions bfc_set_allocator takes.
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_installed = None  # keeps the installed callbacks alive
 
 
 class BfcError(RuntimeError):
@@ -61,8 +66,10 @@ class KernelTimes(ctypes.Structure):
                 ("other_ms", ctypes.c_double)]
 
 
-def load(path: str | None = None):
-    """Loads libbfc.so; raises if it has not been built."""
+def load(path: str | None = None, torch_memory: bool = True):
+    """Loads libbfc.so; raises if it has not been built.  With torch_memory
+    (the default) the library takes its device memory from PyTorch's caching
+    allocator (``bfc_set_allocator``)."""
     global _lib
     if _lib is not None:
         return _lib
@@ -96,6 +103,10 @@ def load(path: str | None = None):
         "bfc_clustering_coefficient": ([vp, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "bfc_k_wing": ([vp, i64, i32, i32, i64, vp, vp, vp, pi64, pi32], i32),
         "bfc_count_total_sorted": ([vp, vp, i32, i64, pi64, pi64, pi64], i32),
+        "bfc_sync": ([vp, vp], i32),
+        "bfc_set_allocator": ([ALLOC_FN, FREE_FN, vp], i32),
+        "bfc_trim_cache": ([], i64),
+        "bfc_cached_bytes": ([], i64),
         "bfc_last_error": ([], ctypes.c_char_p),
         "bfc_version": ([], ctypes.c_char_p),
     }
@@ -104,7 +115,54 @@ def load(path: str | None = None):
         f.argtypes = args
         f.restype = res
     _lib = lib
+    if torch_memory:
+        use_torch_allocator()
     return lib
+
+
+def _torch_alloc(nbytes, stream, _ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), int(stream or 0))
+    except Exception:  # out of memory (or no device): the library reports BFC_ERR_OUT_OF_MEMORY
+        return None
+
+
+def _torch_free(ptr, _stream, _ctx):
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+def set_allocator(alloc=None, free=None) -> None:
+    """Installs Python functions alloc(bytes, stream) -> int pointer or None and
+    free(ptr, stream) as the library's source of device memory
+    (``bfc_set_allocator``); both None restores hipMalloc / hipFree."""
+    global _installed
+    if (alloc is None) != (free is None):
+        raise ValueError("alloc and free must both be given or both be None")
+    if alloc is None:
+        pair = (ALLOC_FN(), FREE_FN())
+    else:
+        pair = (ALLOC_FN(lambda n, st, c: alloc(int(n), int(st or 0))),
+                FREE_FN(lambda ptr, st, c: free(int(ptr), int(st or 0))))
+    _check(load(torch_memory=False).bfc_set_allocator(pair[0], pair[1], None))
+    _installed = pair
+
+
+def use_torch_allocator() -> None:
+    """Device memory from torch.cuda's caching allocator (counted in
+    torch.cuda.memory_allocated while the library holds it)."""
+    global _installed
+    pair = (ALLOC_FN(_torch_alloc), FREE_FN(_torch_free))
+    _check(load(torch_memory=False).bfc_set_allocator(pair[0], pair[1], None))
+    _installed = pair
+
+
+def trim_cache() -> int:
+    """Returns the library's idle cached device blocks to their allocator (bytes)."""
+    return int(load().bfc_trim_cache())
+
+
+def cached_bytes() -> int:
+    return int(load().bfc_cached_bytes())
 
 
 def _check(status: int) -> None:
@@ -177,16 +235,28 @@ class Graph:
         _check(load().bfc_count_total_async(self._h, _stream(stream), _ptr(out)))
         return out
 
-    def count_per_vertex(self, stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+    def count_per_vertex(self, stream=None, sync: bool = True) -> tuple[torch.Tensor, torch.Tensor]:
+        """(B_u by upper id, B_v by lower id), int64 CUDA tensors.  With sync
+        (the default) waits for the count and raises if its kernels failed
+        (``bfc_sync``); otherwise the call is asynchronous."""
         up = torch.empty(self.n_upper, dtype=torch.int64, device=self.device)
         lo = torch.empty(self.n_lower, dtype=torch.int64, device=self.device)
         _check(load().bfc_count_per_vertex(self._h, _stream(stream), _ptr(up), _ptr(lo)))
+        if sync:
+            self.sync(stream)
         return up, lo
 
-    def count_per_edge(self, stream=None) -> torch.Tensor:
+    def count_per_edge(self, stream=None, sync: bool = True) -> torch.Tensor:
+        """B_e in input edge order (int64 CUDA tensor [m]); sync as in count_per_vertex."""
         out = torch.empty(self.m, dtype=torch.int64, device=self.device)
         _check(load().bfc_count_per_edge(self._h, _stream(stream), _ptr(out)))
+        if sync:
+            self.sync(stream)
         return out
+
+    def sync(self, stream=None) -> None:
+        """Waits for the handle's counts; raises if any failed (``bfc_sync``)."""
+        _check(load().bfc_sync(self._h, _stream(stream)))
 
     def count_total_sorted(self, max_pairs: int = 0, stream=None, direction: int = 0) -> tuple[int, int, int]:
         """(B_G, pairs, chunks) by Algorithm 6's pair sort (``bfc_count_total_sorted``)

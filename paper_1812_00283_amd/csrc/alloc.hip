@@ -10,6 +10,11 @@
 // block stays cached and a new one is allocated.  Memory is returned to the
 // driver only when an allocation fails (blocks whose events have completed
 // are freed and the allocation is retried).
+//
+// The blocks themselves come from hipMalloc, or from the functions the caller
+// installs with bfc_set_allocator (for example a framework's caching
+// allocator, so that the library's memory is counted in its pool).  Every
+// block remembers the functions that made it and goes back through them.
 #include "internal.hpp"
 
 #include <map>
@@ -19,15 +24,24 @@ namespace bfc {
 
 namespace {
 
+// Where blocks come from: hipMalloc / hipFree when alloc is null.
+struct Source {
+  bfc_alloc_fn alloc = nullptr;
+  bfc_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+
 struct Block {
   size_t size = 0;
   int device = 0;
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
   bool pending = false;  // ev marks the end of the work queued before the free
+  Source src;            // the allocator that made the block
 };
 
 std::mutex g_mu;
+Source g_src;  // the allocator for new blocks (guarded by g_mu)
 std::unordered_map<void*, Block> g_live;
 std::multimap<std::pair<int, size_t>, std::pair<void*, Block>> g_free;  // (device, size) -> block
 
@@ -44,18 +58,42 @@ bool capturing(hipStream_t s) {
   return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
 }
 
-// Frees cached blocks of `device` whose work has completed (caller holds g_mu).
-void trim_locked(int device) {
+void release_block(void* p, const Block& b) {
+  if (b.src.free) b.src.free(p, b.stream, b.src.ctx);
+  else (void)hipFree(p);
+}
+
+// Frees cached blocks of `device` (every device when device < 0) whose work
+// has completed (caller holds g_mu).  Returns the number of bytes freed.
+int64_t trim_locked(int device) {
+  int64_t freed = 0;
   for (auto it = g_free.begin(); it != g_free.end();) {
     Block& b = it->second.second;
-    if (b.device == device && (!b.pending || hipEventQuery(b.ev) == hipSuccess)) {
+    if ((device < 0 || b.device == device) && (!b.pending || hipEventQuery(b.ev) == hipSuccess)) {
       if (b.ev) (void)hipEventDestroy(b.ev);
-      (void)hipFree(it->second.first);
+      int cur = -1;
+      (void)hipGetDevice(&cur);
+      if (cur != b.device) (void)hipSetDevice(b.device);
+      release_block(it->second.first, b);
+      if (cur >= 0 && cur != b.device) (void)hipSetDevice(cur);
+      freed += (int64_t)b.size;
       it = g_free.erase(it);
     } else {
       ++it;
     }
   }
+  return freed;
+}
+
+// One new block from the current source; null when it has no memory.
+void* new_block(size_t size, hipStream_t s, const Source& src) {
+  if (src.alloc) return src.alloc(size, s, src.ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, size) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
 }
 
 }  // namespace
@@ -79,26 +117,52 @@ void* cache_alloc(size_t bytes, hipStream_t s) {
       return p;
     }
   }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, size);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
+  Source src;
+  {
+    std::lock_guard<std::mutex> hold(g_mu);
+    src = g_src;
+  }
+  void* p = new_block(size, s, src);
+  if (!p) {
     {
       std::lock_guard<std::mutex> hold(g_mu);
       trim_locked(device);
     }
-    e = hipMalloc(&p, size);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error{BFC_ERR_OUT_OF_MEMORY, std::string("device allocation failed: ") + hipGetErrorString(e)};
-    }
+    p = new_block(size, s, src);
+    if (!p)
+      throw Error{BFC_ERR_OUT_OF_MEMORY,
+                  "device allocation of " + std::to_string(size) + " bytes failed" +
+                      (src.alloc ? " (installed allocator returned null)" : "")};
   }
   std::lock_guard<std::mutex> hold(g_mu);
   Block b;
   b.size = size;
   b.device = device;
+  b.stream = s;
+  b.src = src;
   g_live[p] = b;
   return p;
+}
+
+void set_allocator(bfc_alloc_fn alloc_fn, bfc_free_fn free_fn, void* ctx) {
+  std::lock_guard<std::mutex> hold(g_mu);
+  // idle blocks go back to the allocator that made them before the switch
+  trim_locked(-1);
+  g_src.alloc = alloc_fn;
+  g_src.free = free_fn;
+  g_src.ctx = ctx;
+}
+
+int64_t trim_cache() {
+  std::lock_guard<std::mutex> hold(g_mu);
+  return trim_locked(-1);
+}
+
+int64_t cached_bytes() {
+  std::lock_guard<std::mutex> hold(g_mu);
+  int64_t b = 0;
+  for (auto& kv : g_free) b += (int64_t)kv.second.second.size;
+  return b;
 }
 
 void cache_free(void* p, hipStream_t s) {

@@ -188,7 +188,7 @@ bfc_status bfc_count_total(bfc_graph g, void* stream, int64_t* total_host, int64
     BFC_HIP(hipStreamSynchronize(s));
     const int64_t v = rb[0];
     const int32_t st = *reinterpret_cast<const int32_t*>(rb + 1);
-    if (st) throw Error{BFC_ERR_DEVICE, "internal error: a counting window could not be sized"};
+    if (st) throw Error{BFC_ERR_DEVICE, "internal error: a counting window could not be sized (counts are inexact)"};
     *total_host = v;
     if (wedges_host) *wedges_host = h->sched.wedges;
   });
@@ -419,6 +419,15 @@ bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t) {
     if (!t) throw Error{BFC_ERR_INVALID_ARGUMENT, "tuning is null"};
     DeviceScope ds(h->device);
     std::lock_guard<std::mutex> hold(h->mu);
+    // a captured count holds the old schedule's buffers and settings: drop it
+    // (replay fails until the caller captures again)
+    if (h->cap_exec || h->cap_graph) {
+      if (h->used) BFC_HIP(hipEventSynchronize(h->done));
+      if (h->cap_exec) (void)hipGraphExecDestroy(h->cap_exec);
+      if (h->cap_graph) (void)hipGraphDestroy(h->cap_graph);
+      h->cap_exec = nullptr;
+      h->cap_graph = nullptr;
+    }
     if (t->light_max_wedges > 2048)
       throw Error{BFC_ERR_INVALID_ARGUMENT, "light_max_wedges must be at most 2048"};
     if (t->dense_block > 0 && (t->dense_block % 64 || t->dense_block > 32768))
@@ -444,6 +453,47 @@ bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t) {
       BFC_HIP(hipStreamSynchronize(nullptr));
     }
   });
+}
+
+bfc_status bfc_sync(bfc_graph g, void* stream) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    DeviceScope ds(h->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t* rb = static_cast<int32_t*>(pinned_stage(sizeof(int32_t)));
+    {
+      CountSection cs(h, s);
+      if (cs.capturing) throw Error{BFC_ERR_INVALID_ARGUMENT, "bfc_sync waits on the stream: not capturable"};
+      BFC_HIP(hipMemcpyAsync(rb, count_status(h), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      cs.finish();
+    }
+    BFC_HIP(hipStreamSynchronize(s));
+    if (*rb) throw Error{BFC_ERR_DEVICE, "internal error: a counting window could not be sized (counts are inexact)"};
+  });
+}
+
+bfc_status bfc_set_allocator(bfc_alloc_fn alloc_fn, bfc_free_fn free_fn, void* ctx) {
+  return guard([&] {
+    if (!alloc_fn != !free_fn)
+      throw Error{BFC_ERR_INVALID_ARGUMENT, "alloc_fn and free_fn must both be set or both be null"};
+    set_allocator(alloc_fn, free_fn, ctx);
+  });
+}
+
+int64_t bfc_trim_cache(void) {
+  try {
+    return trim_cache();
+  } catch (...) {
+    return 0;
+  }
+}
+
+int64_t bfc_cached_bytes(void) {
+  try {
+    return cached_bytes();
+  } catch (...) {
+    return 0;
+  }
 }
 
 bfc_status bfc_get_schedule_info(bfc_graph g, bfc_schedule_info* out) {

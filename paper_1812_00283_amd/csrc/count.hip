@@ -1488,9 +1488,7 @@ void zero_u64(void* p, int64_t n, hipStream_t s) {
   BFC_LAUNCH_CHECK();
 }
 
-int32_t* count_status(bfc_graph_s* g) {
-  return reinterpret_cast<int32_t*>(g->scratch.as<char>() + g->scratch_bytes - 128);
-}
+int32_t* count_status(bfc_graph_s* g) { return g->info.as<int32_t>() + kInfoCountStatus; }
 
 void prepare_count(bfc_graph_s* g, hipStream_t s) {
   prepare_dense(g, s);
@@ -1512,7 +1510,8 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   int32_t* med_cursor = reinterpret_cast<int32_t*>(g->scratch.as<char>() + big_cursor_bytes(g));
   // tickets: [0] big heavy starts, [1] medium heavy starts
   unsigned int* ticket = reinterpret_cast<unsigned int*>(g->scratch.as<char>() + g->scratch_bytes - 256);
-  int32_t* status = reinterpret_cast<int32_t*>(g->scratch.as<char>() + g->scratch_bytes - 128);
+  // sticky: set by any count on the handle, never cleared (read by the calls that wait)
+  int32_t* status = count_status(g);
 
   CountParams p{};
   for (int x = 0; x < 2; ++x) {
@@ -1584,7 +1583,6 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     p.dld[1] = d.PL;
   }
   zero_u64(ticket, 1, s);      // both tickets
-  zero_u64(status, 1, s);
   // events: [0] dense block [1] light [2] heavy [3] fold [4]
   bfc_graph_s::TimedCall tc{};
   if (g->timing) {

@@ -22,6 +22,10 @@ constexpr int32_t kWinMinDegree = 64;
 // byte offset of the caterpillar partial sums (64 int64 slots) in a graph's
 // info block (past the status words and the schedule totals), and its size
 constexpr int kInfoCaterpillars = 192;
+// int32 index in the info block of the count status word (bit 0: a counting
+// window could not be sized); zeroed by the build, set by the count kernels
+// and never cleared, so any later call that waits can report it
+constexpr int kInfoCountStatus = 6;
 constexpr int kInfoBytes = kInfoCaterpillars + 64 * 8;
 // Light starts of at most kSmallMax wedges use the small-table kernel, those
 // of at most kLightMidMax the mid-table one, the rest (to light_max) the
@@ -55,6 +59,13 @@ void set_error(bfc_status s, const std::string& what);
 // that work completes); cache_free_idle when no queued work uses it.  None
 // may be called for a stream that is being captured.
 void* cache_alloc(size_t bytes, hipStream_t s);
+// Installs the source of new blocks (null functions: hipMalloc / hipFree),
+// after returning every idle cached block to the allocator that made it.
+void set_allocator(bfc_alloc_fn alloc_fn, bfc_free_fn free_fn, void* ctx);
+// Returns every idle cached block to its allocator; the bytes freed.
+int64_t trim_cache();
+// Bytes held in idle cached blocks.
+int64_t cached_bytes();
 void cache_free(void* p, hipStream_t s);
 void cache_free_idle(void* p);
 // A pinned host buffer of at least `bytes` owned by the calling thread, for
@@ -270,7 +281,8 @@ void build_batch(bfc_graph_s* g, const int32_t* edges, const int64_t* eoff_host,
 // Allocates the count kernels' scratch for the current schedule on stream s
 // (not capture-safe; called when a schedule is built).
 void prepare_count(bfc_graph_s* g, hipStream_t s);
-// Device status word of the count kernels (0 = fine), reset by every count call.
+// Device status word of the count kernels on this handle (0 = fine): set by
+// any count call that failed internally, never cleared.
 int32_t* count_status(bfc_graph_s* g);
 // Sums the durations of timed count calls (waits for them).
 void collect_times(bfc_graph_s* g);

@@ -4,8 +4,14 @@ Requests (total, per-vertex or per-edge counts of one bipartite graph) arrive
 over time.  The server
 
 * admits work while its estimated device footprint fits the HBM budget
-  (``bfc_estimate_device_bytes`` plus outputs), evicting idle cached graphs
-  least-recently-used first;
+  (``bfc_estimate_device_bytes`` plus the uploaded edges and the outputs;
+  a follow-up on a resident graph reserves its outputs only, since the
+  graph's own reservation covers its count accumulators), counting the
+  library's idle cached blocks against the budget and trimming them when a
+  job does not fit, and evicting idle cached graphs least-recently-used
+  first.  A job larger than the whole budget can never fit beside others:
+  it is admitted alone once the server is idle (nothing admitted), so it
+  runs rather than waiting forever;
 * keeps built graphs device-resident so that follow-up queries on the same
   graph skip the build;
 * runs admitted work on several HIP streams ("slots") at once, so jobs that
@@ -62,13 +68,19 @@ def digest(*arrays: torch.Tensor) -> tuple[str, int]:
     return h.hexdigest(), total
 
 
-def job_bytes(m: int, nu: int, nl: int, kind: str) -> int:
-    b = bfc.estimate_device_bytes(m, nu, nl) + 8 * m  # graph + uploaded edges
+def out_bytes(m: int, nu: int, nl: int, kind: str) -> int:
+    """Device bytes of a request's outputs."""
     if kind == "vertex":
-        b += 8 * (nu + nl)
-    elif kind == "edge":
-        b += 8 * m
-    return b
+        return 8 * (nu + nl)
+    if kind == "edge":
+        return 8 * m
+    return 0
+
+
+def job_bytes(m: int, nu: int, nl: int, kind: str) -> int:
+    """A request that builds its graph: graph (build peak and count
+    accumulators), uploaded edges and outputs."""
+    return bfc.estimate_device_bytes(m, nu, nl) + 8 * m + out_bytes(m, nu, nl, kind)
 
 
 class _Resident:
@@ -128,15 +140,24 @@ class Server:
             raise self.errors[0]
 
     # ---------------------------------------------------------------- dispatcher
-    def _evict_for(self, need: int) -> bool:
-        """Frees idle cached graphs (LRU first) until `need` more bytes fit."""
-        while self.used + need > self.budget:
-            victim = next((k for k, r in self.cache.items() if r.users == 0), None)
+    def _in_use(self) -> int:
+        """Admitted bytes plus the library's idle cached blocks."""
+        return self.used + bfc.cached_bytes()
+
+    def _evict_for(self, need: int, keep: int | None = None) -> bool:
+        """Makes room for `need` more bytes: first returns the library's idle
+        cached blocks, then frees idle resident graphs (LRU first, never
+        `keep`)."""
+        if self._in_use() + need > self.budget:
+            bfc.trim_cache()
+        while self._in_use() + need > self.budget:
+            victim = next((k for k, r in self.cache.items() if r.users == 0 and k != keep), None)
             if victim is None:
                 return False
             r = self.cache.pop(victim)
             r.graph.close()
             self.used -= r.bytes
+            bfc.trim_cache()
         return True
 
     def _next_unit(self):
@@ -146,7 +167,7 @@ class Server:
         job = self.pending[0]
         if self.plain:
             need = job_bytes(job.m, job.n_upper, job.n_lower, job.kind)
-            if self.used + need > self.budget and self.used > 0:
+            if not self._evict_for(need) and self.used > 0:
                 return None
             self.pending.popleft()
             self.used += need
@@ -155,9 +176,8 @@ class Server:
         for i, jb in enumerate(self.pending):
             if jb.key in self.cache and jb.key not in self.inflight_keys:
                 r = self.cache[jb.key]
-                need = job_bytes(0, jb.n_upper, jb.n_lower, jb.kind) - bfc.estimate_device_bytes(0, jb.n_upper,
-                                                                                                   jb.n_lower)
-                if not self._evict_for_keep(need, jb.key):
+                need = out_bytes(jb.m, jb.n_upper, jb.n_lower, jb.kind)
+                if not self._evict_for(need, keep=jb.key):
                     continue
                 del self.pending[i]
                 r.users += 1
@@ -194,16 +214,6 @@ class Server:
             self.inflight_keys.add(jb.key)
             return ("single", [jb], need)
         return None
-
-    def _evict_for_keep(self, need: int, keep: int) -> bool:
-        while self.used + need > self.budget:
-            victim = next((k for k, r in self.cache.items() if r.users == 0 and k != keep), None)
-            if victim is None:
-                return False
-            r = self.cache.pop(victim)
-            r.graph.close()
-            self.used -= r.bytes
-        return True
 
     def _dispatch(self):
         try:
@@ -306,9 +316,11 @@ class Server:
         finally:
             keep = False
             if self.cache_on:
-                nbytes = bfc.estimate_device_bytes(jb.m, jb.n_upper, jb.n_lower)
+                # the larger of the estimate and what the handle holds (its
+                # scratch depends on the graph's largest degrees)
+                nbytes = max(bfc.estimate_device_bytes(jb.m, jb.n_upper, jb.n_lower), g.info()["device_bytes"])
                 with self.lock:
-                    if jb.key not in self.cache and self.used + nbytes <= self.budget:
+                    if jb.key not in self.cache and self._in_use() + nbytes <= self.budget:
                         self.cache[jb.key] = _Resident(g, nbytes)
                         self.used += nbytes
                         keep = True

@@ -1,12 +1,15 @@
 """Served form: results in the continuous-batching mix equal results alone.
 
 A seeded arrival trace (the served workload's generator, with smaller graphs
-so the oracle can check every total) is served twice: by the batched,
+so the oracle can check every request) is served twice: by the batched,
 caching, multi-stream server under a tight HBM budget, and one request at a
-time by the plain server.  Every request's output must be identical, every
-total must equal the oracle's, and admitted work must never exceed the
-budget.
+time by the plain server.  Every request's output must be identical in both,
+every output must equal the oracle's (totals by value, per-vertex and
+per-edge arrays by the digest of the whole array), and admitted work must
+never exceed the budget.
 """
+import hashlib
+
 import numpy as np
 import pytest
 
@@ -15,6 +18,21 @@ import oracle
 from paper_1812_00283_amd import serve
 
 pytestmark = pytest.mark.gpu
+
+
+def oracle_result(g, kind):
+    """The oracle's answer in the server's result form: the total, or
+    (sha256 of the int64 little-endian arrays, their sum)."""
+    if kind == "total":
+        return oracle.total(g)
+    arrays = oracle.vertex_counts(g) if kind == "vertex" else (oracle.edge_counts(g),)
+    h = hashlib.sha256()
+    s = 0
+    for a in arrays:
+        x = np.ascontiguousarray(a, dtype="<i8")
+        h.update(x.tobytes())
+        s += int(x.sum())
+    return h.hexdigest(), s
 
 
 def make_jobs(reqs, graphs):
@@ -40,7 +58,8 @@ def test_mix_equals_alone_and_oracle(gpu_lib):
     assert any(j.batched for j in mixed) and any(j.cache_hit for j in mixed)
     for a, b in zip(mixed, alone):
         assert a.result == b.result, (a.index, a.kind)
+    kinds = set()
     for jb in mixed:
-        if jb.kind == "total":
-            g = built[jb.key]
-            assert jb.result == oracle.total(g), jb.index
+        assert jb.result == oracle_result(built[jb.key], jb.kind), (jb.index, jb.kind)
+        kinds.add(jb.kind)
+    assert kinds == {"total", "vertex", "edge"}
