@@ -85,6 +85,28 @@ bfc_status bfc_count_total(bfc_graph g, void* stream, int64_t* total_host, int64
 bfc_status bfc_count_total_async(bfc_graph g, void* stream, int64_t* total_dev);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the count
+ * of bfc_count_total_async, whose kernels here keep their scratch (per-start
+ * cursors and work tickets) in a fixed array of bfc_static_scratch_bytes()
+ * bytes (64 MiB) that the library holds on each device it runs on until the
+ * process ends.  The call allocates and frees nothing, creates no event and
+ * records no memset (kernel timing is not applied), so it may be captured.
+ *   total_dev  device int64 [1], receives B_G (same value as bfc_count_total).
+ * When the full grid's cursors do not fit the array the count runs on fewer
+ * workgroups (slower, same result); BFC_ERR_TOO_LARGE when not even one
+ * workgroup's cursors fit (a start with more than about 5.5 million
+ * lower-priority neighbours).  The array is shared by every call on a
+ * device and keeps the last call's contents (the call clears what must
+ * start at zero): calls that overlap on one device, on different streams
+ * or from different threads, race and give wrong results; order them.
+ * Asynchronous on `stream`; internal failures are reported like those of
+ * bfc_count_per_vertex.
+ */
+bfc_status bfc_count_total_static(bfc_graph g, void* stream, int64_t* total_dev);
+int64_t bfc_static_scratch_bytes(void);
+
+/*
  * B_x for every vertex (Lemma 1 Eq. 1).  Each pair (start, end) with c
  * common lower-priority middles adds C(c,2) to both, and each of its c
  * wedges adds c-1 to its middle.

@@ -34,6 +34,7 @@ EXPORTS = [
     "bfc_build_batch", "bfc_count_total_batch", "bfc_batch_wedges", "bfc_graph_capture_total", "bfc_graph_replay",
     "bfc_graph_count", "bfc_caterpillars", "bfc_clustering_coefficient", "bfc_k_wing",
     "bfc_count_total_sorted", "bfc_sync", "bfc_set_allocator", "bfc_trim_cache", "bfc_cached_bytes",
+    "bfc_count_total_static", "bfc_static_scratch_bytes",
 ]
 
 # Signatures of the allocator functions bfc_set_allocator takes.
@@ -104,6 +105,8 @@ def load(path: str | None = None, torch_memory: bool = True):
         "bfc_k_wing": ([vp, i64, i32, i32, i64, vp, vp, vp, pi64, pi32], i32),
         "bfc_count_total_sorted": ([vp, vp, i32, i64, pi64, pi64, pi64], i32),
         "bfc_sync": ([vp, vp], i32),
+        "bfc_count_total_static": ([vp, vp, vp], i32),
+        "bfc_static_scratch_bytes": ([], i64),
         "bfc_set_allocator": ([ALLOC_FN, FREE_FN, vp], i32),
         "bfc_trim_cache": ([], i64),
         "bfc_cached_bytes": ([], i64),
@@ -233,6 +236,14 @@ class Graph:
         if out.dtype != torch.int64 or not out.is_cuda or out.numel() < 1:
             raise TypeError("out must be an int64 CUDA tensor")
         _check(load().bfc_count_total_async(self._h, _stream(stream), _ptr(out)))
+        return out
+
+    def count_total_static(self, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """As count_total_async, with the kernels' scratch in the library's fixed
+        device array (``bfc_count_total_static``: no allocation)."""
+        if out.dtype != torch.int64 or not out.is_cuda or out.numel() < 1:
+            raise TypeError("out must be an int64 CUDA tensor")
+        _check(load().bfc_count_total_static(self._h, _stream(stream), _ptr(out)))
         return out
 
     def count_per_vertex(self, stream=None, sync: bool = True) -> tuple[torch.Tensor, torch.Tensor]:

@@ -311,6 +311,25 @@ bfc_status bfc_count_total_async(bfc_graph g, void* stream, int64_t* total_dev) 
   });
 }
 
+bfc_status bfc_count_total_static(bfc_graph g, void* stream, int64_t* total_dev) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (!total_dev) throw Error{BFC_ERR_INVALID_ARGUMENT, "total_dev is null"};
+    if (min_count_scratch_bytes(h) > static_scratch_bytes())
+      throw Error{BFC_ERR_TOO_LARGE, "the count needs " + std::to_string(min_count_scratch_bytes(h)) +
+                                         " bytes of scratch; the static buffer holds " +
+                                         std::to_string(static_scratch_bytes())};
+    DeviceScope ds(h->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    CountSection cs(h, s);
+    zero_i64(total_dev, 1, s);
+    count(h, kTotal, total_dev, nullptr, nullptr, s, nullptr, true);
+    cs.finish();
+  });
+}
+
+int64_t bfc_static_scratch_bytes(void) { return (int64_t)static_scratch_bytes(); }
+
 bfc_status bfc_count_per_vertex(bfc_graph g, void* stream, int64_t* upper_dev, int64_t* lower_dev) {
   return guard([&] {
     bfc_graph_s* h = checked(g);

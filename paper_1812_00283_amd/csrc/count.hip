@@ -24,6 +24,8 @@
 //     end ids stay coalesced.
 // The count of a pair is final once its window has been walked, so the
 // per-edge and per-vertex second pass runs window by window.
+#include <algorithm>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -1467,11 +1469,37 @@ int med_grid_for(const bfc_graph_s* g) {
 int64_t cursor_stride_for(const bfc_graph_s* g) { return ((int64_t)g->sched.max_prefix + 63) / 64 * 64; }
 
 // scratch: three cursor arrays per big workgroup, three per medium workgroup
-// (stride kMedPre), then 256 bytes: the two tickets and the status word
-size_t big_cursor_bytes(const bfc_graph_s* g) {
-  return (size_t)big_grid_for(g) * 3 * (size_t)cursor_stride_for(g) * sizeof(int32_t);
+// (stride kMedPre), then 256 bytes: the two tickets
+size_t big_wg_bytes(const bfc_graph_s* g) { return 3 * (size_t)cursor_stride_for(g) * sizeof(int32_t); }
+size_t med_wg_bytes() { return 3 * (size_t)kMedPre * sizeof(int32_t); }
+size_t big_cursor_bytes(const bfc_graph_s* g) { return (size_t)big_grid_for(g) * big_wg_bytes(g); }
+size_t med_cursor_bytes(const bfc_graph_s* g) { return (size_t)med_grid_for(g) * med_wg_bytes(); }
+
+// ------------------------------------------------------------ static scratch
+// Scratch of bfc_count_total_static: a fixed array in device memory, so that
+// call allocates nothing.  Each device holds its own copy, at its own
+// address, for the life of the process.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_static_mu;
+void* g_static_ptr[256] = {};
+
+// Device address of this device's copy of `scratch` (the host-side name is
+// only a stand-in for it), looked up once per device with it current.
+void* static_scratch_ptr() {
+  int dev = 0;
+  BFC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 256) throw Error{BFC_ERR_DEVICE, "device index out of range"};
+  std::lock_guard<std::mutex> hold(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* ptr = nullptr;
+    BFC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw Error{BFC_ERR_DEVICE, "no device address for the static scratch"};
+    g_static_ptr[dev] = ptr;
+  }
+  return g_static_ptr[dev];
 }
-size_t med_cursor_bytes(const bfc_graph_s* g) { return (size_t)med_grid_for(g) * 3 * kMedPre * sizeof(int32_t); }
 
 __global__ void fill_zero_kernel(unsigned long long* __restrict__ p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -1499,17 +1527,48 @@ void prepare_count(bfc_graph_s* g, hipStream_t s) {
   }
 }
 
+size_t static_scratch_bytes() { return kStaticScratchBytes; }
+
+size_t min_count_scratch_bytes(const bfc_graph_s* g) {
+  size_t b = 256;
+  if (g->sched.n_heavy - g->sched.n_medium > 0) b += big_wg_bytes(g);
+  if (g->sched.n_medium > 0) b += med_wg_bytes();
+  return b;
+}
+
 void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, int64_t* out1, hipStream_t s,
-           int64_t* gtotals) {
+           int64_t* gtotals, bool static_scratch) {
   const Schedule& sc = g->sched;
   const int cus = num_cus();
-  const int big_grid = big_grid_for(g);
-  const int med_grid = med_grid_for(g);
+  int big_grid = big_grid_for(g);
+  int med_grid = med_grid_for(g);
   const int64_t stride = cursor_stride_for(g);
-  int32_t* cursor = g->scratch.as<int32_t>();
-  int32_t* med_cursor = reinterpret_cast<int32_t*>(g->scratch.as<char>() + big_cursor_bytes(g));
+  char* sbase = g->scratch.as<char>();
+  size_t sbytes = g->scratch_bytes;
+  if (static_scratch) {
+    // the same layout in the static array, with fewer workgroups when the
+    // full grid's cursors do not fit (the starts come from a ticket, so any
+    // grid of at least one workgroup counts every start)
+    const size_t need = min_count_scratch_bytes(g);
+    if (need > kStaticScratchBytes)
+      throw Error{BFC_ERR_TOO_LARGE, "the count needs " + std::to_string(need) +
+                                         " bytes of scratch; the static buffer holds " +
+                                         std::to_string(kStaticScratchBytes)};
+    sbase = static_cast<char*>(static_scratch_ptr());
+    sbytes = kStaticScratchBytes;
+    size_t room = kStaticScratchBytes - 256;
+    if (sc.n_medium > 0) {
+      const int fit = (int)std::min<size_t>((size_t)med_grid, (room - (sc.n_heavy > sc.n_medium ? big_wg_bytes(g) : 0)) /
+                                                                   med_wg_bytes());
+      med_grid = fit;
+      room -= (size_t)med_grid * med_wg_bytes();
+    }
+    if (sc.n_heavy - sc.n_medium > 0) big_grid = (int)std::min<size_t>((size_t)big_grid, room / big_wg_bytes(g));
+  }
+  int32_t* cursor = reinterpret_cast<int32_t*>(sbase);
+  int32_t* med_cursor = reinterpret_cast<int32_t*>(sbase + (size_t)big_grid * big_wg_bytes(g));
   // tickets: [0] big heavy starts, [1] medium heavy starts
-  unsigned int* ticket = reinterpret_cast<unsigned int*>(g->scratch.as<char>() + g->scratch_bytes - 256);
+  unsigned int* ticket = reinterpret_cast<unsigned int*>(sbase + sbytes - 256);
   // sticky: set by any count on the handle, never cleared (read by the calls that wait)
   int32_t* status = count_status(g);
 
@@ -1583,14 +1642,16 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     p.dld[1] = d.PL;
   }
   zero_u64(ticket, 1, s);      // both tickets
+  // kernel timing creates events: not in the static-scratch call, which creates nothing
+  const bool timing = g->timing && !static_scratch;
   // events: [0] dense block [1] light [2] heavy [3] fold [4]
   bfc_graph_s::TimedCall tc{};
-  if (g->timing) {
+  if (timing) {
     for (int i = 0; i < 5; ++i) BFC_HIP(hipEventCreate(&tc.ev[i]));
     BFC_HIP(hipEventRecord(tc.ev[0], s));
   }
   dense_block(g, s);
-  if (g->timing) BFC_HIP(hipEventRecord(tc.ev[1], s));
+  if (timing) BFC_HIP(hipEventRecord(tc.ev[1], s));
   {
     // the light list holds the small starts, then the mid ones, then the large ones
     const int4* llist = g->sched.light.as<int4>();
@@ -1630,7 +1691,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
       BFC_LAUNCH_CHECK();
     }
   }
-  if (g->timing) BFC_HIP(hipEventRecord(tc.ev[2], s));
+  if (timing) BFC_HIP(hipEventRecord(tc.ev[2], s));
   // the heavy list holds the big starts (decreasing work), then the medium ones
   const int32_t n_big = sc.n_heavy - sc.n_medium;
   if (n_big > 0) {
@@ -1652,7 +1713,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
     else heavy_kernel<kEdge, kMedNT, kMedWords><<<(unsigned)med_grid, kMedNT, 0, s>>>(p);
     BFC_LAUNCH_CHECK();
   }
-  if (g->timing) BFC_HIP(hipEventRecord(tc.ev[3], s));
+  if (timing) BFC_HIP(hipEventRecord(tc.ev[3], s));
   if (mode == kVertex) {
     for (int x = 0; x < 2; ++x) {
       const int32_t n = g->side[x].n;
@@ -1676,7 +1737,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
                                                        reinterpret_cast<unsigned long long*>(out0));
     BFC_LAUNCH_CHECK();
   }
-  if (g->timing) {
+  if (timing) {
     BFC_HIP(hipEventRecord(tc.ev[4], s));
     g->timed.push_back(tc);
   }

@@ -272,8 +272,14 @@ enum CountMode { kTotal = 0, kVertex = 1, kEdge = 2 };
 // per-vertex counts into out0 (upper, by id) and out1 (lower, by id).
 // kEdge: writes per-edge counts into out0 (int64 [m]).
 // gtotals (kTotal only): per-graph totals [n_graphs] instead of total_dev.
+// static_scratch: the kernels' cursors and tickets live in the library's
+// fixed device array instead of the handle's scratch (nothing is allocated;
+// BFC_ERR_TOO_LARGE when one workgroup's cursors do not fit it).
 void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, int64_t* out1, hipStream_t s,
-           int64_t* gtotals = nullptr);
+           int64_t* gtotals = nullptr, bool static_scratch = false);
+// Size of the fixed scratch array, and the least scratch a count of g needs.
+size_t static_scratch_bytes();
+size_t min_count_scratch_bytes(const bfc_graph_s* g);
 // Batch build: shifts each graph's ids into the union, validates them per
 // graph and builds the union; fills gid[] and graph_wedges.
 void build_batch(bfc_graph_s* g, const int32_t* edges, const int64_t* eoff_host, const int32_t* nu_host,
