@@ -319,6 +319,21 @@ int64_t bfc_cached_bytes(void);
  *                      256-thread workgroups with a 32 KB LDS table, four to
  *                      a CU; the others 1024 threads and 128 KB.  0 puts
  *                      every workgroup start on 1024 threads.  Default 0.
+ *   vpp                which wedges the hash / counter kernels process, per
+ *                      layer of the start (< 0 keeps; at most 3): bit 0 for
+ *                      upper starts, bit 1 for lower starts; a clear bit
+ *                      takes Algorithm 2's wedges (BFC-VP: the start
+ *                      outranks the middle and the end; default 0), a set
+ *                      bit Algorithm 3's (BFC-VP++, Section 5: the end
+ *                      outranks the start and the middle, so a start's ends
+ *                      are the ranks above it).  The two are the same wedges
+ *                      walked from opposite ends, and a butterfly's counted
+ *                      pair lies in the layer of its top vertex, so any mix
+ *                      gives the same counts and the same |W| (Lemma 3); the
+ *                      lists, light / heavy split and per-start work follow
+ *                      the chosen wedges.  With vpp != 0 the dense block and
+ *                      the 256-thread shape are not used (dense_block and
+ *                      medium_max_wedges are kept but ignored).
  */
 typedef struct {
   int32_t light_max_wedges;
@@ -328,6 +343,7 @@ typedef struct {
   int32_t dense_block;
   int32_t dense_min_wedges;
   int32_t medium_max_wedges;
+  int32_t vpp;
 } bfc_tuning;
 
 bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t);

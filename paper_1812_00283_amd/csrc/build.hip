@@ -638,6 +638,12 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
 // ---------------------------------------------------------------- schedule
 namespace {
 
+// deg[r] = off[r + 1] - off[r]
+__global__ void degree_of_kernel(const int32_t* __restrict__ off, int32_t n, int32_t* __restrict__ deg) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    deg[r] = off[r + 1] - off[r];
+}
+
 // Classifies start (x, r): 0 = no pair can reach a count of 2, 1 = light, 2 = heavy.
 // sums: [0] |W|, [1] max prefix of a heavy start, [2] light wedges,
 // [3] heavy wedges, [4] light middles, [5] heavy middles, [6] max start wedges
@@ -788,6 +794,33 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   Schedule& sc = g->sched;
   const int32_t n0 = g->side[0].n, n1 = g->side[1].n;
   const int64_t n = (int64_t)n0 + n1;
+  // Algorithm 2: a start's middles are its lower-priority prefix (lo) and its
+  // work the wedges through them.  Algorithm 3: every neighbour is a middle
+  // (the degree) and the work is Algorithm 3's count for the start.
+  const bool vpp = g->tune.vpp != 0;  // Algorithm 3 in at least one layer
+  TmpBuf degs[2];
+  const int64_t* work_x[2];
+  const int32_t* pre_x[2];
+  for (int x = 0; x < 2; ++x) {
+    Side& sd = g->side[x];
+    work_x[x] = sd.work.as<int64_t>();
+    pre_x[x] = sd.lo.as<int32_t>();
+    if (!((g->tune.vpp >> x) & 1)) continue;
+    if (sd.wpp.bytes < sizeof(int64_t) * (size_t)sd.n) {
+      sd.wpp.alloc(sizeof(int64_t) * (size_t)sd.n, s);
+      vpp_work(g, x, sd.wpp.as<int64_t>(), s);
+    }
+    degs[x].alloc(sizeof(int32_t) * (size_t)sd.n, s);
+    if (sd.n > 0) {
+      degree_of_kernel<<<grid_1d(sd.n), 256, 0, s>>>(sd.off.as<int32_t>(), sd.n, degs[x].as<int32_t>());
+      BFC_LAUNCH_CHECK();
+    }
+    work_x[x] = sd.wpp.as<int64_t>();
+    pre_x[x] = degs[x].as<int32_t>();
+  }
+  sc.vpp = g->tune.vpp;
+  // Algorithm 3's heavy starts all take the 1024-thread shape: the 256-thread
+  // shape hung on them (kept off until its cause is found)
   // totals go to g->info from byte 64: [0..7] the classify sums, [7] medium
   // starts, [8] light counts (small | mid << 32), [9] heavy | large light << 32
   unsigned long long* sums = reinterpret_cast<unsigned long long*>(g->info.as<char>() + 64);
@@ -799,13 +832,14 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   pos_h.alloc(sizeof(int64_t) * (size_t)(n + 1), s);
   const int64_t light_max =
       g->tune.light_max_wedges < g->light_max_cap() ? g->tune.light_max_wedges : g->light_max_cap();
-  const int32_t K = g->tune.dense_block;
+  // the dense block seeds Algorithm 2's windows only
+  const int32_t K = vpp ? 0 : g->tune.dense_block;
   int32_t KU = K > 0 ? (K < n0 ? K : n0) : 0;
   int32_t KL = K > 0 ? (K < n1 ? K : n1) : 0;
   if (KU == 0 || KL == 0) KU = KL = 0;
   if (n > 0) {
-    classify_kernel<<<grid_1d(n) < 1024 ? grid_1d(n) : 1024, kClassifyNT, 0, s>>>(g->side[0].work.as<int64_t>(), g->side[0].lo.as<int32_t>(), n0,
-                                                g->side[1].work.as<int64_t>(), g->side[1].lo.as<int32_t>(), n1,
+    classify_kernel<<<grid_1d(n) < 1024 ? grid_1d(n) : 1024, kClassifyNT, 0, s>>>(work_x[0], pre_x[0], n0,
+                                                work_x[1], pre_x[1], n1,
                                                 light_max, KU, KL, flags_l.as<int64_t>(), flags_h.as<int64_t>(),
                                                 sums);
     BFC_LAUNCH_CHECK();
@@ -825,10 +859,9 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   if (n > 0) {
     BFC_HIP(hipMemsetAsync(hkey.p, 0xFF, sizeof(uint32_t) * (size_t)n, s));  // past the heavy starts: key 0xFFFF...
     compact_kernel<<<grid_1d(n), 256, 0, s>>>(flags_l.as<int64_t>(), flags_h.as<int64_t>(), pos_l.as<int64_t>(),
-                                               pos_h.as<int64_t>(), n0, n1, g->side[0].work.as<int64_t>(),
-                                               g->side[1].work.as<int64_t>(), g->side[0].lo.as<int32_t>(),
-                                               g->side[1].lo.as<int32_t>(), g->side[0].off.as<int32_t>(),
-                                               g->side[1].off.as<int32_t>(), (int64_t)g->tune.medium_max_wedges, KU,
+                                               pos_h.as<int64_t>(), n0, n1, work_x[0], work_x[1], pre_x[0],
+                                               pre_x[1], g->side[0].off.as<int32_t>(),
+                                               g->side[1].off.as<int32_t>(), vpp ? 0 : (int64_t)g->tune.medium_max_wedges, KU,
                                                KL, sc.light.as<int4>(), hcode.as<int32_t>(), hkey.as<uint32_t>(),
                                                sums + 7, reinterpret_cast<long long*>(sums + 8));
     BFC_LAUNCH_CHECK();
@@ -838,8 +871,7 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
                      16, s);
     heavy_entries_kernel<<<grid_1d(n), 256, 0, s>>>(
         hcode.as<uint32_t>(), pos_h.as<int64_t>() + n, g->side[0].off.as<int32_t>(), g->side[1].off.as<int32_t>(),
-        g->side[0].lo.as<int32_t>(), g->side[1].lo.as<int32_t>(), g->side[0].work.as<int64_t>(),
-        g->side[1].work.as<int64_t>(), sc.heavy.as<int4>());
+        pre_x[0], pre_x[1], work_x[0], work_x[1], sc.heavy.as<int4>());
     BFC_LAUNCH_CHECK();
   }
 }

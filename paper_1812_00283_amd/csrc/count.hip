@@ -68,6 +68,8 @@ struct CountParams {
   const int32_t* wt[2];        // window-boundary tables per middle layer (rows for ranks >= wt_first)
   int32_t wt_first[2];
   int32_t wt_row[2];
+  int32_t vpp;                 // bit x: layer x's starts take Algorithm 3's wedges (ends above the start and the middle)
+  int32_t nX[2];               // layer sizes (the end of Algorithm 3's end ranges)
 };
 
 __device__ __forceinline__ int32_t graph_index(const CountParams& p, int x, int32_t r) {
@@ -87,6 +89,25 @@ __device__ __forceinline__ SideView pick(const CountParams& p, int x) {
 }
 
 __device__ __forceinline__ unsigned long long* pick_ptr(unsigned long long* const* a, int x) { return x ? a[1] : a[0]; }
+
+// Middle j of a start (its slot k = base + j in the start's list; lo_r =
+// the start's lower-priority prefix) and the slice [s0, e0) of adj_other
+// holding the ends of its wedges, ascending by end rank:
+//   Algorithm 2: the entries of N(v) before the start, [off(v), rev(k));
+//   Algorithm 3: the entries of N(v) above both the start and v: past the
+//   start's slot when v ranks below the start, else past v's own
+//   lower-priority prefix (which then holds the start).
+__device__ __forceinline__ void mid_slice(bool vpp, const SideView& S, const SideView& O, int32_t k, int32_t j,
+                                          int32_t lo_r, int32_t& v, int32_t& s0, int32_t& e0) {
+  v = S.adj[k];
+  if (!vpp) {
+    s0 = O.off[v];
+    e0 = S.rev[k];
+  } else {
+    s0 = j < lo_r ? S.rev[k] + 1 : O.off[v] + O.lo[v];
+    e0 = O.off[v + 1];
+  }
+}
 
 // Adds d to per-arc accumulator i of side x.  Every partial sum is at most
 // its edge's B_e <= (d_u - 1)(d_v - 1), so while the largest degrees keep
@@ -319,7 +340,8 @@ static_assert(kLightPackedCap / 2 < (1 << kLightCountBits), "packed counts must 
 static_assert(kLightMidMax <= kLightCap / 2, "mid starts must fit the mid table");
 
 // Each entry of the light list is {code, first slot of N(r), middles, wedges}.
-template <int kMode, int kCap, bool kPacked>
+// kVpp: some layer's starts take Algorithm 3's wedges (compiled out when not).
+template <int kMode, int kCap, bool kPacked, bool kVpp>
 __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const int4* __restrict__ list,
                                                          int32_t n_list) {
   // packed: kCap words; else kCap keys then kCap counts
@@ -347,6 +369,8 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
     const int32_t pre = cur.z;
     const SideView S = pick(p, x);
     const SideView O = pick(p, 1 - x);
+    const bool vpp = kVpp && ((p.vpp >> x) & 1);
+    const int32_t lo_r = vpp ? S.lo[r] : 0;
     uint32_t cap = 64;
     while ((int32_t)cap < 2 * cur.w) cap <<= 1;
     const uint32_t mask = cap - 1;
@@ -355,9 +379,9 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
       const int32_t j = j0 + lane;
       int32_t cs = 0, len = 0;
       if (j < pre) {
-        const int32_t k = base + j;
-        cs = O.off[S.adj[k]];
-        len = S.rev[k] - cs;
+        int32_t v, e;
+        mid_slice(vpp, S, O, base + j, j, lo_r, v, cs, e);
+        len = e - cs;
       }
       light_walk(O.adj, cs, len, [&](int, int32_t, int32_t w) {
         a += (unsigned)(kPacked ? wave_packed_inc(ptab, mask, w) : wave_hash_inc(keys, cnt, mask, w));
@@ -390,10 +414,9 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
         const int32_t j = j0 + lane;
         int32_t cs = 0, len = 0, v = 0;
         if (j < pre) {
-          const int32_t k = base + j;
-          v = S.adj[k];
-          cs = O.off[v];
-          len = S.rev[k] - cs;
+          int32_t e;
+          mid_slice(vpp, S, O, base + j, j, lo_r, v, cs, e);
+          len = e - cs;
         }
         light_walk(O.adj, cs, len, [&](int mid, int32_t slot, int32_t w) {
           const int32_t c = kPacked ? wave_packed_get(ptab, mask, w) : hash_get(keys, cnt, mask, w);
@@ -676,7 +699,8 @@ constexpr int32_t kRewalkMax = 8192;
 
 // One instantiation per count mode (the total count carries no second pass)
 // and per workgroup shape: kNT threads and an LDS table of kWords words.
-template <int kMode, int kNT, int kWords>
+// kVpp: some layer's starts take Algorithm 3's wedges (compiled out when not).
+template <int kMode, int kNT, int kWords, bool kVpp>
 __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
   constexpr int kWaves = kNT / 64;
   constexpr int kCap = kWords / 2;          // hash entries (keys | counts)
@@ -725,13 +749,17 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     const int32_t base = ent.y;
     const int32_t pre = ent.z;
     const int64_t W = ent.w < 0x7FFFFFFF ? (int64_t)ent.w : S.work[r];
-    const int32_t range = r;
-    // ends lie in [rlo, r): a batch ranks each graph's vertices contiguously
-    // (rlo = the graph's first rank, rounded down to even because dense
-    // counters pair ranks; one graph: 0)
+    const bool vpp = kVpp && ((p.vpp >> x) & 1);
+    const int32_t lo_r = vpp ? S.lo[r] : 0;
+    // End ranks lie in [elo, ehi): below the start under Algorithm 2, above
+    // it under Algorithm 3, within the start's graph (a batch ranks each
+    // graph's vertices contiguously).  elo is rounded down to even because
+    // dense counters pair ranks (rank r itself is never an end).
     const int32_t* grank = x ? p.grank[1] : p.grank[0];
-    const int32_t rlo = grank ? (grank[graph_index(p, x, r)] & ~1) : 0;
-    const int32_t span = range - rlo;
+    const int32_t gi = grank ? graph_index(p, x, r) : 0;
+    const int32_t elo = vpp ? ((r + 1) & ~1) : (grank ? (grank[gi] & ~1) : 0);
+    const int32_t ehi = vpp ? (grank ? grank[gi + 1] : p.nX[x]) : r;
+    const int32_t span = ehi - elo;
     // middles of rank >= tfirst find their window slices in the table and
     // keep no cursor
     const int32_t* tab = x ? p.wt[0] : p.wt[1];
@@ -752,31 +780,32 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     // walks only middles outside the other layer's block (a prefix).
     const int32_t top = x ? p.dtop[1] : p.dtop[0];
     const bool in_block = r > top;
-    const int32_t sparse_end = in_block ? top : range;
+    const int32_t sparse_end = in_block ? top : ehi;
     // Windows: hash windows over [0, hash_end) (width hwidth, adapted as they
     // go), then dense windows of `width` ranks up to sparse_end.
     int32_t width = half ? 2 * kWords : kWords;
     int32_t hwidth = 0, hash_end = 0;
     uint32_t cap = kCap;
     if (dense) {
-      const int32_t base_lo = S.off[rlo];
-      hash_end = rlo;
-      if (p.window_mode == 1 && base > base_lo) {
+      const int32_t base_lo = S.off[elo];
+      const int32_t base_hi = vpp ? S.off[ehi] : base;  // (Algorithm 2: ehi = r)
+      hash_end = elo;
+      if (p.window_mode == 1 && base_hi > base_lo) {
         // Sparse prefix of a dense start: the ends of its wedges are
         // neighbours of its middles, which in a degree-driven graph fall on
         // the start layer's vertices in proportion to their degree, so about
-        // W * (off_X[x] - off_X[rlo]) / (off_X[r] - off_X[rlo]) wedges end
+        // W * (off_X[x] - off_X[elo]) / (off_X[ehi] - off_X[elo]) wedges end
         // below rank x.  The prefix is the
         // longest multiple of the dense width expected to hold at most
         // hash_window_wedges of them (one 64-lane probe of off_X); a wrong
         // guess costs time only (an overfull hash window is split).
-        const int32_t step0 = (sparse_end - rlo + 63) / 64;
+        const int32_t step0 = (sparse_end - elo + 63) / 64;
         const int32_t step = (step0 + 2 * kWords - 1) / (2 * kWords) * (2 * kWords);
-        const int64_t xl = rlo + (int64_t)(lane + 1) * step;
+        const int64_t xl = elo + (int64_t)(lane + 1) * step;
         const bool ok = xl < sparse_end && (double)W * (double)(S.off[xl] - base_lo) <=
-                                               (double)p.hash_window_wedges * (double)(base - base_lo);
-        hash_end = rlo + __popcll(__ballot(ok)) * step;
-        hwidth = hash_end - rlo;
+                                               (double)p.hash_window_wedges * (double)(base_hi - base_lo);
+        hash_end = elo + __popcll(__ballot(ok)) * step;
+        hwidth = hash_end - elo;
       }
     } else {
       hash_end = sparse_end;
@@ -801,19 +830,18 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
       }
       pre_out = a;
     }
-    // one window over [0, range) needs no cursors; otherwise every middle
+    // one window over [elo, ehi) needs no cursors; otherwise every middle
     // below tfirst keeps its next slot and next end id in scratch
     auto init_cursors = [&] {
       for (int32_t j = t; j < pre; j += kNT) {
-        const int32_t k = base + j;
-        const int32_t v = S.adj[k];
+        int32_t v, ps, pe;
+        mid_slice(vpp, S, O, base + j, j, lo_r, v, ps, pe);
         if (v >= tfirst) continue;
-        const int32_t ps = O.off[v];
         pos[j] = ps;
-        nxt[j] = ps < S.rev[k] ? O.adj[ps] : kNone;
+        nxt[j] = ps < pe ? O.adj[ps] : kNone;
       }
     };
-    bool cursors = !(sparse_end == range && (hash_end >= range ? hwidth >= span : (hash_end == rlo && width >= span)));
+    bool cursors = !(sparse_end == ehi && (hash_end >= ehi ? hwidth >= span : (hash_end == elo && width >= span)));
     // Resident mode: a multi-window start with at most 2 * kNT middles
     // keeps middle 2t + h's slice state in thread t's registers: the end of
     // its list below r (re), the start of its current slice (rcs), and raux
@@ -829,10 +857,8 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         re[h] = rcs[h] = rce[h] = 0;
         raux[h] = rnv[h] = -1 - kNoEnd;
         if (j < pre) {
-          const int32_t k = base + j;
-          const int32_t v = S.adj[k];
-          const int32_t e = S.rev[k];
-          const int32_t cs = O.off[v];
+          int32_t v, cs, e;
+          mid_slice(vpp, S, O, base + j, j, lo_r, v, cs, e);
           re[h] = e;
           rcs[h] = rce[h] = cs;
           raux[h] = v >= tfirst ? (v - tfirst) * trow : -1 - (cs < e ? O.adj[cs] : kNoEnd);
@@ -842,7 +868,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
       init_cursors();
     }
     unsigned long long start_acc = 0;
-    int32_t lo_w = rlo;
+    int32_t lo_w = elo;
     for (;;) {
       int32_t hi_w;
       bool wdense = lo_w >= hash_end;
@@ -851,8 +877,8 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
       if (!seeded) {
         if (wdense) hi_w = (int64_t)lo_w + width >= sparse_end ? sparse_end : lo_w + width;
         else hi_w = (int64_t)lo_w + hwidth >= hash_end ? hash_end : lo_w + hwidth;
-      } else if (in_block && lo_w < range) {
-        hi_w = range;
+      } else if (in_block && lo_w < ehi) {
+        hi_w = ehi;
         wdense = true;
         whalf = false;
       } else {
@@ -862,7 +888,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
       const bool wpacked = !wdense && packable;  // hash entries of this window: key | count words
       if (seeded) {
         const int32_t* crow = (x ? p.dC[1] : p.dC[0]) + (int64_t)(r - top) * (x ? p.dld[1] : p.dld[0]);
-        for (int32_t i = t; i < range - top; i += kNT) table[i] = crow[i];
+        for (int32_t i = t; i < ehi - top; i += kNT) table[i] = crow[i];
       }
       // cursors advance during pass 1 only for dense windows of a total count
       // (a hash window may have to be redone; pass 2 needs the old cursors)
@@ -888,23 +914,24 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
             actv[h] = false;
             csv[h] = cev[h] = ev[h] = vv[h] = 0;
             if (j < npre) {
-              const int32_t k = base + j;
-              const int32_t e = S.rev[k];
-              const int32_t v = S.adj[k];
+              int32_t v, s0, e;
+              mid_slice(vpp, S, O, base + j, j, lo_r, v, s0, e);
               const int32_t pj = cursors ? pos[j] : 0;  // cursor state (meaningful below tfirst)
               const int32_t nj = cursors ? nxt[j] : kNone;
               ev[h] = e;
               vv[h] = v;
               if (!cursors) {
-                const int32_t cs = O.off[v];
-                csv[h] = cs;
+                csv[h] = s0;
                 cev[h] = e;
-                actv[h] = e > cs;
+                actv[h] = e > s0;
               } else if (v >= tfirst) {
+                // the table finds the window's slots in the whole list; the
+                // slice keeps to [s0, e)
                 const int32_t* rowp = tab + (int64_t)(v - tfirst) * trow;
-                const int32_t cs = table_lb(O.adj, rowp, lo_w);
+                int32_t cs = table_lb(O.adj, rowp, lo_w);
+                if (vpp) cs = cs > s0 ? cs : s0;  // (Algorithm 2: the table's slot is never before s0)
                 int32_t ce = e;
-                if (hi_w < range) {
+                if (hi_w < ehi) {
                   const int32_t c2 = table_lb(O.adj, rowp, hi_w);
                   ce = c2 < e ? c2 : e;
                 }
@@ -915,7 +942,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
                 const int32_t cs = pj;  // O.adj[cs] = nj < hi_w
                 actv[h] = true;
                 csv[h] = cs;
-                cev[h] = hi_w >= range ? e : (second ? cend[j] : near_lower_bound(O.adj, cs + 1, e, hi_w));
+                cev[h] = hi_w >= ehi ? e : (second ? cend[j] : near_lower_bound(O.adj, cs + 1, e, hi_w));
               }
             }
           }
@@ -986,14 +1013,16 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
           int32_t ce = cs, nv = -1 - raux[h];
           if (cs < e) {
             if (raux[h] >= 0) {
-              if (hi_w >= range) {
+              if (hi_w >= ehi) {
                 ce = e;
               } else {
+                // (Algorithm 3: the table's slot can lie before the slice)
                 const int32_t c2 = table_lb(O.adj, tab + raux[h], hi_w);
                 ce = c2 < e ? c2 : e;
+                if (vpp) ce = ce > cs ? ce : cs;
               }
             } else if (nv < hi_w) {
-              if (hi_w >= range) {
+              if (hi_w >= ehi) {
                 ce = e;
                 nv = kNoEnd;
               } else {
@@ -1262,10 +1291,12 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
       } else if (cursors && !advance_now && !resident) {
         // hash window of a total count: advance the cursors now that the window is final
         for (int32_t j = t; j < pre1; j += kNT) {
-          if (S.adj[base + j] < tfirst && nxt[j] < hi_w) {
+          int32_t v, s0, e;
+          mid_slice(vpp, S, O, base + j, j, lo_r, v, s0, e);
+          if (v < tfirst && nxt[j] < hi_w) {
             const int32_t ce = cend[j];
             pos[j] = ce;
-            nxt[j] = ce < S.rev[base + j] ? O.adj[ce] : kNone;
+            nxt[j] = ce < e ? O.adj[ce] : kNone;
           }
         }
       }
@@ -1527,6 +1558,29 @@ void prepare_count(bfc_graph_s* g, hipStream_t s) {
   }
 }
 
+template <int kCap, bool kPacked>
+void launch_light(CountMode mode, bool vpp, unsigned grid, hipStream_t s, const CountParams& p, const int4* l,
+                  int32_t n) {
+  if (vpp) {
+    if (mode == kTotal) light_kernel<kTotal, kCap, kPacked, true><<<grid, kLightNT, 0, s>>>(p, l, n);
+    else if (mode == kVertex) light_kernel<kVertex, kCap, kPacked, true><<<grid, kLightNT, 0, s>>>(p, l, n);
+    else light_kernel<kEdge, kCap, kPacked, true><<<grid, kLightNT, 0, s>>>(p, l, n);
+  } else {
+    if (mode == kTotal) light_kernel<kTotal, kCap, kPacked, false><<<grid, kLightNT, 0, s>>>(p, l, n);
+    else if (mode == kVertex) light_kernel<kVertex, kCap, kPacked, false><<<grid, kLightNT, 0, s>>>(p, l, n);
+    else light_kernel<kEdge, kCap, kPacked, false><<<grid, kLightNT, 0, s>>>(p, l, n);
+  }
+  BFC_LAUNCH_CHECK();
+}
+
+template <int kNT, int kWords, bool kVpp>
+void launch_heavy(CountMode mode, int grid, hipStream_t s, const CountParams& p) {
+  if (mode == kTotal) heavy_kernel<kTotal, kNT, kWords, kVpp><<<(unsigned)grid, kNT, 0, s>>>(p);
+  else if (mode == kVertex) heavy_kernel<kVertex, kNT, kWords, kVpp><<<(unsigned)grid, kNT, 0, s>>>(p);
+  else heavy_kernel<kEdge, kNT, kWords, kVpp><<<(unsigned)grid, kNT, 0, s>>>(p);
+  BFC_LAUNCH_CHECK();
+}
+
 size_t static_scratch_bytes() { return kStaticScratchBytes; }
 
 size_t min_count_scratch_bytes(const bfc_graph_s* g) {
@@ -1591,6 +1645,12 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   p.window_mode = g->tune.window_mode;
   p.hash_window_wedges = g->tune.hash_window_wedges;
   p.dense_min_wedges = g->tune.dense_min_wedges;
+  p.vpp = sc.vpp;
+  p.nX[0] = g->side[0].n;
+  p.nX[1] = g->side[1].n;
+  // Algorithm 3's per-start work (read when a list entry's clamps)
+  if (sc.vpp & 1) p.sv[0].work = g->side[0].wpp.as<int64_t>();
+  if (sc.vpp & 2) p.sv[1].work = g->side[1].wpp.as<int64_t>();
   for (int o = 0; o < 2; ++o) {
     p.wt[o] = g->wt[o].bytes ? g->wt[o].as<int32_t>() : nullptr;
     p.wt_first[o] = g->wt_first[o];
@@ -1660,35 +1720,18 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
       return (unsigned)(grid > (int64_t)cus * 16 ? (int64_t)cus * 16 : grid);
     };
     const int32_t n_small = sc.n_small, n_mid = sc.n_mid, n_large = sc.n_light - sc.n_small - sc.n_mid;
+    const bool vpp = sc.vpp != 0;
     if (n_small > 0) {
-      const unsigned grid = light_grid(n_small);
-      if (mode == kTotal) light_kernel<kTotal, kSmallCap, false><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
-      else if (mode == kVertex) light_kernel<kVertex, kSmallCap, false><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
-      else light_kernel<kEdge, kSmallCap, false><<<grid, kLightNT, 0, s>>>(p, llist, n_small);
-      BFC_LAUNCH_CHECK();
+      launch_light<kSmallCap, false>(mode, vpp, light_grid(n_small), s, p, llist, n_small);
     }
     if (n_mid > 0) {
-      const unsigned grid = light_grid(n_mid);
       const int4* l = llist + n_small;
-      if (g->light_packed) {
-        if (mode == kTotal) light_kernel<kTotal, kLightCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_mid);
-        else if (mode == kVertex) light_kernel<kVertex, kLightCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_mid);
-        else light_kernel<kEdge, kLightCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_mid);
-      } else {
-        if (mode == kTotal) light_kernel<kTotal, kLightCap, false><<<grid, kLightNT, 0, s>>>(p, l, n_mid);
-        else if (mode == kVertex) light_kernel<kVertex, kLightCap, false><<<grid, kLightNT, 0, s>>>(p, l, n_mid);
-        else light_kernel<kEdge, kLightCap, false><<<grid, kLightNT, 0, s>>>(p, l, n_mid);
-      }
-      BFC_LAUNCH_CHECK();
+      if (g->light_packed) launch_light<kLightCap, true>(mode, vpp, light_grid(n_mid), s, p, l, n_mid);
+      else launch_light<kLightCap, false>(mode, vpp, light_grid(n_mid), s, p, l, n_mid);
     }
     if (n_large > 0) {
       // only where the tables pack (light_max above 1024)
-      const unsigned grid = light_grid(n_large);
-      const int4* l = llist + n_small + n_mid;
-      if (mode == kTotal) light_kernel<kTotal, kLightPackedCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_large);
-      else if (mode == kVertex) light_kernel<kVertex, kLightPackedCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_large);
-      else light_kernel<kEdge, kLightPackedCap, true><<<grid, kLightNT, 0, s>>>(p, l, n_large);
-      BFC_LAUNCH_CHECK();
+      launch_light<kLightPackedCap, true>(mode, vpp, light_grid(n_large), s, p, llist + n_small + n_mid, n_large);
     }
   }
   if (timing) BFC_HIP(hipEventRecord(tc.ev[2], s));
@@ -1697,21 +1740,17 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   if (n_big > 0) {
     p.list = g->sched.heavy.as<int4>();
     p.n_list = n_big;
-    if (mode == kTotal) heavy_kernel<kTotal, kBigNT, kBigWords><<<(unsigned)big_grid, kBigNT, 0, s>>>(p);
-    else if (mode == kVertex) heavy_kernel<kVertex, kBigNT, kBigWords><<<(unsigned)big_grid, kBigNT, 0, s>>>(p);
-    else heavy_kernel<kEdge, kBigNT, kBigWords><<<(unsigned)big_grid, kBigNT, 0, s>>>(p);
-    BFC_LAUNCH_CHECK();
+    if (sc.vpp) launch_heavy<kBigNT, kBigWords, true>(mode, big_grid, s, p);
+    else launch_heavy<kBigNT, kBigWords, false>(mode, big_grid, s, p);
   }
   if (sc.n_medium > 0) {
+    // (the schedule has no medium starts when a layer takes Algorithm 3's wedges)
     p.list = g->sched.heavy.as<int4>() + n_big;
     p.n_list = sc.n_medium;
     p.ticket = ticket + 1;
     p.cursor = med_cursor;
     p.cursor_stride = kMedPre;
-    if (mode == kTotal) heavy_kernel<kTotal, kMedNT, kMedWords><<<(unsigned)med_grid, kMedNT, 0, s>>>(p);
-    else if (mode == kVertex) heavy_kernel<kVertex, kMedNT, kMedWords><<<(unsigned)med_grid, kMedNT, 0, s>>>(p);
-    else heavy_kernel<kEdge, kMedNT, kMedWords><<<(unsigned)med_grid, kMedNT, 0, s>>>(p);
-    BFC_LAUNCH_CHECK();
+    launch_heavy<kMedNT, kMedWords, false>(mode, med_grid, s, p);
   }
   if (timing) BFC_HIP(hipEventRecord(tc.ev[3], s));
   if (mode == kVertex) {

@@ -133,6 +133,7 @@ struct Side {
   DevBuf lo;       // int32 [n] number of neighbours with lower priority (a prefix of the list)
   DevBuf id_of;    // int32 [n] local rank -> input id
   DevBuf work;     // int64 [n] wedges Algorithm 2 processes from this start
+  DevBuf wpp;      // int64 [n] wedges Algorithm 3 processes from this start (computed when first needed)
 };
 
 struct Schedule {
@@ -150,6 +151,7 @@ struct Schedule {
   int64_t max_start_wedges = 0;
   int32_t light_max = 0; // thresholds the lists were built with
   int32_t medium_max = 0;
+  int32_t vpp = 0;       // bit x: the lists hold Algorithm 3's starts of layer x (entry = {code, off, degree, wedges})
 };
 
 struct Tuning {
@@ -160,6 +162,7 @@ struct Tuning {
   int32_t dense_block = 0;
   int32_t dense_min_wedges = 8192;
   int32_t medium_max_wedges = 0;  // 256-thread workgroups measured slower on the degree-skewed workloads
+  int32_t vpp = 0;                // bit x: layer x's starts count Algorithm 3's wedges (BFC-VP++), else Algorithm 2's
 };
 
 // Dense block of top-priority vertices (int8 MFMA, see dense.hip).
@@ -263,6 +266,9 @@ bool radix_sort_u64_keys_any(uint64_t* keys, uint64_t* keys_tmp, int64_t n, int 
 void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int32_t* const* groups = nullptr,
                  int32_t G = 0);
 void build_schedule(bfc_graph_s* g, hipStream_t s);
+// Wedges Algorithm 3 processes from every start of layer x (int64 [n_x]):
+// each neighbour v contributes the part of N(v) above both the start and v.
+void vpp_work(const bfc_graph_s* g, int x, int64_t* work, hipStream_t s);
 // Waits for the build and schedule queued on s and reads their results
 // (throws on a duplicate edge).  The only wait after the degree check.
 void finish_schedule(bfc_graph_s* g, hipStream_t s);

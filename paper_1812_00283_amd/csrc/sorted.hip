@@ -255,6 +255,18 @@ __global__ __launch_bounds__(kRunNT) void run_count_kernel(const uint64_t* __res
 
 }  // namespace
 
+void vpp_work(const bfc_graph_s* g, int x, int64_t* work, hipStream_t s) {
+  const Side& S = g->side[x];
+  const Side& O = g->side[1 - x];
+  const int32_t n = S.n;
+  if (n <= 0) return;
+  const int64_t wg = ((int64_t)n + 3) / 4;
+  vpp_work_kernel<<<(unsigned)(wg < 65536 ? wg : 65536), 256, 0, s>>>(
+      S.off.as<int32_t>(), S.adj.as<int32_t>(), S.rev.as<int32_t>(), S.lo.as<int32_t>(), O.off.as<int32_t>(),
+      O.lo.as<int32_t>(), n, work);
+  BFC_LAUNCH_CHECK();
+}
+
 void count_total_sorted(bfc_graph_s* g, int direction, int64_t max_pairs, hipStream_t s, int64_t* total_host,
                         int64_t* pairs_host, int64_t* chunks_host) {
   // the radix sort ranks keys with 32-bit offsets
@@ -279,11 +291,7 @@ void count_total_sorted(bfc_graph_s* g, int direction, int64_t max_pairs, hipStr
     const int64_t* work = S.work.as<int64_t>();
     if (plus) {
       work_plus.alloc(sizeof(int64_t) * (size_t)n, s);
-      const int64_t wg = ((int64_t)n + 3) / 4;
-      vpp_work_kernel<<<(unsigned)(wg < 65536 ? wg : 65536), 256, 0, s>>>(
-          S.off.as<int32_t>(), S.adj.as<int32_t>(), S.rev.as<int32_t>(), S.lo.as<int32_t>(), O.off.as<int32_t>(),
-          O.lo.as<int32_t>(), n, work_plus.as<int64_t>());
-      BFC_LAUNCH_CHECK();
+      vpp_work(g, x, work_plus.as<int64_t>(), s);
       work = work_plus.as<int64_t>();
     }
     exclusive_scan_i64(work, offs.as<int64_t>(), n, offs.as<int64_t>() + n, s);

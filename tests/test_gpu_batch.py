@@ -61,6 +61,29 @@ def test_small_batch_matches_oracle_and_plain_loop(gpu_lib):
                 assert p.count_total() == (int(totals[i]), int(wedges[i]))
 
 
+def test_small_batch_vpp(gpu_lib):
+    """Algorithm 3's wedges on a batch: each start's ends stay inside its
+    graph's ranks (above the start), so per-graph outputs are unchanged."""
+    graphs = small_batch(48, seed=13)
+    b = gg.concat(graphs)
+    with gpu_lib.build_batch(torch.from_numpy(b.edges).cuda(), b.offsets, b.n_upper, b.n_lower) as h:
+        for tun in ({"vpp": 3}, {"vpp": 3, "light_max_wedges": 1, "window_mode": 3, "hash_window_wedges": 16}):
+            h.set_tuning(**tun)
+            totals = h.count_total_batch().cpu().numpy()
+            up, lo = h.count_per_vertex()
+            be = h.count_per_edge()
+            up, lo, be = up.cpu().numpy(), lo.cpu().numpy(), be.cpu().numpy()
+            ou = ol = 0
+            for i, g in enumerate(graphs):
+                assert totals[i] == oracle.total(g), (i, tun)
+                o_up, o_lo = oracle.vertex_counts(g)
+                np.testing.assert_array_equal(up[ou:ou + g.n_upper], o_up)
+                np.testing.assert_array_equal(lo[ol:ol + g.n_lower], o_lo)
+                np.testing.assert_array_equal(be[b.offsets[i]:b.offsets[i + 1]], oracle.edge_counts(g))
+                ou += g.n_upper
+                ol += g.n_lower
+
+
 def test_batch_errors(gpu_lib):
     e = torch.tensor([[0, 0], [1, 1], [2, 0]], dtype=torch.int32, device="cuda")
     with pytest.raises(gpu_lib.BfcError) as err:   # edge 2 is outside graph 1's upper layer

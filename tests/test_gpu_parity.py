@@ -60,6 +60,20 @@ def test_random_tiny_graphs(gpu_lib):
         check_against_oracle(gpu_lib, g)
 
 
+def test_random_tiny_graphs_vpp(gpu_lib):
+    """Algorithm 3's wedges: the same outputs, and |W| equal to Algorithm 2's
+    (Lemma 3), on every tiny graph and on each kernel path."""
+    rng = np.random.default_rng(78)
+    for i in range(120):
+        g = gg.random_small(9500 + i, int(rng.integers(1, 12)), int(rng.integers(1, 12)),
+                            float(rng.choice([0.2, 0.5, 0.8, 1.0])))
+        tun = [{"vpp": 3}, {"vpp": 3, "light_max_wedges": 1}, {"vpp": 3, "light_max_wedges": 1, "window_mode": 3,
+                                                                 "hash_window_wedges": 4},
+               {"vpp": 1, "light_max_wedges": 1}, {"vpp": 2}][i % 5]
+        check_against_oracle(gpu_lib, g, tun)
+        assert oracle.vpp_wedges(g) == oracle.vp_wedges(g)
+
+
 def test_union_of_many_small_graphs(gpu_lib):
     rng = np.random.default_rng(5)
     parts, ou, ol = [], 0, 0
@@ -117,12 +131,39 @@ TUNINGS = {
     "medium-hash-tiny": {"light_max_wedges": 1, "window_mode": 3, "hash_window_wedges": 32,
                          "medium_max_wedges": 1 << 30},
     "medium-dense-block": {"light_max_wedges": 64, "dense_block": 1024, "medium_max_wedges": 1 << 30},
+    # Algorithm 3's wedges (BFC-VP++) through the same kernel paths: ends
+    # above the start, middles every neighbour
+    "vpp": {"vpp": 3},
+    "vpp-light-1024": {"vpp": 3, "light_max_wedges": 1024},
+    "vpp-all-workgroup": {"vpp": 3, "light_max_wedges": 1},
+    "vpp-dense-windows": {"vpp": 3, "light_max_wedges": 16, "window_mode": 2},
+    "vpp-hash-windows": {"vpp": 3, "light_max_wedges": 16, "window_mode": 3},
+    "vpp-hash-tiny-windows": {"vpp": 3, "light_max_wedges": 1, "window_mode": 3, "hash_window_wedges": 64},
+    "vpp-hash-overfull": {"vpp": 3, "light_max_wedges": 64, "window_mode": 3, "hash_window_wedges": 1 << 30},
+    "vpp-dense-ratio-1": {"vpp": 3, "dense_min_ratio": 1},
+    "vpp-auto-prefix-overfull": {"vpp": 3, "light_max_wedges": 64, "hash_window_wedges": 1 << 30},
+    "vpp-auto-prefix-small": {"vpp": 3, "light_max_wedges": 64, "dense_min_wedges": 256,
+                              "hash_window_wedges": 2048},
+    # (medium_max_wedges is ignored under vpp: these run on 1024-thread workgroups)
+    "vpp-medium-hash": {"vpp": 3, "light_max_wedges": 16, "window_mode": 3, "medium_max_wedges": 1 << 30},
+    "vpp-medium-hash-tiny": {"vpp": 3, "light_max_wedges": 1, "window_mode": 3, "hash_window_wedges": 32,
+                             "medium_max_wedges": 1 << 30},
+    "vpp-ignores-dense-block": {"vpp": 3, "dense_block": 1024, "light_max_wedges": 64},
+    # one layer's starts each way (a butterfly's counted pair lies in the
+    # layer of its top vertex, so any mix is exact)
+    "vpp-upper-only": {"vpp": 1},
+    "vpp-lower-only": {"vpp": 2, "light_max_wedges": 64},
 }
 
 
 @pytest.mark.parametrize("name", list(TUNINGS))
 def test_hub_graph_every_kernel_path(gpu_lib, hub_graph, hub_oracle, name):
-    tot, wed, up, lo, be = gpu_all(gpu_lib, hub_graph, TUNINGS[name] or None)
+    tun = TUNINGS[name]
+    tot, wed, up, lo, be = gpu_all(gpu_lib, hub_graph, tun or None)
+    if tun.get("vpp") and tun.get("medium_max_wedges"):
+        with gpu_lib.Graph(to_dev(hub_graph), hub_graph.n_upper, hub_graph.n_lower) as h:
+            h.set_tuning(**tun)
+            assert h.schedule_info()["starts_medium"] == 0
     o_tot, o_wed, o_up, o_lo, o_be = hub_oracle
     assert tot == o_tot and wed == o_wed
     np.testing.assert_array_equal(up, o_up)

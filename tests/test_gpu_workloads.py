@@ -39,12 +39,14 @@ def digest(t: torch.Tensor) -> str:
     return hashlib.sha256(t.cpu().numpy().astype("<i8").tobytes()).hexdigest()
 
 
-def run_workload(gpu_lib, name, per_vertex=True, per_edge=True, live_samples=8, sorted_count=False):
+def run_workload(gpu_lib, name, per_vertex=True, per_edge=True, live_samples=8, sorted_count=False, tuning=None):
     rec = golden(name)
     g = gg.workload(name)
-    print(f"{name}: generated m={g.m}", flush=True)
+    print(f"{name}: generated m={g.m} tuning={tuning}", flush=True)
     assert g.sha256() == rec["edges_sha256"], "generator output changed"
     with gpu_lib.Graph(to_dev(g), g.n_upper, g.n_lower) as h:
+        if tuning:
+            h.set_tuning(**tuning)
         tot, wed = h.count_total()
         print(f"{name}: total={tot} wedges={wed}", flush=True)
         assert tot == rec["total"]
@@ -96,3 +98,12 @@ def test_chunglu_1m_500k_20m(gpu_lib):
 
 def test_chunglu_16m_4m_200m_planted(gpu_lib):
     run_workload(gpu_lib, "chunglu-16m-4m-200m-planted", live_samples=4, sorted_count=True)
+
+
+def test_chunglu_1m_500k_20m_vpp(gpu_lib):
+    """Algorithm 3's wedges on the 20M-edge graph: every output identical."""
+    run_workload(gpu_lib, "chunglu-1m-500k-20m", live_samples=4, tuning={"vpp": 3})
+
+
+def test_chunglu_16m_4m_200m_planted_vpp(gpu_lib):
+    run_workload(gpu_lib, "chunglu-16m-4m-200m-planted", per_vertex=False, live_samples=4, tuning={"vpp": 3})
