@@ -194,6 +194,71 @@ def cpu_baseline(g, wedges: int, target_s: float = 15.0) -> dict:
     }
 
 
+SECONDARY_WORKLOAD = "chunglu-16m-4m-200m-planted"
+
+
+def secondary_record(name: str, steps: int, warmup: int) -> dict:
+    """The 200M-edge graph beside the headline: steps of bfc_build +
+    bfc_count_total with the default settings and with the per-layer wedge
+    direction the tuner picks on this graph (picked once, before the timed
+    steps; the step then includes the schedule rebuild that applies it), each
+    with the heavy kernel's roofline entry (HIP events on its stream)."""
+    import torch
+
+    import graphgen as gg
+    from paper_1812_00283_amd import bfc, tune
+
+    t = time.perf_counter()
+    g = gg.workload(name)
+    log(f"generated {name}: m={g.m} in {time.perf_counter() - t:.1f}s")
+    gold = golden_total(name)
+    if gold and gold[2] != g.sha256():
+        gold = None
+    edges = torch.from_numpy(np.ascontiguousarray(g.edges)).cuda()
+    with bfc.Graph(edges, g.n_upper, g.n_lower) as h:
+        choice, ms = tune.pick_direction(h)
+    log(f"{name}: direction masks (count ms) {ms}: tuner picks {choice}")
+    rec = {"workload": name, "m": g.m, "n_upper": g.n_upper, "n_lower": g.n_lower,
+           "tuner_direction_count_ms": {str(k): v for k, v in ms.items()}}
+    for label, tun in (("default", None), ("tuned", choice)):
+        steps_s, count_s, heavy_ms, tots = [], [], [], set()
+        si = None
+        for i in range(warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = bfc.Graph(edges, g.n_upper, g.n_lower)
+            if tun:
+                h.set_tuning(**tun)
+            h.set_kernel_timing(True)
+            tb = time.perf_counter()
+            tot, wed = h.count_total()
+            tc = time.perf_counter() - tb
+            kt = h.kernel_times()
+            si = h.schedule_info()
+            h.close()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            tots.add((tot, wed))
+            if i >= warmup:
+                steps_s.append(dt)
+                count_s.append(tc)
+                heavy_ms.append(kt["heavy_ms"] / max(kt["calls"], 1))
+            log(f"{name} {label} step {i}: {1e3 * dt:.1f} ms (count {1e3 * tc:.1f} ms, heavy {heavy_ms[-1] if heavy_ms else 0:.1f} ms)")
+        assert len(tots) == 1, "totals differ between steps"
+        tot, wed = tots.pop()
+        hk = float(np.mean(heavy_ms))
+        hb = heavy_kernel_bytes(si)
+        ms_step = 1e3 * float(np.mean(steps_s))
+        rec[label] = {
+            "tuning": tun or "default", "ms_per_step": ms_step, "wedges_per_s": wed / (ms_step / 1e3),
+            "count_ms": 1e3 * float(np.median(count_s)), "heavy_ms": hk,
+            "heavy_roofline": {"achieved": hb / (hk / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": hb / (hk / 1e3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": hb},
+            "butterflies": tot, "wedges": wed, "exact_vs_oracle": bool(gold and gold[0] == tot and gold[1] == wed),
+        }
+    return rec
+
+
 def bench_batch(args) -> int:
     """Batched form: all graphs in one handle (one build, one set of count
     launches replayed from a captured HIP graph) against a loop of
@@ -203,6 +268,8 @@ def bench_batch(args) -> int:
     import graphgen as gg
     from paper_1812_00283_amd import bfc
 
+    from paper_1812_00283_amd import tune
+
     bfc.load()
     t = time.perf_counter()
     b = gg.batch_workload(count=args.graphs)
@@ -211,30 +278,48 @@ def bench_batch(args) -> int:
     stream = torch.cuda.Stream()  # capture needs a created stream
     torch.cuda.synchronize()
     totals = torch.zeros(b.count, dtype=torch.int64, device="cuda")
-    # batched: build + captured count
-    ref = None
-    times_build, times_count = [], []
-    for i in range(args.warmup + args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        h = bfc.build_batch(edges, b.offsets, b.n_upper, b.n_lower, stream)
-        t1 = time.perf_counter()
-        h.capture_total(totals, stream)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        h.replay(stream)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        got = totals.cpu().numpy().copy()
-        ref = got if ref is None else ref
-        assert (got == ref).all()
-        if i >= args.warmup:
-            times_build.append(t1 - t0)
-            times_count.append(t3 - t2)
-        wed = h.batch_wedges()
-        h.close()
-        log(f"batched step {i}: build {1e3 * (t1 - t0):.1f} ms, replayed count {1e3 * (t3 - t2):.1f} ms")
-    batched_s = float(np.median(times_build)) + float(np.median(times_count))
+    # the tuner: per (size, skew) bucket, the fastest setting on a sample of
+    # the bucket's graphs (before and outside the timed steps)
+    t = time.perf_counter()
+    buckets = tune.graph_buckets(b.edges, b.offsets, b.n_upper, b.n_lower)
+    table = tune.tune_batch(b.edges, b.offsets, b.n_upper, b.n_lower, log=log)
+    tune_s = time.perf_counter() - t
+    log(f"tuned {len(table)} buckets in {tune_s:.1f}s")
+
+    def batched(tuned: bool):
+        """Steps of batched build (+ per-graph settings) + captured count,
+        replayed; returns (build s, count s, totals, wedges)."""
+        ref = None
+        times_build, times_count = [], []
+        for i in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = bfc.build_batch(edges, b.offsets, b.n_upper, b.n_lower, stream)
+            if tuned:
+                tune.apply_table(h, table, buckets)
+            t1 = time.perf_counter()
+            h.capture_total(totals, stream)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            h.replay(stream)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            got = totals.cpu().numpy().copy()
+            ref = got if ref is None else ref
+            assert (got == ref).all()
+            if i >= args.warmup:
+                times_build.append(t1 - t0)
+                times_count.append(t3 - t2)
+            wed = h.batch_wedges()
+            h.close()
+            log(f"batched{' tuned' if tuned else ''} step {i}: build {1e3 * (t1 - t0):.1f} ms, "
+                f"replayed count {1e3 * (t3 - t2):.1f} ms")
+        return float(np.median(times_build)), float(np.median(times_count)), ref, wed
+
+    d_build, d_count, ref, wed = batched(False)
+    t_build, t_count, ref_t, _ = batched(True)
+    assert (ref_t == ref).all(), "tuned and default per-graph totals differ"
+    batched_s = t_build + t_count
     # plain: one graph per handle
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -255,15 +340,22 @@ def bench_batch(args) -> int:
             rec = json.load(f)["batch-4096"]
         exact = bool(rec["sha256"] == b.sha256() and (np.array(rec["totals"]) == ref).all())
     print(json.dumps({
-        "metric": "batched graphs/s", "value": b.count / batched_s, "unit": "graphs/s", "n_gpus": 1,
+        "metric": "batched graphs/s (tuned)", "value": b.count / batched_s, "unit": "graphs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * batched_s, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"batch-{b.count}", "edges": int(b.offsets[-1]), "wedges": int(wed.sum()),
                    "exact_vs_oracle": exact},
-        "batched_build_ms": 1e3 * float(np.median(times_build)),
-        "batched_count_ms": 1e3 * float(np.median(times_count)),
+        "batched_build_ms": 1e3 * t_build,
+        "batched_count_ms": 1e3 * t_count,
+        "default_tuning": {"graphs_per_s": b.count / (d_build + d_count), "build_ms": 1e3 * d_build,
+                           "count_ms": 1e3 * d_count},
+        "tuner": {"seconds": tune_s, "buckets": {k: {kk: v[kk] for kk in ("tuning", "graphs", "default_ms",
+                                                                            "tuned_ms")}
+                                                 for k, v in table.items()}},
         "plain_graphs_per_s": b.count / plain_s, "plain_ms": 1e3 * plain_s,
         "speedup_vs_plain": plain_s / batched_s,
+        "capture": "count only: the build waits on the device twice (degree check, schedule sizes), so it is "
+                   "not capturable",
     }), flush=True)
     return 0
 
@@ -416,6 +508,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 200M-edge graph's record that follows the headline")
     ap.add_argument("--steps-only", action="store_true",
                     help="time the steps only: no per-vertex / per-edge counts and no copy measurement afterwards "
                          "(for profiler runs whose kernels should all be steps)")
@@ -603,6 +697,10 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         result["cpu_baseline"] = cpu_baseline(g, wedges)
+    if args.workload == DEFAULT_WORKLOAD and not args.steps_only and not args.no_secondary:
+        del edges, g
+        torch.cuda.empty_cache()
+        result["secondary"] = secondary_record(SECONDARY_WORKLOAD, steps=3, warmup=1)
     print(json.dumps(result), flush=True)
     return 0
 

@@ -347,6 +347,21 @@ typedef struct {
 } bfc_tuning;
 
 bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t);
+
+/*
+ * Per-graph settings of a batch handle (bfc_build_batch), for an autotuner
+ * that picks settings per kind of graph while every graph is still counted
+ * by the same launches: tunings_host[g] (host array of `count` =
+ * the handle's number of graphs) applies to the starts of graph g.  Used
+ * fields: light_max_wedges (which kernel takes a start), dense_min_ratio,
+ * window_mode, hash_window_wedges and dense_min_wedges (how its end range
+ * is cut); a field <= 0 takes the handle's setting; other fields are
+ * ignored (they stay per handle).  count = 0 returns every graph to the
+ * handle's settings.  No count changes.  Rebuilds the schedule and discards
+ * a captured count, as bfc_set_tuning does.  BFC_ERR_INVALID_ARGUMENT for a
+ * handle from bfc_build, another count, or a field out of range.
+ */
+bfc_status bfc_set_graph_tuning(bfc_graph g, const bfc_tuning* tunings_host, int32_t count);
 bfc_status bfc_get_tuning(bfc_graph g, bfc_tuning* t);
 
 /*

@@ -34,7 +34,7 @@ EXPORTS = [
     "bfc_build_batch", "bfc_count_total_batch", "bfc_batch_wedges", "bfc_graph_capture_total", "bfc_graph_replay",
     "bfc_graph_count", "bfc_caterpillars", "bfc_clustering_coefficient", "bfc_k_wing",
     "bfc_count_total_sorted", "bfc_sync", "bfc_set_allocator", "bfc_trim_cache", "bfc_cached_bytes",
-    "bfc_count_total_static", "bfc_static_scratch_bytes",
+    "bfc_count_total_static", "bfc_static_scratch_bytes", "bfc_set_graph_tuning",
 ]
 
 # Signatures of the allocator functions bfc_set_allocator takes.
@@ -107,6 +107,7 @@ def load(path: str | None = None, torch_memory: bool = True):
         "bfc_sync": ([vp, vp], i32),
         "bfc_count_total_static": ([vp, vp, vp], i32),
         "bfc_static_scratch_bytes": ([], i64),
+        "bfc_set_graph_tuning": ([vp, vp, i32], i32),
         "bfc_set_allocator": ([ALLOC_FN, FREE_FN, vp], i32),
         "bfc_trim_cache": ([], i64),
         "bfc_cached_bytes": ([], i64),
@@ -327,6 +328,20 @@ class Graph:
         t = Tuning(light_max_wedges, dense_min_ratio, window_mode, hash_window_wedges, dense_block, dense_min_wedges,
                    medium_max_wedges, vpp)
         _check(load().bfc_set_tuning(self._h, ctypes.byref(t)))
+
+    def set_graph_tuning(self, per_graph) -> None:
+        """Per-graph settings of a batch handle (``bfc_set_graph_tuning``):
+        one dict of bfc_set_tuning fields per graph (missing fields take the
+        handle's); an empty list clears them."""
+        fields = [f for f, _ in Tuning._fields_]
+        if not per_graph:
+            _check(load().bfc_set_graph_tuning(self._h, None, 0))
+            return
+        arr = (Tuning * len(per_graph))()
+        for i, d in enumerate(per_graph):
+            for f in fields:
+                setattr(arr[i], f, int(d.get(f, -1 if f in ("dense_block", "medium_max_wedges", "vpp") else 0)))
+        _check(load().bfc_set_graph_tuning(self._h, ctypes.cast(arr, ctypes.c_void_p), len(per_graph)))
 
     def get_tuning(self) -> dict:
         t = Tuning()

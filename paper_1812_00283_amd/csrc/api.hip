@@ -2,6 +2,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 #include "sorted.hpp"
@@ -515,6 +516,59 @@ int64_t bfc_cached_bytes(void) {
   } catch (...) {
     return 0;
   }
+}
+
+bfc_status bfc_set_graph_tuning(bfc_graph g, const bfc_tuning* tunings_host, int32_t count) {
+  return guard([&] {
+    bfc_graph_s* h = checked(g);
+    if (count != 0 && count != h->n_graphs)
+      throw Error{BFC_ERR_INVALID_ARGUMENT, "count must be 0 or the handle's number of graphs"};
+    if (count > 0 && !tunings_host) throw Error{BFC_ERR_INVALID_ARGUMENT, "tunings_host is null"};
+    if (count > 0 && !h->gid[0].bytes)
+      throw Error{BFC_ERR_INVALID_ARGUMENT, "per-graph settings need a batch handle (else use bfc_set_tuning)"};
+    DeviceScope ds(h->device);
+    std::lock_guard<std::mutex> hold(h->mu);
+    if (h->cap_exec || h->cap_graph) {
+      if (h->used) BFC_HIP(hipEventSynchronize(h->done));
+      if (h->cap_exec) (void)hipGraphExecDestroy(h->cap_exec);
+      if (h->cap_graph) (void)hipGraphDestroy(h->cap_graph);
+      h->cap_exec = nullptr;
+      h->cap_graph = nullptr;
+    }
+    if (h->used) BFC_HIP(hipEventSynchronize(h->done));
+    BFC_HIP(hipDeviceSynchronize());
+    if (count == 0) {
+      // back to the handle's settings (the device is idle: free at once)
+      for (DevBuf* b : {&h->glight, &h->gtune}) {
+        if (b->p) cache_free_idle(b->p);
+        b->p = nullptr;
+        b->bytes = 0;
+      }
+    } else {
+      const int32_t cap = h->light_max_cap();
+      std::vector<int32_t> lm(count);
+      std::vector<int4> gt(count);
+      for (int32_t i = 0; i < count; ++i) {
+        const bfc_tuning& t = tunings_host[i];
+        if (t.light_max_wedges > 2048 || t.window_mode > 3)
+          throw Error{BFC_ERR_INVALID_ARGUMENT, "light_max_wedges above 2048 or window_mode above 3"};
+        const int32_t l = t.light_max_wedges > 0 ? t.light_max_wedges : h->tune.light_max_wedges;
+        lm[i] = l < cap ? l : cap;
+        gt[i] = make_int4(t.dense_min_ratio > 0 ? t.dense_min_ratio : h->tune.dense_min_ratio,
+                          t.window_mode > 0 ? t.window_mode : h->tune.window_mode,
+                          t.hash_window_wedges > 0 ? t.hash_window_wedges : h->tune.hash_window_wedges,
+                          t.dense_min_wedges > 0 ? t.dense_min_wedges : h->tune.dense_min_wedges);
+      }
+      h->glight.alloc(sizeof(int32_t) * (size_t)count, nullptr);
+      h->gtune.alloc(sizeof(int4) * (size_t)count, nullptr);
+      BFC_HIP(hipMemcpy(h->glight.p, lm.data(), sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice));
+      BFC_HIP(hipMemcpy(h->gtune.p, gt.data(), sizeof(int4) * (size_t)count, hipMemcpyHostToDevice));
+    }
+    build_schedule(h, nullptr);
+    finish_schedule(h, nullptr);
+    prepare_count(h, nullptr);
+    BFC_HIP(hipStreamSynchronize(nullptr));
+  });
 }
 
 bfc_status bfc_get_schedule_info(bfc_graph g, bfc_schedule_info* out) {

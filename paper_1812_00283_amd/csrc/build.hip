@@ -653,7 +653,9 @@ constexpr int kClassifyNT = 256;
 
 __global__ __launch_bounds__(kClassifyNT) void classify_kernel(const int64_t* __restrict__ work0, const int32_t* __restrict__ lo0, int32_t n0,
                                 const int64_t* __restrict__ work1, const int32_t* __restrict__ lo1, int32_t n1,
-                                int64_t light_max, int32_t KU, int32_t KL, int64_t* __restrict__ is_light,
+                                int64_t light_max, const int32_t* __restrict__ glight,
+                                const int32_t* __restrict__ gid0, const int32_t* __restrict__ gid1,
+                                int32_t KU, int32_t KL, int64_t* __restrict__ is_light,
                                 int64_t* __restrict__ is_heavy, unsigned long long* __restrict__ sums) {
   const int64_t n = (int64_t)n0 + n1;
   unsigned long long s_all = 0, s_lw = 0, s_hw = 0, s_lm = 0, s_hm = 0, max_w = 0;
@@ -662,7 +664,9 @@ __global__ __launch_bounds__(kClassifyNT) void classify_kernel(const int64_t* __
     const int64_t w = i < n0 ? work0[i] : work1[i - n0];
     const int32_t pre = i < n0 ? lo0[i] : lo1[i - n0];
     const bool in_block = i < n0 ? i >= (int64_t)n0 - KU : (i - n0) >= (int64_t)n1 - KL;
-    const bool heavy = w > light_max || (in_block && w >= 2);
+    // a tuned batch: this start's graph's cutoff
+    const int64_t lm = glight ? (int64_t)glight[i < n0 ? gid0[i] : gid1[i - n0]] : light_max;
+    const bool heavy = w > lm || (in_block && w >= 2);
     const bool light = w >= 2 && !heavy;
     s_all += (unsigned long long)w;
     // light starts: small ones count in is_light's low word, mid ones in its
@@ -840,7 +844,9 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   if (n > 0) {
     classify_kernel<<<grid_1d(n) < 1024 ? grid_1d(n) : 1024, kClassifyNT, 0, s>>>(work_x[0], pre_x[0], n0,
                                                 work_x[1], pre_x[1], n1,
-                                                light_max, KU, KL, flags_l.as<int64_t>(), flags_h.as<int64_t>(),
+                                                light_max, g->glight.bytes ? g->glight.as<int32_t>() : nullptr,
+                                                g->gid[0].as<int32_t>(), g->gid[1].as<int32_t>(), KU, KL,
+                                                flags_l.as<int64_t>(), flags_h.as<int64_t>(),
                                                 sums);
     BFC_LAUNCH_CHECK();
   }

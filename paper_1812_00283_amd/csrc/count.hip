@@ -69,6 +69,7 @@ struct CountParams {
   int32_t wt_first[2];
   int32_t wt_row[2];
   int32_t vpp;                 // bit x: layer x's starts take Algorithm 3's wedges (ends above the start and the middle)
+  const int4* gtune;           // per graph {dense ratio, window mode, hash window wedges, dense min wedges}, or null
   int32_t nX[2];               // layer sizes (the end of Algorithm 3's end ranges)
 };
 
@@ -741,14 +742,17 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     if (ent.x < 0) break;
     uint32_t next_ticket = 0;
     if (t == 0) next_ticket = atomicAdd(p.ticket, 1u);
-    const int32_t code = ent.x;
+    // the entry is the same in every lane: keep it (and what derives from
+    // it) in scalar registers
+    const int32_t code = __builtin_amdgcn_readfirstlane(ent.x);
     const int x = (int)((uint32_t)code >> 30);
     const int32_t r = code & ((1 << 30) - 1);
     const SideView S = pick(p, x);
     const SideView O = pick(p, 1 - x);
-    const int32_t base = ent.y;
-    const int32_t pre = ent.z;
-    const int64_t W = ent.w < 0x7FFFFFFF ? (int64_t)ent.w : S.work[r];
+    const int32_t base = __builtin_amdgcn_readfirstlane(ent.y);
+    const int32_t pre = __builtin_amdgcn_readfirstlane(ent.z);
+    const int32_t ew = __builtin_amdgcn_readfirstlane(ent.w);
+    const int64_t W = ew < 0x7FFFFFFF ? (int64_t)ew : S.work[r];
     const bool vpp = kVpp && ((p.vpp >> x) & 1);
     const int32_t lo_r = vpp ? S.lo[r] : 0;
     // End ranks lie in [elo, ehi): below the start under Algorithm 2, above
@@ -756,7 +760,17 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     // graph's vertices contiguously).  elo is rounded down to even because
     // dense counters pair ranks (rank r itself is never an end).
     const int32_t* grank = x ? p.grank[1] : p.grank[0];
-    const int32_t gi = grank ? graph_index(p, x, r) : 0;
+    const int32_t gi = (grank || p.gtune) ? graph_index(p, x, r) : 0;
+    // window settings: the handle's, or this start's graph's in a tuned batch
+    int32_t window_mode = p.window_mode, dense_ratio = p.dense_ratio;
+    int32_t hash_window_wedges = p.hash_window_wedges, dense_min_wedges = p.dense_min_wedges;
+    if (p.gtune) {
+      const int4 gt = p.gtune[gi];
+      dense_ratio = gt.x;
+      window_mode = gt.y;
+      hash_window_wedges = gt.z;
+      dense_min_wedges = gt.w;
+    }
     const int32_t elo = vpp ? ((r + 1) & ~1) : (grank ? (grank[gi] & ~1) : 0);
     const int32_t ehi = vpp ? (grank ? grank[gi + 1] : p.nX[x]) : r;
     const int32_t span = ehi - elo;
@@ -771,9 +785,9 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     const bool packable = pre < kPackMaxPre && span < kPackMaxWidth;
     const int64_t psingle = (int64_t)kWords / 8 * 5;
     const bool dense =
-        p.window_mode == 2 ||
-        (p.window_mode == 1 && ((W > p.dense_min_wedges && !(packable && W <= psingle)) ||
-                                W * (int64_t)p.dense_ratio >= (int64_t)span));
+        window_mode == 2 ||
+        (window_mode == 1 && ((W > dense_min_wedges && !(packable && W <= psingle)) ||
+                              W * (int64_t)dense_ratio >= (int64_t)span));
     const bool half = pre < 65536;
     // Starts in the dense block: the last window covers the block's end ranks
     // [top, r); its counters start from the MFMA products and its first pass
@@ -790,7 +804,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
       const int32_t base_lo = S.off[elo];
       const int32_t base_hi = vpp ? S.off[ehi] : base;  // (Algorithm 2: ehi = r)
       hash_end = elo;
-      if (p.window_mode == 1 && base_hi > base_lo) {
+      if (window_mode == 1 && base_hi > base_lo) {
         // Sparse prefix of a dense start: the ends of its wedges are
         // neighbours of its middles, which in a degree-driven graph fall on
         // the start layer's vertices in proportion to their degree, so about
@@ -803,7 +817,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         const int32_t step = (step0 + 2 * kWords - 1) / (2 * kWords) * (2 * kWords);
         const int64_t xl = elo + (int64_t)(lane + 1) * step;
         const bool ok = xl < sparse_end && (double)W * (double)(S.off[xl] - base_lo) <=
-                                               (double)p.hash_window_wedges * (double)(base_hi - base_lo);
+                                               (double)hash_window_wedges * (double)(base_hi - base_lo);
         hash_end = elo + __popcll(__ballot(ok)) * step;
         hwidth = hash_end - elo;
       }
@@ -815,7 +829,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         cap = 512;
         while (cap < cmax && (int64_t)cap < 2 * W) cap <<= 1;
       } else {
-        const int64_t wd = (int64_t)span * p.hash_window_wedges / W;
+        const int64_t wd = (int64_t)span * hash_window_wedges / W;
         hwidth = (int32_t)(wd < 256 ? 256 : (wd > span ? span : wd));
         cap = cmax;
       }
@@ -1645,6 +1659,11 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   p.window_mode = g->tune.window_mode;
   p.hash_window_wedges = g->tune.hash_window_wedges;
   p.dense_min_wedges = g->tune.dense_min_wedges;
+  if (g->gtune.bytes && g->gid[0].bytes) {
+    p.gtune = g->gtune.as<int4>();
+    p.gid[0] = g->gid[0].as<int32_t>();
+    p.gid[1] = g->gid[1].as<int32_t>();
+  }
   p.vpp = sc.vpp;
   p.nX[0] = g->side[0].n;
   p.nX[1] = g->side[1].n;

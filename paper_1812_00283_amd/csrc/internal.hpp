@@ -211,6 +211,10 @@ struct bfc_graph_s {
     return a * b < (uint64_t(1) << 32);
   }
   std::vector<int64_t> graph_wedges;
+  // per-graph settings of a batch (bfc_set_graph_tuning): light_max per
+  // graph (int32 [G]) and {dense ratio, window mode, hash window wedges,
+  // dense min wedges} per graph (int4 [G]); empty when not set
+  bfc::DevBuf glight, gtune;
   // captured total count
   hipGraph_t cap_graph = nullptr;
   hipGraphExec_t cap_exec = nullptr;

@@ -84,6 +84,59 @@ def test_small_batch_vpp(gpu_lib):
                 ol += g.n_lower
 
 
+def test_per_graph_tuning(gpu_lib):
+    """Per-graph settings (what the tuner installs per bucket): every output
+    unchanged, through a captured and replayed count too."""
+    graphs = small_batch(48, seed=14)
+    b = gg.concat(graphs)
+    rng = np.random.default_rng(15)
+    per = []
+    for i in range(len(graphs)):
+        per.append({"light_max_wedges": int(rng.choice([1, 16, 256, 2048])),
+                    "window_mode": int(rng.choice([1, 2, 3])),
+                    "hash_window_wedges": int(rng.choice([16, 512, 8192])),
+                    "dense_min_ratio": int(rng.choice([1, 4, 64])),
+                    "dense_min_wedges": int(rng.choice([64, 8192]))})
+    expect = np.array([oracle.total(g) for g in graphs], np.int64)
+    s = torch.cuda.Stream()
+    with gpu_lib.build_batch(torch.from_numpy(b.edges).cuda(), b.offsets, b.n_upper, b.n_lower, stream=s) as h:
+        h.set_graph_tuning(per)
+        tot = h.count_total_batch(stream=s)
+        s.synchronize()
+        assert (tot.cpu().numpy() == expect).all()
+        up, lo = h.count_per_vertex(stream=s)
+        be = h.count_per_edge(stream=s)
+        up, lo, be = up.cpu().numpy(), lo.cpu().numpy(), be.cpu().numpy()
+        ou = ol = 0
+        for i, g in enumerate(graphs):
+            o_up, o_lo = oracle.vertex_counts(g)
+            np.testing.assert_array_equal(up[ou:ou + g.n_upper], o_up)
+            np.testing.assert_array_equal(lo[ol:ol + g.n_lower], o_lo)
+            np.testing.assert_array_equal(be[b.offsets[i]:b.offsets[i + 1]], oracle.edge_counts(g))
+            ou += g.n_upper
+            ol += g.n_lower
+        out = torch.zeros(len(graphs), dtype=torch.int64, device="cuda")
+        h.capture_total(out, stream=s)
+        for _ in range(3):
+            out.fill_(-1)
+            torch.cuda.synchronize()
+            h.replay(stream=s)
+            torch.cuda.synchronize()
+            assert (out.cpu().numpy() == expect).all()
+        h.set_graph_tuning([])  # back to the handle's settings
+        tot = h.count_total_batch(stream=s)
+        s.synchronize()
+        assert (tot.cpu().numpy() == expect).all()
+        with pytest.raises(gpu_lib.BfcError) as err:
+            h.set_graph_tuning(per[:-1])
+        assert err.value.status == 1
+    g = graphs[2]
+    with gpu_lib.Graph(torch.from_numpy(g.edges).cuda(), g.n_upper, g.n_lower) as h1:
+        with pytest.raises(gpu_lib.BfcError) as err:
+            h1.set_graph_tuning([{}])
+        assert err.value.status == 1
+
+
 def test_batch_errors(gpu_lib):
     e = torch.tensor([[0, 0], [1, 1], [2, 0]], dtype=torch.int32, device="cuda")
     with pytest.raises(gpu_lib.BfcError) as err:   # edge 2 is outside graph 1's upper layer
