@@ -30,17 +30,19 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 DEFAULT_WORKLOAD = "chunglu-1m-500k-20m"
 
 # HBM traffic of one heavy-kernel launch on the default workload, from
-# rocprofv3 --pmc FETCH_SIZE and, in a separate run, WRITE_SIZE (KiB per
-# dispatch, mean of 3 dispatches), each scaled by what the same counter reads
-# for a plain 1 GiB device-to-device copy (FETCH_SIZE reads 512 MiB: x2.0;
-# WRITE_SIZE reads 1 GiB: x1.0).  Reported only while the library sources
-# hash to the value they were measured with (any change voids the figure).
+# rocprofv3 --pmc runs (mean of 3 dispatches): TCC_EA0_RDREQ_sum read
+# requests (none of them 32-byte requests, TCC_BUBBLE_sum about 30), each
+# 128 bytes -- a plain 1 GiB device-to-device copy issues 8,388,792 such
+# requests, and FETCH_SIZE counts them as 64 bytes, hence its factor 2 --
+# and, in a separate run, WRITE_SIZE (KiB, factor 1.0 on the same copy).
+# Reported only while the heavy kernel's sources hash to the value they were
+# measured with (any change voids the figure).
 HEAVY_TRAFFIC = {
     "workload": DEFAULT_WORKLOAD,
-    "sources_sha256": "ee2bc77abb89dff7504f7fd41b40b41508f3b5a72a09a2acf2c77b8dc76cc3e9",
-    "fetch_kib": 17075036.9,
-    "write_kib": 885903.2,
-    "fetch_factor": 2.0,
+    "sources_sha256": "7a98f2f4e0e1def5fd5deb1074a6a901abacdc275c405ad46542e86d7aea612d",
+    "read_requests": 270466575.7,
+    "bytes_per_read_request": 128.0,
+    "write_kib": 892015.0,
     "write_factor": 1.0,
 }
 
@@ -76,7 +78,7 @@ def heavy_traffic(workload: str, tuned: bool):
     t = HEAVY_TRAFFIC
     if tuned or workload != t["workload"] or sources_sha256() != t["sources_sha256"]:
         return None
-    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+    return t["read_requests"] * t["bytes_per_read_request"] + 1024.0 * t["write_kib"] * t["write_factor"]
 
 
 def golden_caterpillars(name: str):
@@ -397,6 +399,27 @@ def bench_serve(args) -> int:
         log(f"{name}: p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms, {st['requests_per_s']:.1f} req/s")
     assert out["batched"][1] == out["plain"][1], "served results differ between the mix and the plain server"
     bst, pst = out["batched"][0], out["plain"][0]
+    # the oracle's answers for the checked requests (every request of at most
+    # 1e6 edges and a seeded 2% of the larger ones), stored by
+    # tests/golden/make_serve_golden.py
+    oracle_check = None
+    gold = os.path.join(ROOT, "tests", "golden", "serve_10s.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            grec = json.load(f)
+        if (grec["trace"]["duration_s"] == args.serve_seconds and args.serve_max_edges == 50_000_000):
+            results = {r.index: res for r, res in zip(reqs, out["batched"][1])}
+            bad = []
+            for k, v in grec["answers"].items():
+                got = results[int(k)]
+                got = list(got) if isinstance(got, tuple) else got
+                if got != v:
+                    bad.append(int(k))
+            oracle_check = {"checked": len(grec["answers"]), "of_requests": len(reqs), "mismatches": len(bad),
+                            "first_mismatches": bad[:10],
+                            "rule": "every request with m <= 1e6 and a seeded 2% of the larger ones"}
+            log(f"oracle check: {oracle_check['checked']} requests, {len(bad)} mismatches")
+            assert not bad, f"served results differ from the oracle for requests {bad[:10]}"
     print(json.dumps({
         "metric": "served p99 latency", "value": bst["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": 1,
         "warmup": 0, "ms_per_step": 1e3 * bst["wall_s"], "higher_is_better": False, "scaling": "weak",
@@ -405,7 +428,11 @@ def bench_serve(args) -> int:
                    "offered_requests_per_s": len(reqs) / args.serve_seconds,
                    "offered_edges_per_s": offered_edges / args.serve_seconds, "budget_gb": budget / (1 << 30),
                    "max_edges_per_request": args.serve_max_edges},
-        "batched": bst, "plain": pst, "results_identical": True,
+        "batched": bst, "plain": pst, "results_identical": True, "oracle_check": oracle_check,
+        "offered_vs_achieved": {"offered_requests_per_s": len(reqs) / args.serve_seconds,
+                                "achieved_requests_per_s": bst["requests_per_s"],
+                                "offered_edges_per_s": offered_edges / args.serve_seconds,
+                                "achieved_edges_per_s": bst["edges_per_s"]},
     }), flush=True)
     return 0
 
@@ -517,7 +544,7 @@ def main() -> int:
                     help="only run a plain device-to-device copy of this many MiB (calibrates HBM counters)")
     ap.add_argument("--tuning", default="", help='JSON dict of bfc_set_tuning fields, e.g. {"window_mode": 3}')
     ap.add_argument("--graphs", type=int, default=4096, help="graphs in the batched workload")
-    ap.add_argument("--serve-seconds", type=float, default=1.0, help="prefix of the arrival trace to serve")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="prefix of the arrival trace to serve")
     ap.add_argument("--serve-max-edges", type=int, default=50_000_000)
     ap.add_argument("--serve-budget-gb", type=float, default=0.0)
     ap.add_argument("--k", type=int, default=10000, help="threshold of the k-wing workload")
@@ -687,7 +714,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_unit": "bytes per launch (rocprofv3 TCC_EA0_RDREQ x 128 B + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": hk_bytes,
             "avg_launch_ms": hk_ms,
             "copy_measured": None if args.steps_only else measured_copy_gbs(),
