@@ -752,27 +752,33 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     const int32_t base = __builtin_amdgcn_readfirstlane(ent.y);
     const int32_t pre = __builtin_amdgcn_readfirstlane(ent.z);
     const int32_t ew = __builtin_amdgcn_readfirstlane(ent.w);
-    const int64_t W = ew < 0x7FFFFFFF ? (int64_t)ew : S.work[r];
+    int64_t W = ew;
+    if (ew == 0x7FFFFFFF) {
+      const int64_t w = S.work[r];
+      W = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(w >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)w));
+    }
     const bool vpp = kVpp && ((p.vpp >> x) & 1);
-    const int32_t lo_r = vpp ? S.lo[r] : 0;
+    const int32_t lo_r = vpp ? __builtin_amdgcn_readfirstlane(S.lo[r]) : 0;
     // End ranks lie in [elo, ehi): below the start under Algorithm 2, above
     // it under Algorithm 3, within the start's graph (a batch ranks each
     // graph's vertices contiguously).  elo is rounded down to even because
     // dense counters pair ranks (rank r itself is never an end).
     const int32_t* grank = x ? p.grank[1] : p.grank[0];
-    const int32_t gi = (grank || p.gtune) ? graph_index(p, x, r) : 0;
+    const int32_t gi = (grank || p.gtune) ? __builtin_amdgcn_readfirstlane(graph_index(p, x, r)) : 0;
     // window settings: the handle's, or this start's graph's in a tuned batch
+    // (uniform: scalar registers)
     int32_t window_mode = p.window_mode, dense_ratio = p.dense_ratio;
     int32_t hash_window_wedges = p.hash_window_wedges, dense_min_wedges = p.dense_min_wedges;
     if (p.gtune) {
       const int4 gt = p.gtune[gi];
-      dense_ratio = gt.x;
-      window_mode = gt.y;
-      hash_window_wedges = gt.z;
-      dense_min_wedges = gt.w;
+      dense_ratio = __builtin_amdgcn_readfirstlane(gt.x);
+      window_mode = __builtin_amdgcn_readfirstlane(gt.y);
+      hash_window_wedges = __builtin_amdgcn_readfirstlane(gt.z);
+      dense_min_wedges = __builtin_amdgcn_readfirstlane(gt.w);
     }
-    const int32_t elo = vpp ? ((r + 1) & ~1) : (grank ? (grank[gi] & ~1) : 0);
-    const int32_t ehi = vpp ? (grank ? grank[gi + 1] : p.nX[x]) : r;
+    const int32_t elo = vpp ? ((r + 1) & ~1) : (grank ? (__builtin_amdgcn_readfirstlane(grank[gi]) & ~1) : 0);
+    const int32_t ehi = vpp ? (grank ? __builtin_amdgcn_readfirstlane(grank[gi + 1]) : (x ? p.nX[1] : p.nX[0])) : r;
     const int32_t span = ehi - elo;
     // middles of rank >= tfirst find their window slices in the table and
     // keep no cursor
@@ -801,8 +807,8 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     int32_t hwidth = 0, hash_end = 0;
     uint32_t cap = kCap;
     if (dense) {
-      const int32_t base_lo = S.off[elo];
-      const int32_t base_hi = vpp ? S.off[ehi] : base;  // (Algorithm 2: ehi = r)
+      const int32_t base_lo = __builtin_amdgcn_readfirstlane(S.off[elo]);
+      const int32_t base_hi = vpp ? __builtin_amdgcn_readfirstlane(S.off[ehi]) : base;  // (Algorithm 2: ehi = r)
       hash_end = elo;
       if (window_mode == 1 && base_hi > base_lo) {
         // Sparse prefix of a dense start: the ends of its wedges are
