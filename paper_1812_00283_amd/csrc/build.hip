@@ -73,19 +73,22 @@ __global__ __launch_bounds__(kDegNT) void degree_kernel(const int32_t* __restric
 }
 
 // Degrees by partition (no global atomics per endpoint): ids are grouped
-// into buckets of 2^kBucketShift consecutive ids -- bucket totals per tile,
-// a scatter of each id into its bucket's region (order inside a bucket is
-// irrelevant), then one workgroup per bucket counts its ids in LDS.  Both
-// layers at once; used while each layer has at most kMaxBuckets buckets.
+// into buckets of 2^shift consecutive ids -- bucket totals per tile, a
+// scatter of each id into its bucket's region (order inside a bucket is
+// irrelevant), then kDegSplit workgroups per bucket count its ids in LDS.
+// Both layers at once.  The bucket width is the smallest of 2^13 .. 2^14
+// ids that leaves each layer at most kMaxBuckets buckets (layers up to
+// 2^26 ids: batches of thousands of graphs have tens of millions); wider
+// layers fall back to one atomic per endpoint.
 constexpr int kPartNT = 512;
 constexpr int64_t kPartTile = 16384;  // edges per workgroup
-constexpr int kBucketShift = 13;
-constexpr int kBucketIds = 1 << kBucketShift;
+constexpr int kMinBucketShift = 13;
+constexpr int kMaxBucketShift = 14;  // 64 KB of dynamic LDS in part_degree_kernel
 constexpr int kMaxBuckets = 4096;
 
 __global__ __launch_bounds__(kPartNT) void part_count_kernel(const int32_t* __restrict__ edges, int64_t m,
                                                              int32_t nU, int32_t nL, int32_t BU, int32_t BL,
-                                                             uint32_t* __restrict__ cnt,
+                                                             int shift, uint32_t* __restrict__ cnt,
                                                              int32_t* __restrict__ status) {
   __shared__ uint32_t h[2 * kMaxBuckets];
   const int nb = BU + BL;
@@ -99,8 +102,8 @@ __global__ __launch_bounds__(kPartNT) void part_count_kernel(const int32_t* __re
       atomicOr(&status[0], 1);
       continue;
     }
-    atomicAdd(&h[e.x >> kBucketShift], 1u);
-    atomicAdd(&h[BU + (e.y >> kBucketShift)], 1u);
+    atomicAdd(&h[e.x >> shift], 1u);
+    atomicAdd(&h[BU + (e.y >> shift)], 1u);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nb; i += kPartNT)
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(kPartNT) void part_count_kernel(const int32_t* __re
 
 __global__ __launch_bounds__(kPartNT) void part_scatter_kernel(const int32_t* __restrict__ edges, int64_t m,
                                                                int32_t nU, int32_t nL, int32_t BU, int32_t BL,
-                                                               const uint32_t* __restrict__ off,
+                                                               int shift, const uint32_t* __restrict__ off,
                                                                uint32_t* __restrict__ fill,
                                                                int32_t* __restrict__ part) {
   __shared__ uint32_t h[2 * kMaxBuckets];
@@ -122,8 +125,8 @@ __global__ __launch_bounds__(kPartNT) void part_scatter_kernel(const int32_t* __
   for (int64_t i = e0 + threadIdx.x; i < e1; i += kPartNT) {
     const int2 e = reinterpret_cast<const int2*>(edges)[i];
     if (e.x < 0 || e.x >= nU || e.y < 0 || e.y >= nL) continue;
-    atomicAdd(&h[e.x >> kBucketShift], 1u);
-    atomicAdd(&h[BU + (e.y >> kBucketShift)], 1u);
+    atomicAdd(&h[e.x >> shift], 1u);
+    atomicAdd(&h[BU + (e.y >> shift)], 1u);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nb; i += kPartNT) {
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(kPartNT) void part_scatter_kernel(const int32_t* __
   for (int64_t i = e0 + threadIdx.x; i < e1; i += kPartNT) {
     const int2 e = reinterpret_cast<const int2*>(edges)[i];
     if (e.x < 0 || e.x >= nU || e.y < 0 || e.y >= nL) continue;
-    const int bu = e.x >> kBucketShift, bl = BU + (e.y >> kBucketShift);
+    const int bu = e.x >> shift, bl = BU + (e.y >> shift);
     part[base[bu] + atomicAdd(&h[bu], 1u)] = e.x;
     part[base[bl] + atomicAdd(&h[bl], 1u)] = e.y;
   }
@@ -143,17 +146,20 @@ __global__ __launch_bounds__(kPartNT) void part_scatter_kernel(const int32_t* __
 // kDegSplit workgroups share a bucket: each counts a slice of its ids in
 // LDS and adds its non-zero counts to the (zeroed) degrees.
 constexpr int kDegSplit = 8;
+// (dynamic LDS: 4 bytes per id of a bucket)
 __global__ __launch_bounds__(kPartNT) void part_degree_kernel(const int32_t* __restrict__ part,
                                                               const uint32_t* __restrict__ off, int32_t BU,
-                                                              int32_t nU, int32_t nL, int32_t* __restrict__ degU,
+                                                              int32_t nU, int32_t nL, int shift,
+                                                              int32_t* __restrict__ degU,
                                                               int32_t* __restrict__ degL) {
-  __shared__ uint32_t h[kBucketIds];
+  extern __shared__ uint32_t h[];
+  const int32_t bucket_ids = 1 << shift;
   const int b = blockIdx.x / kDegSplit;
   const int sp = blockIdx.x % kDegSplit;
   const bool lower = b >= BU;
-  const int32_t id0 = (lower ? b - BU : b) << kBucketShift;
+  const int32_t id0 = (lower ? b - BU : b) << shift;
   const int32_t n = lower ? nL : nU;
-  const int32_t w = n - id0 < kBucketIds ? n - id0 : kBucketIds;
+  const int32_t w = n - id0 < bucket_ids ? n - id0 : bucket_ids;
   for (int i = threadIdx.x; i < w; i += kPartNT) h[i] = 0;
   __syncthreads();
   const uint32_t a0 = off[b], len = off[b + 1] - a0;
@@ -440,7 +446,11 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
     deg[x].alloc(sizeof(int32_t) * (size_t)(n[x] + 1), s);
     BFC_HIP(hipMemsetAsync(deg[x].p, 0, sizeof(int32_t) * (size_t)(n[x] + 1), s));
   }
-  const int32_t BU = (n[0] + kBucketIds - 1) >> kBucketShift, BL = (n[1] + kBucketIds - 1) >> kBucketShift;
+  int shift = kMinBucketShift;
+  while (shift < kMaxBucketShift && (((int64_t)(n[0] > n[1] ? n[0] : n[1]) + (1 << shift) - 1) >> shift) > kMaxBuckets)
+    ++shift;
+  const int32_t BU = (int32_t)(((int64_t)n[0] + (1 << shift) - 1) >> shift);
+  const int32_t BL = (int32_t)(((int64_t)n[1] + (1 << shift) - 1) >> shift);
   if (m > 0 && BU <= kMaxBuckets && BL <= kMaxBuckets) {
     const int nb = BU + BL;
     TmpBuf cnt, fill, part;
@@ -450,15 +460,16 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
     BFC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * (size_t)(nb + 1), s));
     BFC_HIP(hipMemsetAsync(fill.p, 0, sizeof(uint32_t) * (size_t)nb, s));
     const unsigned tiles = (unsigned)((m + kPartTile - 1) / kPartTile);
-    part_count_kernel<<<tiles, kPartNT, 0, s>>>(edges, m, n[0], n[1], BU, BL, cnt.as<uint32_t>(),
+    part_count_kernel<<<tiles, kPartNT, 0, s>>>(edges, m, n[0], n[1], BU, BL, shift, cnt.as<uint32_t>(),
                                                 status.as<int32_t>());
     BFC_LAUNCH_CHECK();
     exclusive_scan_u32(cnt.as<uint32_t>(), cnt.as<uint32_t>(), nb + 1, s);
-    part_scatter_kernel<<<tiles, kPartNT, 0, s>>>(edges, m, n[0], n[1], BU, BL, cnt.as<uint32_t>(),
+    part_scatter_kernel<<<tiles, kPartNT, 0, s>>>(edges, m, n[0], n[1], BU, BL, shift, cnt.as<uint32_t>(),
                                                   fill.as<uint32_t>(), part.as<int32_t>());
     BFC_LAUNCH_CHECK();
     if (nb > 0) {
-      part_degree_kernel<<<(unsigned)nb * kDegSplit, kPartNT, 0, s>>>(part.as<int32_t>(), cnt.as<uint32_t>(), BU, n[0], n[1],
+      part_degree_kernel<<<(unsigned)nb * kDegSplit, kPartNT, sizeof(uint32_t) << shift, s>>>(
+          part.as<int32_t>(), cnt.as<uint32_t>(), BU, n[0], n[1], shift,
                                                           deg[0].as<int32_t>(), deg[1].as<int32_t>());
       BFC_LAUNCH_CHECK();
     }
