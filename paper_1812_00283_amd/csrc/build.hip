@@ -936,11 +936,24 @@ void finish_schedule(bfc_graph_s* g, hipStream_t s) {
 // ---------------------------------------------------------------- batches
 namespace {
 
-__global__ void shift_kernel(const int32_t* __restrict__ edges, int64_t m, const int64_t* __restrict__ eoff,
-                             int32_t G, const int32_t* __restrict__ uoff, const int32_t* __restrict__ loff,
-                             int32_t* __restrict__ out, int32_t* __restrict__ status) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t gi = graph_of<int64_t>(eoff, G, i);
+// Edges come grouped by graph, so a tile of consecutive edges spans few
+// graphs: one binary search finds the tile's first graph, and each edge
+// steps forward from it (usually not at all).
+constexpr int kShiftNT = 256;
+constexpr int kShiftTile = 4 * kShiftNT;
+__global__ __launch_bounds__(kShiftNT) void shift_kernel(const int32_t* __restrict__ edges, int64_t m,
+                                                         const int64_t* __restrict__ eoff, int32_t G,
+                                                         const int32_t* __restrict__ uoff,
+                                                         const int32_t* __restrict__ loff, int32_t* __restrict__ out,
+                                                         int32_t* __restrict__ status) {
+  __shared__ int32_t s_g0;
+  const int64_t t0 = (int64_t)blockIdx.x * kShiftTile;
+  if (threadIdx.x == 0) s_g0 = graph_of<int64_t>(eoff, G, t0);
+  __syncthreads();
+  const int32_t g0 = s_g0;
+  for (int64_t i = t0 + threadIdx.x; i < m && i < t0 + kShiftTile; i += kShiftNT) {
+    int32_t gi = g0;
+    while (gi + 1 < G && eoff[gi + 1] <= i) ++gi;
     const int2 e = reinterpret_cast<const int2*>(edges)[i];
     const int32_t nu = uoff[gi + 1] - uoff[gi];
     const int32_t nl = loff[gi + 1] - loff[gi];
@@ -957,14 +970,36 @@ __global__ void shift_kernel(const int32_t* __restrict__ edges, int64_t m, const
   }
 }
 
-__global__ void gid_kernel(const int32_t* __restrict__ id_of, int32_t n, const int32_t* __restrict__ voff, int32_t G,
-                           int32_t* __restrict__ gid, const int64_t* __restrict__ work,
-                           unsigned long long* __restrict__ gw) {
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t gi = graph_of<int32_t>(voff, G, id_of[r]);
-    gid[r] = gi;
-    const int64_t w = work[r];
-    if (w) atomicAdd(&gw[gi], (unsigned long long)w);
+// Graph of every rank (a graph's ranks are contiguous, [voff[g], voff[g+1]),
+// as its ids are) and per-graph wedge sums: per wavefront, each run of
+// lanes in one graph adds its sum with one atomic.
+__global__ void gid_kernel(int32_t n, const int32_t* __restrict__ voff, int32_t G, int32_t* __restrict__ gid,
+                           const int64_t* __restrict__ work, unsigned long long* __restrict__ gw) {
+  const int lane = __lane_id();
+  for (int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~63ll; b < n;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = b + lane;
+    int32_t gi = -1;
+    unsigned long long w = 0;
+    if (r < n) {
+      gi = graph_of<int32_t>(voff, G, (int32_t)r);
+      gid[r] = gi;
+      w = (unsigned long long)work[r];
+    }
+    // runs of equal graph over the lanes: the last lane of a run adds the run's sum
+    const int32_t g_prev = __shfl_up(gi, 1, 64);
+    const int32_t g_next = __shfl_down(gi, 1, 64);
+    const bool head = lane == 0 || g_prev != gi;
+    const bool tail = lane == 63 || g_next != gi;
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = lane == 63 ? heads : heads & ((2ull << lane) - 1ull);
+    const int s0 = 63 - (int)__builtin_clzll(upto);
+    const unsigned long long inc = wave_inclusive_scan(w);
+    const unsigned long long before = __shfl(inc, s0 > 0 ? s0 - 1 : 0, 64);
+    if (tail && gi >= 0) {
+      const unsigned long long run = inc - (s0 > 0 ? before : 0ull);
+      if (run) atomicAdd(&gw[gi], run);
+    }
   }
 }
 
@@ -1001,8 +1036,9 @@ void build_batch(bfc_graph_s* g, const int32_t* edges, const int64_t* eoff_host,
   BFC_HIP(hipMemcpyAsync(d_loff.p, loff.data(), sizeof(int32_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
   BFC_HIP(hipMemsetAsync(status.p, 0, 4 * sizeof(int32_t), s));
   if (m > 0) {
-    shift_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, d_eoff.as<int64_t>(), G, d_uoff.as<int32_t>(),
-                                             d_loff.as<int32_t>(), shifted.as<int32_t>(), status.as<int32_t>());
+    shift_kernel<<<(unsigned)((m + kShiftTile - 1) / kShiftTile), kShiftNT, 0, s>>>(
+        edges, m, d_eoff.as<int64_t>(), G, d_uoff.as<int32_t>(), d_loff.as<int32_t>(), shifted.as<int32_t>(),
+        status.as<int32_t>());
     BFC_LAUNCH_CHECK();
   }
   int32_t st[4] = {0, 0, 0, 0};
@@ -1024,9 +1060,8 @@ void build_batch(bfc_graph_s* g, const int32_t* edges, const int64_t* eoff_host,
     Side& sd = g->side[x];
     g->gid[x].alloc(sizeof(int32_t) * (size_t)sd.n, s);
     if (sd.n > 0) {
-      gid_kernel<<<grid_1d(sd.n), 256, 0, s>>>(sd.id_of.as<int32_t>(), sd.n, voff[x]->as<int32_t>(), G,
-                                                g->gid[x].as<int32_t>(), sd.work.as<int64_t>(),
-                                                gw.as<unsigned long long>());
+      gid_kernel<<<grid_1d(sd.n), 256, 0, s>>>(sd.n, voff[x]->as<int32_t>(), G, g->gid[x].as<int32_t>(),
+                                                sd.work.as<int64_t>(), gw.as<unsigned long long>());
       BFC_LAUNCH_CHECK();
     }
   }
