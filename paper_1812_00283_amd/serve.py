@@ -42,7 +42,7 @@ class Job:
     index: int
     kind: str                 # "total" | "vertex" | "edge"
     key: int                  # graph identity (requests with the same key share a graph)
-    edges: np.ndarray         # int32 [m, 2] host edge list
+    edges: object             # int32 [m, 2] host edge list: numpy array, or a pinned CPU tensor (copied asynchronously)
     n_upper: int
     n_lower: int
     arrival: float = 0.0      # monotonic seconds when submitted
@@ -66,6 +66,15 @@ def digest(*arrays: torch.Tensor) -> tuple[str, int]:
         h.update(x.tobytes())
         total += int(x.sum())
     return h.hexdigest(), total
+
+
+def _host_tensor(edges) -> torch.Tensor:
+    """A request's edge list as a CPU tensor: pinned tensors are copied to the
+    device asynchronously on the worker's stream (DMA, no staging); numpy
+    arrays go through a pageable copy."""
+    if isinstance(edges, torch.Tensor):
+        return edges
+    return torch.from_numpy(np.ascontiguousarray(edges))
 
 
 def out_bytes(m: int, nu: int, nl: int, kind: str) -> int:
@@ -295,10 +304,12 @@ class Server:
             self.completed.append(jb)
             return
         if kind == "batch":
-            edges = np.concatenate([jb.edges for jb in jobs]) if jobs else np.zeros((0, 2), np.int32)
             offs = np.zeros(len(jobs) + 1, np.int64)
             offs[1:] = np.cumsum([jb.m for jb in jobs])
-            dev = torch.from_numpy(np.ascontiguousarray(edges)).to("cuda", non_blocking=False)
+            dev = torch.empty((int(offs[-1]), 2), dtype=torch.int32, device="cuda")
+            for jb, o in zip(jobs, offs):
+                if jb.m:
+                    dev[int(o):int(o) + jb.m].copy_(_host_tensor(jb.edges), non_blocking=True)
             with bfc.build_batch(dev, offs, [jb.n_upper for jb in jobs], [jb.n_lower for jb in jobs], stream) as g:
                 totals = g.count_total_batch(stream=stream).cpu().numpy()
             now = time.monotonic()
@@ -308,7 +319,7 @@ class Server:
                 self.completed.append(jb)
             return
         jb = jobs[0]
-        dev = torch.from_numpy(np.ascontiguousarray(jb.edges)).to("cuda", non_blocking=False)
+        dev = _host_tensor(jb.edges).to("cuda", non_blocking=True)
         g = bfc.Graph(dev, jb.n_upper, jb.n_lower, stream)
         del dev
         try:
