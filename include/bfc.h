@@ -334,6 +334,23 @@ int64_t bfc_cached_bytes(void);
  *                      the chosen wedges.  With vpp != 0 the dense block and
  *                      the 256-thread shape are not used (dense_block and
  *                      medium_max_wedges are kept but ignored).
+ *   top_band           width T of each layer's top band of priority ranks
+ *                      (< 0 keeps; 0, the default, disables; ignored for a
+ *                      layer in vpp, a layer of at most T vertices and a
+ *                      batch handle).  A pair of same-layer vertices is
+ *                      counted once, from one of its two vertices (Theorem
+ *                      1): from the higher one with Algorithm 2's wedges
+ *                      when both lie in the band or both below it, and from
+ *                      the lower one with Algorithm 3's wedges (Section 5)
+ *                      when only the higher one lies in the band.  The two
+ *                      walks see the same wedges of the pair, so the counts
+ *                      and |W| are those of Algorithm 2 alone.  Every end
+ *                      range then lies inside one part: band starts and the
+ *                      band wedges of lower starts end within the T top
+ *                      ranks (one dense LDS window when T <= 65536).  A start
+ *                      below the band becomes two list items (its own part,
+ *                      then the band); the dense block and the 256-thread
+ *                      shape are not used while a band is set.
  */
 typedef struct {
   int32_t light_max_wedges;
@@ -344,6 +361,7 @@ typedef struct {
   int32_t dense_min_wedges;
   int32_t medium_max_wedges;
   int32_t vpp;
+  int32_t top_band;
 } bfc_tuning;
 
 bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t);

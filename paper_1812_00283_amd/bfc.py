@@ -53,7 +53,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("light_max_wedges", ctypes.c_int32), ("dense_min_ratio", ctypes.c_int32),
                 ("window_mode", ctypes.c_int32), ("hash_window_wedges", ctypes.c_int32),
                 ("dense_block", ctypes.c_int32), ("dense_min_wedges", ctypes.c_int32),
-                ("medium_max_wedges", ctypes.c_int32), ("vpp", ctypes.c_int32)]
+                ("medium_max_wedges", ctypes.c_int32), ("vpp", ctypes.c_int32),
+                ("top_band", ctypes.c_int32)]
 
 
 class ScheduleInfo(ctypes.Structure):
@@ -321,12 +322,13 @@ class Graph:
 
     def set_tuning(self, light_max_wedges: int = 0, dense_min_ratio: int = 0, window_mode: int = 0,
                    hash_window_wedges: int = 0, dense_block: int = -1, dense_min_wedges: int = 0,
-                   medium_max_wedges: int = -1, vpp: int = -1) -> None:
+                   medium_max_wedges: int = -1, vpp: int = -1, top_band: int = -1) -> None:
         """Changes which kernel path handles each start; no count changes.
         window_mode: 1 automatic, 2 dense windows only, 3 hash windows only.
-        vpp: 1 counts Algorithm 3's wedges (BFC-VP++), 0 Algorithm 2's."""
+        vpp: 1 counts Algorithm 3's wedges (BFC-VP++), 0 Algorithm 2's.
+        top_band: width of each layer's top band of ranks (0: none)."""
         t = Tuning(light_max_wedges, dense_min_ratio, window_mode, hash_window_wedges, dense_block, dense_min_wedges,
-                   medium_max_wedges, vpp)
+                   medium_max_wedges, vpp, top_band)
         _check(load().bfc_set_tuning(self._h, ctypes.byref(t)))
 
     def set_graph_tuning(self, per_graph) -> None:
@@ -340,7 +342,7 @@ class Graph:
         arr = (Tuning * len(per_graph))()
         for i, d in enumerate(per_graph):
             for f in fields:
-                setattr(arr[i], f, int(d.get(f, -1 if f in ("dense_block", "medium_max_wedges", "vpp") else 0)))
+                setattr(arr[i], f, int(d.get(f, -1 if f in ("dense_block", "medium_max_wedges", "vpp", "top_band") else 0)))
         _check(load().bfc_set_graph_tuning(self._h, ctypes.cast(arr, ctypes.c_void_p), len(per_graph)))
 
     def get_tuning(self) -> dict:
@@ -349,7 +351,7 @@ class Graph:
         return {"light_max_wedges": t.light_max_wedges, "dense_min_ratio": t.dense_min_ratio,
                 "window_mode": t.window_mode, "hash_window_wedges": t.hash_window_wedges,
                 "dense_block": t.dense_block, "dense_min_wedges": t.dense_min_wedges,
-                "medium_max_wedges": t.medium_max_wedges, "vpp": t.vpp}
+                "medium_max_wedges": t.medium_max_wedges, "vpp": t.vpp, "top_band": t.top_band}
 
     def schedule_info(self) -> dict:
         si = ScheduleInfo()

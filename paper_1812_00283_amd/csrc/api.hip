@@ -64,7 +64,8 @@ int64_t bfc_graph_s::device_bytes() const {
   int64_t b = 0;
   for (int x = 0; x < 2; ++x) {
     const bfc::Side& s = side[x];
-    b += s.off.bytes + s.adj.bytes + s.rev.bytes + s.lo.bytes + s.id_of.bytes + s.work.bytes + s.wpp.bytes;
+    b += s.off.bytes + s.adj.bytes + s.rev.bytes + s.lo.bytes + s.id_of.bytes + s.work.bytes + s.wpp.bytes +
+         s.band_lb.bytes + s.wband.bytes + s.wtop.bytes;
   }
   b += edge0.bytes + wt[0].bytes + wt[1].bytes + sched.light.bytes + sched.heavy.bytes + scratch.bytes + acc.bytes +
        vacc.bytes;
@@ -463,8 +464,10 @@ bfc_status bfc_set_tuning(bfc_graph g, const bfc_tuning* t) {
     if (t->medium_max_wedges >= 0) nt.medium_max_wedges = t->medium_max_wedges;
     if (t->vpp > 3) throw Error{BFC_ERR_INVALID_ARGUMENT, "vpp must be 0 to 3"};
     if (t->vpp >= 0) nt.vpp = t->vpp;
+    if (t->top_band >= 0) nt.top_band = t->top_band;
     const bool resched = nt.light_max_wedges != h->tune.light_max_wedges || nt.dense_block != h->tune.dense_block ||
-                         nt.medium_max_wedges != h->tune.medium_max_wedges || nt.vpp != h->tune.vpp;
+                         nt.medium_max_wedges != h->tune.medium_max_wedges || nt.vpp != h->tune.vpp ||
+                         nt.top_band != h->tune.top_band;
     h->tune = nt;
     if (resched) {
       if (h->used) BFC_HIP(hipEventSynchronize(h->done));
@@ -627,6 +630,7 @@ bfc_status bfc_get_tuning(bfc_graph g, bfc_tuning* t) {
     t->dense_min_wedges = h->tune.dense_min_wedges;
     t->medium_max_wedges = h->tune.medium_max_wedges;
     t->vpp = h->tune.vpp;
+    t->top_band = h->tune.top_band;
   });
 }
 

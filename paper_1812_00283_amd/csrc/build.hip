@@ -17,6 +17,7 @@
 //   work_X[r]   wedges Algorithm 2 processes from start r: for each middle v
 //               in the prefix, the ends are the entries of N(v) before r,
 //               i.e. rev[k] - off_other[v] of them.
+#include <algorithm>
 #include <vector>
 
 #include "device.hpp"
@@ -434,7 +435,9 @@ __global__ __launch_bounds__(256) void max_kernel(const int32_t* __restrict__ a,
 void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int32_t* const* groups, int32_t G) {
   const int64_t m = g->m;
   const int32_t n[2] = {g->n_upper, g->n_lower};
-  g->light_packed = n[0] < (1 << 20) && n[1] < (1 << 20);
+  const int32_t span0 = g->key_span[0] >= 0 ? g->key_span[0] : n[0];
+  const int32_t span1 = g->key_span[1] >= 0 ? g->key_span[1] : n[1];
+  g->light_packed = span0 < (1 << 20) && span1 < (1 << 20);
 
   // status: [0] id out of range, [1] duplicate edge, [2 + o] first table row of layer o,
   // [4 + x] largest degree of layer x
@@ -655,28 +658,52 @@ __global__ void degree_of_kernel(const int32_t* __restrict__ off, int32_t n, int
     deg[r] = off[r + 1] - off[r];
 }
 
-// Classifies start (x, r): 0 = no pair can reach a count of 2, 1 = light, 2 = heavy.
+// The schedule's items: segment q < 2 holds layer q's starts with
+// Algorithm 2's wedges (or Algorithm 3's for a layer in vpp), segment 2 + x
+// the band items of layer x (Algorithm 3's wedges from a start below the
+// top band into it; empty without a band).  Item i of the concatenation is
+// start i - first[q] of segment q.
+struct Segs {
+  const int64_t* work[4];  // wedges per start
+  const int32_t* pre[4];   // middles per start
+  const int32_t* off[2];   // first slot of each start's list, per layer
+  int64_t first[5];        // first item of each segment; first[4] = item count
+};
+
+__device__ __forceinline__ int seg_of(const Segs& g, int64_t i) {
+  return (int)(i >= g.first[1]) + (int)(i >= g.first[2]) + (int)(i >= g.first[3]);
+}
+
+// item code: band item << 31 | layer << 30 | rank
+__device__ __forceinline__ int32_t item_code(int q, int32_t r) {
+  return (int32_t)(((uint32_t)(q >> 1) << 31) | ((uint32_t)(q & 1) << 30) | (uint32_t)r);
+}
+
+// Classifies item i: 0 = no pair can reach a count of 2, 1 = light, 2 = heavy.
 // sums: [0] |W|, [1] max prefix of a heavy start, [2] light wedges,
 // [3] heavy wedges, [4] light middles, [5] heavy middles, [6] max start wedges
 // Starts in the dense block (the top KU / KL ranks) always go to the
 // workgroup kernel, which seeds them with the block's MFMA products.
 constexpr int kClassifyNT = 256;
 
-__global__ __launch_bounds__(kClassifyNT) void classify_kernel(const int64_t* __restrict__ work0, const int32_t* __restrict__ lo0, int32_t n0,
-                                const int64_t* __restrict__ work1, const int32_t* __restrict__ lo1, int32_t n1,
+__global__ __launch_bounds__(kClassifyNT) void classify_kernel(Segs sg,
                                 int64_t light_max, const int32_t* __restrict__ glight,
                                 const int32_t* __restrict__ gid0, const int32_t* __restrict__ gid1,
                                 int32_t KU, int32_t KL, int64_t* __restrict__ is_light,
                                 int64_t* __restrict__ is_heavy, unsigned long long* __restrict__ sums) {
-  const int64_t n = (int64_t)n0 + n1;
+  const int64_t n = sg.first[4];
+  const int32_t n0 = (int32_t)sg.first[1], n1 = (int32_t)(sg.first[2] - sg.first[1]);
   unsigned long long s_all = 0, s_lw = 0, s_hw = 0, s_lm = 0, s_hm = 0, max_w = 0;
   int32_t max_pre = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t w = i < n0 ? work0[i] : work1[i - n0];
-    const int32_t pre = i < n0 ? lo0[i] : lo1[i - n0];
-    const bool in_block = i < n0 ? i >= (int64_t)n0 - KU : (i - n0) >= (int64_t)n1 - KL;
+    const int q = seg_of(sg, i);
+    const int32_t r = (int32_t)(i - sg.first[q]);
+    const int x = q & 1;
+    const int64_t w = sg.work[q][r];
+    const int32_t pre = sg.pre[q][r];
+    const bool in_block = q < 2 && (x == 0 ? r >= n0 - KU : r >= n1 - KL);
     // a tuned batch: this start's graph's cutoff
-    const int64_t lm = glight ? (int64_t)glight[i < n0 ? gid0[i] : gid1[i - n0]] : light_max;
+    const int64_t lm = glight ? (int64_t)glight[x == 0 ? gid0[r] : gid1[r]] : light_max;
     const bool heavy = w > lm || (in_block && w >= 2);
     const bool light = w >= 2 && !heavy;
     s_all += (unsigned long long)w;
@@ -740,14 +767,12 @@ __global__ __launch_bounds__(kClassifyNT) void classify_kernel(const int64_t* __
 // decreasing work.  n_medium counts the medium starts.
 __global__ void compact_kernel(const int64_t* __restrict__ is_light, const int64_t* __restrict__ is_heavy,
                                const int64_t* __restrict__ pos_light, const int64_t* __restrict__ pos_heavy,
-                               int32_t n0, int32_t n1, const int64_t* __restrict__ work0,
-                               const int64_t* __restrict__ work1, const int32_t* __restrict__ lo0,
-                               const int32_t* __restrict__ lo1, const int32_t* __restrict__ off0,
-                               const int32_t* __restrict__ off1, int64_t medium_max, int32_t KU, int32_t KL,
+                               Segs sg, int64_t medium_max, int32_t KU, int32_t KL,
                                int4* __restrict__ light, int32_t* __restrict__ heavy,
                                uint32_t* __restrict__ heavy_key, unsigned long long* __restrict__ n_medium,
                                long long* __restrict__ counts) {
-  const int64_t n = (int64_t)n0 + n1;
+  const int64_t n = sg.first[4];
+  const int32_t n0 = (int32_t)sg.first[1], n1 = (int32_t)(sg.first[2] - sg.first[1]);
   // the small light starts come first, then the mid ones, then the large ones
   const int32_t n_small = (int32_t)(pos_light[n] & 0xFFFFFFFFll);
   const int32_t n_mid = (int32_t)(pos_light[n] >> 32);
@@ -756,24 +781,24 @@ __global__ void compact_kernel(const int64_t* __restrict__ is_light, const int64
     counts[1] = pos_heavy[n];
   }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t code = i < n0 ? (int32_t)i : (int32_t)((1u << 30) | (uint32_t)(i - n0));
+    const int q = seg_of(sg, i);
+    const int32_t r = (int32_t)(i - sg.first[q]);
+    const int x = q & 1;
+    const int32_t code = item_code(q, r);
     const int64_t fl = is_light[i];
     const int64_t fh = is_heavy[i];
+    const int64_t w = sg.work[q][r];
+    const int32_t pre = sg.pre[q][r];
     if (fl || (fh >> 32)) {
       const int64_t pl = pos_light[i];
       const int32_t at = (fl & 0xFFFFFFFFll)   ? (int32_t)(pl & 0xFFFFFFFFll)
                          : fl                  ? n_small + (int32_t)(pl >> 32)
                                                : n_small + n_mid + (int32_t)(pos_heavy[i] >> 32);
-      const int32_t base = i < n0 ? off0[i] : off1[i - n0];
-      const int32_t pre = i < n0 ? lo0[i] : lo1[i - n0];
-      const int32_t w = (int32_t)(i < n0 ? work0[i] : work1[i - n0]);
-      light[at] = make_int4(code, base, pre, w);
+      light[at] = make_int4(code, sg.off[x][r], pre, (int32_t)w);
     }
     bool med = false;
     if (fh & 0xFFFFFFFFll) {
-      const int64_t w = i < n0 ? work0[i] : work1[i - n0];
-      const int32_t pre = i < n0 ? lo0[i] : lo1[i - n0];
-      const bool in_block = i < n0 ? i > (int64_t)n0 - KU : (i - n0) > (int64_t)n1 - KL;
+      const bool in_block = q < 2 && (x == 0 ? r > n0 - KU : r > n1 - KL);
       med = medium_max > 0 && w <= medium_max && pre <= kMediumMaxPre && !in_block;
       // ascending keys: big starts by decreasing work (steps of 2^(1/512)), then medium ones
       const int32_t lg = (int32_t)(512.0f * log2f((float)w));
@@ -786,20 +811,77 @@ __global__ void compact_kernel(const int64_t* __restrict__ is_light, const int64
   }
 }
 
-// Heavy list entries {code, off[rank], lo[rank], wedges (clamped to int32)}
+// Heavy list entries {code, off[rank], middles, wedges (clamped to int32)}
 // in the sorted order of the codes.
-__global__ void heavy_entries_kernel(const uint32_t* __restrict__ codes, const int64_t* __restrict__ n_dev,
-                                     const int32_t* __restrict__ off0,
-                                     const int32_t* __restrict__ off1, const int32_t* __restrict__ lo0,
-                                     const int32_t* __restrict__ lo1, const int64_t* __restrict__ work0,
-                                     const int64_t* __restrict__ work1, int4* __restrict__ out) {
+__global__ void heavy_entries_kernel(const uint32_t* __restrict__ codes, const int64_t* __restrict__ n_dev, Segs sg,
+                                     int4* __restrict__ out) {
   const int32_t n = (int32_t)(*n_dev & 0xFFFFFFFFll);  // heavy starts: the low word
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t code = (int32_t)codes[i];
-    const int x = (int)((uint32_t)code >> 30);
-    const int32_t r = code & ((1 << 30) - 1);
-    const int64_t w = x ? work1[r] : work0[r];
-    out[i] = make_int4(code, x ? off1[r] : off0[r], x ? lo1[r] : lo0[r], w < 0x7FFFFFFF ? (int32_t)w : 0x7FFFFFFF);
+    const uint32_t code = codes[i];
+    const int x = (int)((code >> 30) & 1u);
+    const int q = (int)(code >> 31) * 2 + x;
+    const int32_t r = (int32_t)(code & ((1u << 30) - 1u));
+    const int64_t w = sg.work[q][r];
+    out[i] = make_int4((int32_t)code, sg.off[x][r], sg.pre[q][r], w < 0x7FFFFFFF ? (int32_t)w : 0x7FFFFFFF);
+  }
+}
+
+// First slot of each list of the other layer whose end rank is >= lo (a
+// binary search per list; lists ascend).
+__global__ void band_lb_kernel(const int32_t* __restrict__ off_o, const int32_t* __restrict__ adj_o, int32_t n_o,
+                               int32_t lo, int32_t* __restrict__ out) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n_o; v += (int64_t)gridDim.x * blockDim.x) {
+    int32_t a = off_o[v], b = off_o[v + 1];
+    while (a < b) {
+      const int32_t mid = a + ((b - a) >> 1);
+      if (adj_o[mid] < lo) a = mid + 1; else b = mid;
+    }
+    out[v] = a;
+  }
+}
+
+// Per start r of a layer with a top band [band_lo, n) (one wavefront per
+// start):
+//   wband[r] = Algorithm 2's wedges through its lower-priority middles that
+//              end in the start's own part: ranks [band_lo, r) for a band
+//              start, [0, r) below the band;
+//   wtop[r]  = for a start below the band, Algorithm 3's wedges that end in
+//              the band: per middle v, the entries of N(v) above both r and
+//              v and >= band_lo (0 for band starts).
+__global__ void band_work_kernel(const int32_t* __restrict__ off_x, const int32_t* __restrict__ adj_x,
+                                 const int32_t* __restrict__ rev_x, const int32_t* __restrict__ lo_x,
+                                 const int32_t* __restrict__ off_o, const int32_t* __restrict__ lo_o,
+                                 const int32_t* __restrict__ blb, int32_t n, int32_t band_lo,
+                                 int64_t* __restrict__ wband, int64_t* __restrict__ wtop) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t wi = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); wi < n; wi += waves) {
+    const int32_t r = (int32_t)wi;
+    const int32_t a0 = off_x[r], lo = lo_x[r], d = off_x[r + 1] - a0;
+    const bool top = r >= band_lo;
+    unsigned long long t0 = 0, t1 = 0;
+    for (int32_t j = lane; j < d; j += 64) {
+      const int32_t a = a0 + j;
+      const int32_t v = adj_x[a];
+      const int32_t b = blb[v];
+      if (j < lo) {
+        const int32_t s0 = top ? b : off_o[v];
+        const int32_t e0 = rev_x[a];
+        t0 += (unsigned long long)(e0 > s0 ? e0 - s0 : 0);
+      }
+      if (!top) {
+        int32_t s0 = j < lo ? rev_x[a] + 1 : off_o[v] + lo_o[v];
+        s0 = s0 > b ? s0 : b;
+        const int32_t e0 = off_o[v + 1];
+        t1 += (unsigned long long)(e0 > s0 ? e0 - s0 : 0);
+      }
+    }
+    t0 = wave_sum(t0);
+    t1 = wave_sum(t1);
+    if (lane == 0) {
+      wband[r] = (int64_t)t0;
+      wtop[r] = (int64_t)t1;
+    }
   }
 }
 
@@ -808,32 +890,69 @@ __global__ void heavy_entries_kernel(const uint32_t* __restrict__ codes, const i
 void build_schedule(bfc_graph_s* g, hipStream_t s) {
   Schedule& sc = g->sched;
   const int32_t n0 = g->side[0].n, n1 = g->side[1].n;
-  const int64_t n = (int64_t)n0 + n1;
   // Algorithm 2: a start's middles are its lower-priority prefix (lo) and its
   // work the wedges through them.  Algorithm 3: every neighbour is a middle
-  // (the degree) and the work is Algorithm 3's count for the start.
+  // (the degree) and the work is Algorithm 3's count for the start.  A top
+  // band splits a layer's pairs between the two (band_work_kernel).
   const bool vpp = g->tune.vpp != 0;  // Algorithm 3 in at least one layer
+  const bool batch = g->grank[0].bytes != 0;
   TmpBuf degs[2];
-  const int64_t* work_x[2];
-  const int32_t* pre_x[2];
+  Segs sg{};
+  int32_t band = 0;
   for (int x = 0; x < 2; ++x) {
     Side& sd = g->side[x];
-    work_x[x] = sd.work.as<int64_t>();
-    pre_x[x] = sd.lo.as<int32_t>();
-    if (!((g->tune.vpp >> x) & 1)) continue;
-    if (sd.wpp.bytes < sizeof(int64_t) * (size_t)sd.n) {
-      sd.wpp.alloc(sizeof(int64_t) * (size_t)sd.n, s);
-      vpp_work(g, x, sd.wpp.as<int64_t>(), s);
-    }
-    degs[x].alloc(sizeof(int32_t) * (size_t)sd.n, s);
-    if (sd.n > 0) {
+    sg.work[x] = sd.work.as<int64_t>();
+    sg.pre[x] = sd.lo.as<int32_t>();
+    sg.off[x] = sd.off.as<int32_t>();
+    const bool layer_vpp = (g->tune.vpp >> x) & 1;
+    const int64_t T = g->tune.top_band;
+    sd.band_lo = (!layer_vpp && !batch && T > 0 && sd.n > T) ? (int32_t)(sd.n - T) : 0;
+    if (layer_vpp || sd.band_lo > 0) {
+      degs[x].alloc(sizeof(int32_t) * (size_t)sd.n, s);
       degree_of_kernel<<<grid_1d(sd.n), 256, 0, s>>>(sd.off.as<int32_t>(), sd.n, degs[x].as<int32_t>());
       BFC_LAUNCH_CHECK();
     }
-    work_x[x] = sd.wpp.as<int64_t>();
-    pre_x[x] = degs[x].as<int32_t>();
+    if (layer_vpp) {
+      if (sd.wpp.bytes < sizeof(int64_t) * (size_t)sd.n) {
+        sd.wpp.alloc(sizeof(int64_t) * (size_t)sd.n, s);
+        vpp_work(g, x, sd.wpp.as<int64_t>(), s);
+      }
+      sg.work[x] = sd.wpp.as<int64_t>();
+      sg.pre[x] = degs[x].as<int32_t>();
+    } else if (sd.band_lo > 0) {
+      const Side& od = g->side[1 - x];
+      sd.band_lb.alloc(sizeof(int32_t) * (size_t)od.n, s);
+      sd.wband.alloc(sizeof(int64_t) * (size_t)sd.n, s);
+      sd.wtop.alloc(sizeof(int64_t) * (size_t)sd.n, s);
+      if (od.n > 0) {
+        band_lb_kernel<<<grid_1d(od.n), 256, 0, s>>>(od.off.as<int32_t>(), od.adj.as<int32_t>(), od.n, sd.band_lo,
+                                                     sd.band_lb.as<int32_t>());
+        BFC_LAUNCH_CHECK();
+      }
+      const int64_t wg = ((int64_t)sd.n + 3) / 4;
+      band_work_kernel<<<(unsigned)(wg < 65536 ? wg : 65536), 256, 0, s>>>(
+          sd.off.as<int32_t>(), sd.adj.as<int32_t>(), sd.rev.as<int32_t>(), sd.lo.as<int32_t>(),
+          od.off.as<int32_t>(), od.lo.as<int32_t>(), sd.band_lb.as<int32_t>(), sd.n, sd.band_lo,
+          sd.wband.as<int64_t>(), sd.wtop.as<int64_t>());
+      BFC_LAUNCH_CHECK();
+      sg.work[x] = sd.wband.as<int64_t>();
+      sg.work[2 + x] = sd.wtop.as<int64_t>();
+      sg.pre[2 + x] = degs[x].as<int32_t>();
+      band |= 1 << x;
+    } else {
+      sd.band_lb.release(s);
+      sd.wband.release(s);
+      sd.wtop.release(s);
+    }
   }
   sc.vpp = g->tune.vpp;
+  sc.band = band;
+  sg.first[0] = 0;
+  sg.first[1] = n0;
+  sg.first[2] = (int64_t)n0 + n1;
+  sg.first[3] = sg.first[2] + ((band & 1) ? n0 : 0);
+  sg.first[4] = sg.first[3] + ((band & 2) ? n1 : 0);
+  const int64_t n = sg.first[4];
   // Algorithm 3's heavy starts all take the 1024-thread shape: the 256-thread
   // shape hung on them (kept off until its cause is found)
   // totals go to g->info from byte 64: [0..7] the classify sums, [7] medium
@@ -847,24 +966,21 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   pos_h.alloc(sizeof(int64_t) * (size_t)(n + 1), s);
   const int64_t light_max =
       g->tune.light_max_wedges < g->light_max_cap() ? g->tune.light_max_wedges : g->light_max_cap();
-  // the dense block seeds Algorithm 2's windows only
-  const int32_t K = vpp ? 0 : g->tune.dense_block;
+  // the dense block seeds Algorithm 2's windows over whole layers only
+  const int32_t K = (vpp || band) ? 0 : g->tune.dense_block;
   int32_t KU = K > 0 ? (K < n0 ? K : n0) : 0;
   int32_t KL = K > 0 ? (K < n1 ? K : n1) : 0;
   if (KU == 0 || KL == 0) KU = KL = 0;
   if (n > 0) {
-    classify_kernel<<<grid_1d(n) < 1024 ? grid_1d(n) : 1024, kClassifyNT, 0, s>>>(work_x[0], pre_x[0], n0,
-                                                work_x[1], pre_x[1], n1,
-                                                light_max, g->glight.bytes ? g->glight.as<int32_t>() : nullptr,
-                                                g->gid[0].as<int32_t>(), g->gid[1].as<int32_t>(), KU, KL,
-                                                flags_l.as<int64_t>(), flags_h.as<int64_t>(),
-                                                sums);
+    classify_kernel<<<grid_1d(n) < 1024 ? grid_1d(n) : 1024, kClassifyNT, 0, s>>>(
+        sg, light_max, g->glight.bytes ? g->glight.as<int32_t>() : nullptr, g->gid[0].as<int32_t>(),
+        g->gid[1].as<int32_t>(), KU, KL, flags_l.as<int64_t>(), flags_h.as<int64_t>(), sums);
     BFC_LAUNCH_CHECK();
   }
   exclusive_scan_i64(flags_l.as<int64_t>(), pos_l.as<int64_t>(), n, pos_l.as<int64_t>() + n, s);
   exclusive_scan_i64(flags_h.as<int64_t>(), pos_h.as<int64_t>(), n, pos_h.as<int64_t>() + n, s);
   // the list sizes are known only once the build is read back: each list
-  // holds every start (32 bytes per vertex for both; shrinking them would
+  // holds every item (32 bytes per item for both; shrinking them would
   // take a copy and a wait at the end of every build)
   sc.light.alloc(sizeof(int4) * (size_t)n, s);
   sc.heavy.alloc(sizeof(int4) * (size_t)n, s);
@@ -875,20 +991,19 @@ void build_schedule(bfc_graph_s* g, hipStream_t s) {
   hval_tmp.alloc(sizeof(uint32_t) * (size_t)n, s);
   if (n > 0) {
     BFC_HIP(hipMemsetAsync(hkey.p, 0xFF, sizeof(uint32_t) * (size_t)n, s));  // past the heavy starts: key 0xFFFF...
+    // the 256-thread shape walks Algorithm 2's wedges of whole layers only
     compact_kernel<<<grid_1d(n), 256, 0, s>>>(flags_l.as<int64_t>(), flags_h.as<int64_t>(), pos_l.as<int64_t>(),
-                                               pos_h.as<int64_t>(), n0, n1, work_x[0], work_x[1], pre_x[0],
-                                               pre_x[1], g->side[0].off.as<int32_t>(),
-                                               g->side[1].off.as<int32_t>(), vpp ? 0 : (int64_t)g->tune.medium_max_wedges, KU,
-                                               KL, sc.light.as<int4>(), hcode.as<int32_t>(), hkey.as<uint32_t>(),
+                                               pos_h.as<int64_t>(), sg,
+                                               (vpp || band) ? 0 : (int64_t)g->tune.medium_max_wedges, KU, KL,
+                                               sc.light.as<int4>(), hcode.as<int32_t>(), hkey.as<uint32_t>(),
                                                sums + 7, reinterpret_cast<long long*>(sums + 8));
     BFC_LAUNCH_CHECK();
     // heavy starts first, in key order (16-bit keys)
     if (n > 1)
       radix_sort_u32(hkey.as<uint32_t>(), hcode.as<uint32_t>(), hkey_tmp.as<uint32_t>(), hval_tmp.as<uint32_t>(), n,
                      16, s);
-    heavy_entries_kernel<<<grid_1d(n), 256, 0, s>>>(
-        hcode.as<uint32_t>(), pos_h.as<int64_t>() + n, g->side[0].off.as<int32_t>(), g->side[1].off.as<int32_t>(),
-        pre_x[0], pre_x[1], work_x[0], work_x[1], sc.heavy.as<int4>());
+    heavy_entries_kernel<<<grid_1d(n), 256, 0, s>>>(hcode.as<uint32_t>(), pos_h.as<int64_t>() + n, sg,
+                                                    sc.heavy.as<int4>());
     BFC_LAUNCH_CHECK();
   }
 }
@@ -1025,6 +1140,8 @@ void build_batch(bfc_graph_s* g, const int32_t* edges, const int64_t* eoff_host,
   g->n_upper = (int32_t)su;
   g->n_lower = (int32_t)sl;
   g->n_graphs = G;
+  g->key_span[0] = G > 0 ? *std::max_element(nu_host, nu_host + G) : 0;
+  g->key_span[1] = G > 0 ? *std::max_element(nl_host, nl_host + G) : 0;
   TmpBuf d_eoff, d_uoff, d_loff, shifted, status;
   d_eoff.alloc(sizeof(int64_t) * (size_t)(G + 1), s);
   d_uoff.alloc(sizeof(int32_t) * (size_t)(G + 1), s);

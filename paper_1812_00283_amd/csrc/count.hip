@@ -71,6 +71,9 @@ struct CountParams {
   int32_t vpp;                 // bit x: layer x's starts take Algorithm 3's wedges (ends above the start and the middle)
   const int4* gtune;           // per graph {dense ratio, window mode, hash window wedges, dense min wedges}, or null
   int32_t nX[2];               // layer sizes (the end of Algorithm 3's end ranges)
+  int32_t band_lo[2];          // first rank of each layer's top band (0: no band)
+  const int32_t* blb[2];       // per layer x with a band: first slot >= band_lo[x] of each other-layer list
+  const int64_t* wtop[2];      // per layer x with a band: band-item wedges per start
 };
 
 __device__ __forceinline__ int32_t graph_index(const CountParams& p, int x, int32_t r) {
@@ -98,8 +101,11 @@ __device__ __forceinline__ unsigned long long* pick_ptr(unsigned long long* cons
 //   Algorithm 3: the entries of N(v) above both the start and v: past the
 //   start's slot when v ranks below the start, else past v's own
 //   lower-priority prefix (which then holds the start).
+// clb (non-null for a band start and for a band item): the slice also
+// keeps to end ranks >= the band's first rank, clb[v] being N(v)'s first
+// slot there.
 __device__ __forceinline__ void mid_slice(bool vpp, const SideView& S, const SideView& O, int32_t k, int32_t j,
-                                          int32_t lo_r, int32_t& v, int32_t& s0, int32_t& e0) {
+                                          int32_t lo_r, const int32_t* clb, int32_t& v, int32_t& s0, int32_t& e0) {
   v = S.adj[k];
   if (!vpp) {
     s0 = O.off[v];
@@ -108,6 +114,26 @@ __device__ __forceinline__ void mid_slice(bool vpp, const SideView& S, const Sid
     s0 = j < lo_r ? S.rev[k] + 1 : O.off[v] + O.lo[v];
     e0 = O.off[v + 1];
   }
+  if (clb) {
+    const int32_t b = clb[v];
+    s0 = s0 > b ? s0 : b;
+  }
+}
+
+// The band part of a list item: clb for mid_slice (null: none) and the end
+// ranks [elo, ehi) of the item's wedges when it has a band part (band
+// start: [band_lo, r); band item: [band_lo, n)).
+struct BandPart {
+  const int32_t* clb;
+  bool band_item;
+};
+
+__device__ __forceinline__ BandPart band_part(const CountParams& p, int32_t code, int x, int32_t r) {
+  BandPart b;
+  b.band_item = (uint32_t)code >> 31;
+  const int32_t lo = x ? p.band_lo[1] : p.band_lo[0];
+  b.clb = (lo > 0 && (b.band_item || r >= lo)) ? (x ? p.blb[1] : p.blb[0]) : nullptr;
+  return b;
 }
 
 // Adds d to per-arc accumulator i of side x.  Every partial sum is at most
@@ -297,8 +323,9 @@ __device__ __forceinline__ int32_t hash_get(const int32_t* keys, const int32_t* 
 }
 
 // Packed wavefront tables: one word per entry, (w + 1) << kLightCountBits |
-// count, for layers of fewer than 2^(32 - kLightCountBits) vertices and
-// starts of fewer than 2^kLightCountBits wedges.  Same probing and return
+// count, for keys w below 2^(32 - kLightCountBits) (a layer's rank, or in a
+// batch its offset from the first rank of its graph) and starts of fewer
+// than 2^kLightCountBits wedges.  Same probing and return
 // value as wave_hash_inc.
 constexpr int kLightCountBits = 12;
 constexpr uint32_t kLightCountMask = (1u << kLightCountBits) - 1u;
@@ -364,14 +391,21 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
   for (; idx < n_list; idx += stride) {
     const int4 cur = next;
     if (idx + stride < n_list) next = list[idx + stride];
-    const int x = (int)((uint32_t)cur.x >> 30);
+    const int x = (int)(((uint32_t)cur.x >> 30) & 1u);
     const int32_t r = cur.x & ((1 << 30) - 1);
     const int32_t base = cur.y;
     const int32_t pre = cur.z;
     const SideView S = pick(p, x);
     const SideView O = pick(p, 1 - x);
-    const bool vpp = kVpp && ((p.vpp >> x) & 1);
+    // (bands need the kVpp instantiation: band items take Algorithm 3's wedges)
+    const BandPart bp = band_part(p, cur.x, x, r);
+    const int32_t* clb = kVpp ? bp.clb : nullptr;
+    const bool vpp = kVpp && (bp.band_item || ((p.vpp >> x) & 1));
     const int32_t lo_r = vpp ? S.lo[r] : 0;
+    // packed keys of a batch count from the first rank of the start's graph
+    // (every end lies in that graph's part of layer x)
+    const int32_t* grank = x ? p.grank[1] : p.grank[0];
+    const int32_t wlo = (kPacked && grank) ? __builtin_amdgcn_readfirstlane(grank[graph_index(p, x, r)]) : 0;
     uint32_t cap = 64;
     while ((int32_t)cap < 2 * cur.w) cap <<= 1;
     const uint32_t mask = cap - 1;
@@ -381,11 +415,11 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
       int32_t cs = 0, len = 0;
       if (j < pre) {
         int32_t v, e;
-        mid_slice(vpp, S, O, base + j, j, lo_r, v, cs, e);
+        mid_slice(vpp, S, O, base + j, j, lo_r, clb, v, cs, e);
         len = e - cs;
       }
       light_walk(O.adj, cs, len, [&](int, int32_t, int32_t w) {
-        a += (unsigned)(kPacked ? wave_packed_inc(ptab, mask, w) : wave_hash_inc(keys, cnt, mask, w));
+        a += (unsigned)(kPacked ? wave_packed_inc(ptab, mask, w - wlo) : wave_hash_inc(keys, cnt, mask, w));
       });
     }
     if (kMode == kTotal) {
@@ -402,7 +436,7 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
         for (uint32_t h = lane; h < cap; h += 64) {
           const uint32_t word = ptab[h];
           const int32_t c = kPacked ? (int32_t)(word & kLightCountMask) : cnt[h];
-          const int32_t key = kPacked ? (int32_t)(word >> kLightCountBits) : keys[h];
+          const int32_t key = kPacked ? (int32_t)(word >> kLightCountBits) + wlo : keys[h];
           if (c > 1) atomicAdd(&vs[key - 1], choose2(c));
         }
         a = wave_sum(a);
@@ -416,11 +450,11 @@ __global__ __launch_bounds__(kLightNT) void light_kernel(CountParams p, const in
         int32_t cs = 0, len = 0, v = 0;
         if (j < pre) {
           int32_t e;
-          mid_slice(vpp, S, O, base + j, j, lo_r, v, cs, e);
+          mid_slice(vpp, S, O, base + j, j, lo_r, clb, v, cs, e);
           len = e - cs;
         }
         light_walk(O.adj, cs, len, [&](int mid, int32_t slot, int32_t w) {
-          const int32_t c = kPacked ? wave_packed_get(ptab, mask, w) : hash_get(keys, cnt, mask, w);
+          const int32_t c = kPacked ? wave_packed_get(ptab, mask, w - wlo) : hash_get(keys, cnt, mask, w);
           if (c > 1) {
             const unsigned long long d = (unsigned long long)(c - 1);
             if (kMode == kEdge) acc_add(p, 1 - x, slot, d);
@@ -733,32 +767,37 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
   // Starts come from a global ticket.  Thread 0 takes the next start's
   // ticket when a start begins and loads its entry when the start ends, so
   // the ticket's round trip overlaps the start's work.
+  // (code -1: none left; a real code has rank < 2^30 - 1)
   auto entry_of = [&](uint32_t i) { return (int32_t)i < p.n_list ? p.list[i] : make_int4(-1, 0, 0, 0); };
   if (t == 0) s_entry = entry_of(atomicAdd(p.ticket, 1u));
   for (;;) {
     __syncthreads();
     const int4 ent = s_entry;
     __syncthreads();
-    if (ent.x < 0) break;
+    if (ent.x == -1) break;
     uint32_t next_ticket = 0;
     if (t == 0) next_ticket = atomicAdd(p.ticket, 1u);
     // the entry is the same in every lane: keep it (and what derives from
     // it) in scalar registers
     const int32_t code = __builtin_amdgcn_readfirstlane(ent.x);
-    const int x = (int)((uint32_t)code >> 30);
+    const int x = (int)(((uint32_t)code >> 30) & 1u);
     const int32_t r = code & ((1 << 30) - 1);
     const SideView S = pick(p, x);
     const SideView O = pick(p, 1 - x);
     const int32_t base = __builtin_amdgcn_readfirstlane(ent.y);
     const int32_t pre = __builtin_amdgcn_readfirstlane(ent.z);
     const int32_t ew = __builtin_amdgcn_readfirstlane(ent.w);
+    // (bands need the kVpp instantiation: band items take Algorithm 3's wedges)
+    const BandPart bp = band_part(p, code, x, r);
+    const int32_t* clb = kVpp ? bp.clb : nullptr;
+    const bool band_item = kVpp && bp.band_item;
     int64_t W = ew;
     if (ew == 0x7FFFFFFF) {
-      const int64_t w = S.work[r];
+      const int64_t w = band_item ? (x ? p.wtop[1] : p.wtop[0])[r] : S.work[r];
       W = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(w >> 32)) << 32) |
                     (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)w));
     }
-    const bool vpp = kVpp && ((p.vpp >> x) & 1);
+    const bool vpp = kVpp && (band_item || ((p.vpp >> x) & 1));
     const int32_t lo_r = vpp ? __builtin_amdgcn_readfirstlane(S.lo[r]) : 0;
     // End ranks lie in [elo, ehi): below the start under Algorithm 2, above
     // it under Algorithm 3, within the start's graph (a batch ranks each
@@ -777,8 +816,14 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
       hash_window_wedges = __builtin_amdgcn_readfirstlane(gt.z);
       dense_min_wedges = __builtin_amdgcn_readfirstlane(gt.w);
     }
-    const int32_t elo = vpp ? ((r + 1) & ~1) : (grank ? (__builtin_amdgcn_readfirstlane(grank[gi]) & ~1) : 0);
-    const int32_t ehi = vpp ? (grank ? __builtin_amdgcn_readfirstlane(grank[gi + 1]) : (x ? p.nX[1] : p.nX[0])) : r;
+    // With a band part the ends lie in [band_lo, r) (band start) or
+    // [band_lo, n_X) (band item).
+    const int32_t elo = clb ? ((x ? p.band_lo[1] : p.band_lo[0]) & ~1)
+                        : vpp ? ((r + 1) & ~1)
+                              : (grank ? (__builtin_amdgcn_readfirstlane(grank[gi]) & ~1) : 0);
+    const int32_t ehi = (clb && !band_item) ? r
+                        : vpp ? (grank ? __builtin_amdgcn_readfirstlane(grank[gi + 1]) : (x ? p.nX[1] : p.nX[0]))
+                              : r;
     const int32_t span = ehi - elo;
     // middles of rank >= tfirst find their window slices in the table and
     // keep no cursor
@@ -855,7 +900,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     auto init_cursors = [&] {
       for (int32_t j = t; j < pre; j += kNT) {
         int32_t v, ps, pe;
-        mid_slice(vpp, S, O, base + j, j, lo_r, v, ps, pe);
+        mid_slice(vpp, S, O, base + j, j, lo_r, clb, v, ps, pe);
         if (v >= tfirst) continue;
         pos[j] = ps;
         nxt[j] = ps < pe ? O.adj[ps] : kNone;
@@ -878,7 +923,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         raux[h] = rnv[h] = -1 - kNoEnd;
         if (j < pre) {
           int32_t v, cs, e;
-          mid_slice(vpp, S, O, base + j, j, lo_r, v, cs, e);
+          mid_slice(vpp, S, O, base + j, j, lo_r, clb, v, cs, e);
           re[h] = e;
           rcs[h] = rce[h] = cs;
           raux[h] = v >= tfirst ? (v - tfirst) * trow : -1 - (cs < e ? O.adj[cs] : kNoEnd);
@@ -935,7 +980,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
             csv[h] = cev[h] = ev[h] = vv[h] = 0;
             if (j < npre) {
               int32_t v, s0, e;
-              mid_slice(vpp, S, O, base + j, j, lo_r, v, s0, e);
+              mid_slice(vpp, S, O, base + j, j, lo_r, clb, v, s0, e);
               const int32_t pj = cursors ? pos[j] : 0;  // cursor state (meaningful below tfirst)
               const int32_t nj = cursors ? nxt[j] : kNone;
               ev[h] = e;
@@ -949,7 +994,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
                 // slice keeps to [s0, e)
                 const int32_t* rowp = tab + (int64_t)(v - tfirst) * trow;
                 int32_t cs = table_lb(O.adj, rowp, lo_w);
-                if (vpp) cs = cs > s0 ? cs : s0;  // (Algorithm 2: the table's slot is never before s0)
+                if (vpp || clb) cs = cs > s0 ? cs : s0;  // (Algorithm 2 alone: the table's slot is never before s0)
                 int32_t ce = e;
                 if (hi_w < ehi) {
                   const int32_t c2 = table_lb(O.adj, rowp, hi_w);
@@ -1039,7 +1084,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
                 // (Algorithm 3: the table's slot can lie before the slice)
                 const int32_t c2 = table_lb(O.adj, tab + raux[h], hi_w);
                 ce = c2 < e ? c2 : e;
-                if (vpp) ce = ce > cs ? ce : cs;
+                if (vpp || clb) ce = ce > cs ? ce : cs;
               }
             } else if (nv < hi_w) {
               if (hi_w >= ehi) {
@@ -1312,7 +1357,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         // hash window of a total count: advance the cursors now that the window is final
         for (int32_t j = t; j < pre1; j += kNT) {
           int32_t v, s0, e;
-          mid_slice(vpp, S, O, base + j, j, lo_r, v, s0, e);
+          mid_slice(vpp, S, O, base + j, j, lo_r, clb, v, s0, e);
           if (v < tfirst && nxt[j] < hi_w) {
             const int32_t ce = cend[j];
             pos[j] = ce;
@@ -1676,6 +1721,19 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   // Algorithm 3's per-start work (read when a list entry's clamps)
   if (sc.vpp & 1) p.sv[0].work = g->side[0].wpp.as<int64_t>();
   if (sc.vpp & 2) p.sv[1].work = g->side[1].wpp.as<int64_t>();
+  // top bands: band starts' own-part work, band items' work and slice bounds
+  for (int x = 0; x < 2; ++x) {
+    p.band_lo[x] = 0;
+    p.blb[x] = nullptr;
+    p.wtop[x] = nullptr;
+    if ((sc.band >> x) & 1) {
+      const Side& sd = g->side[x];
+      p.band_lo[x] = sd.band_lo;
+      p.blb[x] = sd.band_lb.as<int32_t>();
+      p.wtop[x] = sd.wtop.as<int64_t>();
+      p.sv[x].work = sd.wband.as<int64_t>();
+    }
+  }
   for (int o = 0; o < 2; ++o) {
     p.wt[o] = g->wt[o].bytes ? g->wt[o].as<int32_t>() : nullptr;
     p.wt_first[o] = g->wt_first[o];
@@ -1745,7 +1803,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
       return (unsigned)(grid > (int64_t)cus * 16 ? (int64_t)cus * 16 : grid);
     };
     const int32_t n_small = sc.n_small, n_mid = sc.n_mid, n_large = sc.n_light - sc.n_small - sc.n_mid;
-    const bool vpp = sc.vpp != 0;
+    const bool vpp = sc.vpp != 0 || sc.band != 0;
     if (n_small > 0) {
       launch_light<kSmallCap, false>(mode, vpp, light_grid(n_small), s, p, llist, n_small);
     }
@@ -1765,7 +1823,7 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   if (n_big > 0) {
     p.list = g->sched.heavy.as<int4>();
     p.n_list = n_big;
-    if (sc.vpp) launch_heavy<kBigNT, kBigWords, true>(mode, big_grid, s, p);
+    if (sc.vpp || sc.band) launch_heavy<kBigNT, kBigWords, true>(mode, big_grid, s, p);
     else launch_heavy<kBigNT, kBigWords, false>(mode, big_grid, s, p);
   }
   if (sc.n_medium > 0) {

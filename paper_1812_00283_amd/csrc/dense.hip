@@ -167,8 +167,8 @@ int32_t pad32(int32_t x) { return (x + 31) / 32 * 32; }
 
 void prepare_dense(bfc_graph_s* g, hipStream_t s) {
   DenseBlock& d = g->dense;
-  // the block seeds the windows of Algorithm 2's starts only
-  const int32_t K = g->tune.vpp ? 0 : g->tune.dense_block;
+  // the block seeds the windows of Algorithm 2's starts over whole layers only
+  const int32_t K = (g->tune.vpp || g->sched.band) ? 0 : g->tune.dense_block;
   d.KU = K > 0 ? (K < g->n_upper ? K : g->n_upper) : 0;
   d.KL = K > 0 ? (K < g->n_lower ? K : g->n_lower) : 0;
   if (d.KU <= 0 || d.KL <= 0) {

@@ -93,6 +93,11 @@ struct DevBuf {
     p = cache_alloc(n, s);
     bytes = n;
   }
+  void release(hipStream_t s) {
+    if (p) cache_free(p, s);
+    p = nullptr;
+    bytes = 0;
+  }
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
@@ -134,6 +139,15 @@ struct Side {
   DevBuf id_of;    // int32 [n] local rank -> input id
   DevBuf work;     // int64 [n] wedges Algorithm 2 processes from this start
   DevBuf wpp;      // int64 [n] wedges Algorithm 3 processes from this start (computed when first needed)
+  // Top band of this layer (tuning top_band): ranks [band_lo, n).  A pair of
+  // this layer whose lower vertex lies below the band while the higher one
+  // lies in it is counted from the lower vertex with Algorithm 3's wedges
+  // into the band; every other pair from its higher vertex with Algorithm
+  // 2's wedges, which then end inside the start's own part (band or below).
+  int32_t band_lo = 0;  // 0: no band (Algorithm 2's wedges from every start)
+  DevBuf band_lb;  // int32 [n of the other layer]: first slot of each other-layer list whose end rank is >= band_lo
+  DevBuf wband;    // int64 [n]: Algorithm 2 wedges of each start, ends within its part
+  DevBuf wtop;     // int64 [n]: Algorithm 3 wedges from each start below the band into the band
 };
 
 struct Schedule {
@@ -142,7 +156,7 @@ struct Schedule {
   int32_t n_mid = 0;     // the next n_mid at most kLightMidMax, the rest more
   int32_t n_heavy = 0;   // starts counted by one workgroup
   int32_t n_medium = 0;  // of those, the last n_medium use the 256-thread shape
-  DevBuf light;          // int4 {code (side << 30 | rank), off[rank], lo[rank], wedges}
+  DevBuf light;          // int4 {code (band item << 31 | side << 30 | rank), off[rank], middles, wedges}
   DevBuf heavy;          // int4 entries as in `light`, by decreasing work
   int64_t wedges = 0;    // |W|
   int32_t max_prefix = 0;
@@ -152,6 +166,7 @@ struct Schedule {
   int32_t light_max = 0; // thresholds the lists were built with
   int32_t medium_max = 0;
   int32_t vpp = 0;       // bit x: the lists hold Algorithm 3's starts of layer x (entry = {code, off, degree, wedges})
+  int32_t band = 0;      // bit x: layer x has a top band (its band items carry code bit 31)
 };
 
 struct Tuning {
@@ -163,6 +178,7 @@ struct Tuning {
   int32_t dense_min_wedges = 8192;
   int32_t medium_max_wedges = 0;  // 256-thread workgroups measured slower on the degree-skewed workloads
   int32_t vpp = 0;                // bit x: layer x's starts count Algorithm 3's wedges (BFC-VP++), else Algorithm 2's
+  int32_t top_band = 0;           // width of each layer's top band of ranks (0: none); layers in vpp take none
 };
 
 // Dense block of top-priority vertices (int8 MFMA, see dense.hip).
@@ -197,9 +213,11 @@ struct bfc_graph_s {
   // when the build is complete
   bfc::DevBuf info;
   int64_t caterpillars = 0;  // three-paths, sum over edges of (d_u - 1)(d_v - 1)
-  // light tables pack (end + 1) << 12 | count when every layer has fewer
-  // than 2^20 vertices; light starts then go up to 2048 wedges, else 1024
+  // light tables pack (end - first rank of its graph + 1) << 12 | count
+  // when every graph's layers have fewer than 2^20 vertices; light starts
+  // then go up to 2048 wedges, else 1024
   bool light_packed = false;
+  int32_t key_span[2] = {-1, -1};  // largest layer of one graph of a batch (-1: one graph)
   int32_t light_max_cap() const { return light_packed ? 2048 : 1024; }
   int64_t rows_max[2] = {0, 0};  // window-table rows allocated per layer
   int32_t max_deg[2] = {0, 0};   // largest degree per layer

@@ -84,6 +84,34 @@ def test_small_batch_vpp(gpu_lib):
                 ol += g.n_lower
 
 
+def test_wide_batch_graph_local_keys(gpu_lib):
+    """A batch whose upper layer has more than 2^20 vertices in all, every
+    graph below 2^20: the light tables pack keys counted from each graph's
+    first rank.  Every output, with both wedge directions, must equal the
+    oracle's."""
+    graphs = [gg.chung_lu(500 + i, 100_000, 60_000, 150_000, 2.1, 2.1, 600.0) for i in range(11)]
+    b = gg.concat(graphs)
+    assert sum(b.n_upper) >= (1 << 20) and max(b.n_upper) < (1 << 20)
+    print(f"wide batch: {len(graphs)} graphs, {sum(b.n_upper)} upper, {b.offsets[-1]} edges", flush=True)
+    with gpu_lib.build_batch(torch.from_numpy(b.edges).cuda(), b.offsets, b.n_upper, b.n_lower) as h:
+        for tun in ({}, {"vpp": 3}):
+            if tun:
+                h.set_tuning(**tun)
+            totals = h.count_total_batch().cpu().numpy()
+            up, lo = h.count_per_vertex()
+            be = h.count_per_edge()
+            up, lo, be = up.cpu().numpy(), lo.cpu().numpy(), be.cpu().numpy()
+            ou = ol = 0
+            for i, g in enumerate(graphs):
+                assert totals[i] == oracle.total(g), (i, tun)
+                o_up, o_lo = oracle.vertex_counts(g)
+                np.testing.assert_array_equal(up[ou:ou + g.n_upper], o_up)
+                np.testing.assert_array_equal(lo[ol:ol + g.n_lower], o_lo)
+                np.testing.assert_array_equal(be[b.offsets[i]:b.offsets[i + 1]], oracle.edge_counts(g))
+                ou += g.n_upper
+                ol += g.n_lower
+
+
 def test_per_graph_tuning(gpu_lib):
     """Per-graph settings (what the tuner installs per bucket): every output
     unchanged, through a captured and replayed count too."""

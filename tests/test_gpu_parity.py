@@ -74,6 +74,21 @@ def test_random_tiny_graphs_vpp(gpu_lib):
         assert oracle.vpp_wedges(g) == oracle.vp_wedges(g)
 
 
+def test_random_tiny_graphs_band(gpu_lib):
+    """Top bands of every width on tiny graphs: the same outputs and |W| as
+    Algorithm 2's, on each kernel path."""
+    rng = np.random.default_rng(79)
+    for i in range(120):
+        g = gg.random_small(9700 + i, int(rng.integers(1, 12)), int(rng.integers(1, 12)),
+                            float(rng.choice([0.2, 0.5, 0.8, 1.0])))
+        band = int(rng.integers(1, 12))
+        tun = [{"top_band": band}, {"top_band": band, "light_max_wedges": 1},
+               {"top_band": band, "light_max_wedges": 1, "window_mode": 3, "hash_window_wedges": 4},
+               {"top_band": band, "light_max_wedges": 1, "window_mode": 2},
+               {"top_band": band, "vpp": 2}][i % 5]
+        check_against_oracle(gpu_lib, g, tun)
+
+
 def test_union_of_many_small_graphs(gpu_lib):
     rng = np.random.default_rng(5)
     parts, ou, ol = [], 0, 0
@@ -153,6 +168,28 @@ TUNINGS = {
     # layer of its top vertex, so any mix is exact)
     "vpp-upper-only": {"vpp": 1},
     "vpp-lower-only": {"vpp": 2, "light_max_wedges": 64},
+    # top bands: a pair with only its higher vertex in the band is counted
+    # from the lower one with Algorithm 3's wedges into the band
+    "band-64": {"top_band": 64},
+    "band-777-odd": {"top_band": 777, "light_max_wedges": 64},
+    "band-4096": {"top_band": 4096},
+    "band-65536": {"top_band": 65536},
+    "band-light-1024": {"top_band": 4096, "light_max_wedges": 1024},
+    "band-all-workgroup": {"top_band": 4096, "light_max_wedges": 1},
+    "band-dense-windows": {"top_band": 4096, "light_max_wedges": 16, "window_mode": 2},
+    "band-hash-windows": {"top_band": 4096, "light_max_wedges": 16, "window_mode": 3},
+    "band-hash-tiny-windows": {"top_band": 30000, "light_max_wedges": 1, "window_mode": 3,
+                               "hash_window_wedges": 64},
+    "band-hash-overfull": {"top_band": 4096, "light_max_wedges": 64, "window_mode": 3,
+                           "hash_window_wedges": 1 << 30},
+    "band-auto-prefix-small": {"top_band": 30000, "light_max_wedges": 64, "dense_min_wedges": 256,
+                               "hash_window_wedges": 2048},
+    # (the dense block and the 256-thread shape are not used with a band)
+    "band-ignores-dense-block": {"top_band": 4096, "dense_block": 1024, "light_max_wedges": 64},
+    "band-medium-ignored": {"top_band": 4096, "light_max_wedges": 16, "window_mode": 3,
+                            "medium_max_wedges": 1 << 30},
+    # a band in the lower layer only (the upper layer takes Algorithm 3's wedges)
+    "band-with-vpp-upper": {"top_band": 4096, "vpp": 1},
 }
 
 
@@ -160,7 +197,7 @@ TUNINGS = {
 def test_hub_graph_every_kernel_path(gpu_lib, hub_graph, hub_oracle, name):
     tun = TUNINGS[name]
     tot, wed, up, lo, be = gpu_all(gpu_lib, hub_graph, tun or None)
-    if tun.get("vpp") and tun.get("medium_max_wedges"):
+    if (tun.get("vpp") or tun.get("top_band")) and tun.get("medium_max_wedges"):
         with gpu_lib.Graph(to_dev(hub_graph), hub_graph.n_upper, hub_graph.n_lower) as h:
             h.set_tuning(**tun)
             assert h.schedule_info()["starts_medium"] == 0

@@ -107,3 +107,13 @@ def test_chunglu_1m_500k_20m_vpp(gpu_lib):
 
 def test_chunglu_16m_4m_200m_planted_vpp(gpu_lib):
     run_workload(gpu_lib, "chunglu-16m-4m-200m-planted", per_vertex=False, live_samples=4, tuning={"vpp": 3})
+
+
+def test_chunglu_1m_500k_20m_band(gpu_lib):
+    """Top bands of 65,536 ranks on the 20M-edge graph: every output identical."""
+    run_workload(gpu_lib, "chunglu-1m-500k-20m", live_samples=4, tuning={"top_band": 65536})
+
+
+def test_chunglu_16m_4m_200m_planted_band(gpu_lib):
+    run_workload(gpu_lib, "chunglu-16m-4m-200m-planted", per_vertex=False, live_samples=4,
+                 tuning={"top_band": 65536})
