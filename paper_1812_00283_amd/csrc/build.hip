@@ -644,7 +644,14 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
         status.as<int32_t>() + 2 + o, g->wt[o].as<int32_t>());
     BFC_LAUNCH_CHECK();
   }
-  // duplicates and the tables' first rows are read by finish_schedule
+  // first rank of degree >= 256 per layer (status words 8 and 9)
+  if (!groups) {
+    for (int x = 0; x < 2; ++x) {
+      first_rank_kernel<<<1, 64, 0, s>>>(g->side[x].off.as<int32_t>(), n[x], 256, status.as<int32_t>() + 8 + x);
+      BFC_LAUNCH_CHECK();
+    }
+  }
+  // duplicates, the tables' first rows and the byte ranks are read by finish_schedule
   g->rows_max[0] = rows_max[0];
   g->rows_max[1] = rows_max[1];
 }
@@ -1029,6 +1036,8 @@ void finish_schedule(bfc_graph_s* g, hipStream_t s) {
     const int32_t lo = (int32_t)(nn[o] - g->rows_max[o]);
     g->wt_first[o] = st[2 + o] > lo ? st[2 + o] : lo;
   }
+  g->byte_rank[0] = st[8];
+  g->byte_rank[1] = st[9];
   sc.wedges = t[0];
   sc.max_prefix = (int32_t)t[1];
   sc.wedges_light = t[2];

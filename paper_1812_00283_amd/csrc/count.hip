@@ -71,6 +71,7 @@ struct CountParams {
   int32_t vpp;                 // bit x: layer x's starts take Algorithm 3's wedges (ends above the start and the middle)
   const int4* gtune;           // per graph {dense ratio, window mode, hash window wedges, dense min wedges}, or null
   int32_t nX[2];               // layer sizes (the end of Algorithm 3's end ranges)
+  int32_t q8[2];               // per layer: ends below this rank have degree < 256 (8-bit dense counters)
   int32_t band_lo[2];          // first rank of each layer's top band (0: no band)
   const int32_t* blb[2];       // per layer x with a band: first slot >= band_lo[x] of each other-layer list
   const int64_t* wtop[2];      // per layer x with a band: band-item wedges per start
@@ -528,14 +529,17 @@ __device__ __forceinline__ int block_hash_add(int32_t* table, uint32_t cap, int3
   return kOverfull;
 }
 
-// Dense window counters: 32-bit, or two 16-bit counters per word when every
-// count fits (a count is at most the start's number of middles).
+// Dense window counters: 32-bit, two 16-bit counters per word when every
+// count fits (a count is at most the start's number of middles), or four
+// 8-bit counters per word for ends of degree below 256 (an end's count is at
+// most its degree: each of its wedges has its own middle in N(end)).
 __device__ __forceinline__ void dense_add(int32_t* table, int32_t i, bool half) {
   if (half) atomicAdd(reinterpret_cast<uint32_t*>(&table[i >> 1]), 1u << ((i & 1) << 4));
   else atomicAdd(&table[i], 1);
 }
 
-__device__ __forceinline__ int32_t dense_get(const int32_t* table, int32_t i, bool half) {
+__device__ __forceinline__ int32_t dense_get(const int32_t* table, int32_t i, bool half, bool quarter) {
+  if (quarter) return (int32_t)((reinterpret_cast<const uint32_t*>(table)[i >> 2] >> ((i & 3) << 3)) & 0xFFu);
   if (half) return (int32_t)((reinterpret_cast<const uint32_t*>(table)[i >> 1] >> ((i & 1) << 4)) & 0xFFFFu);
   return table[i];
 }
@@ -764,19 +768,27 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
   for (int i = t; i < kWords; i += kNT) table[i] = 0;
   unsigned long long acc_total = 0;
 
-  // Starts come from a global ticket.  Thread 0 takes the next start's
-  // ticket when a start begins and loads its entry when the start ends, so
-  // the ticket's round trip overlaps the start's work.
+  // Starts come from a global ticket, taken two starts ahead by thread 0:
+  // when a start begins, thread 0 loads the entry of the next start (its
+  // ticket taken one start earlier) and takes the ticket of the one after,
+  // so neither round trip delays the workgroup between starts.
   // (code -1: none left; a real code has rank < 2^30 - 1)
   auto entry_of = [&](uint32_t i) { return (int32_t)i < p.n_list ? p.list[i] : make_int4(-1, 0, 0, 0); };
-  if (t == 0) s_entry = entry_of(atomicAdd(p.ticket, 1u));
+  uint32_t ticket_next = 0;
+  if (t == 0) {
+    s_entry = entry_of(atomicAdd(p.ticket, 1u));
+    ticket_next = atomicAdd(p.ticket, 1u);
+  }
   for (;;) {
     __syncthreads();
     const int4 ent = s_entry;
     __syncthreads();
     if (ent.x == -1) break;
-    uint32_t next_ticket = 0;
-    if (t == 0) next_ticket = atomicAdd(p.ticket, 1u);
+    int4 next_entry = make_int4(-1, 0, 0, 0);
+    if (t == 0) {
+      next_entry = entry_of(ticket_next);
+      ticket_next = atomicAdd(p.ticket, 1u);
+    }
     // the entry is the same in every lane: keep it (and what derives from
     // it) in scalar registers
     const int32_t code = __builtin_amdgcn_readfirstlane(ent.x);
@@ -849,6 +861,15 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     // Windows: hash windows over [0, hash_end) (width hwidth, adapted as they
     // go), then dense windows of `width` ranks up to sparse_end.
     int32_t width = half ? 2 * kWords : kWords;
+    // dense windows below q8 hold 8-bit counters: four ranks per word (q8
+    // rounded down to even: the 16-bit windows that follow pair ranks from
+    // an even first rank)
+    const int32_t q8 = (x ? p.q8[1] : p.q8[0]) & ~1;
+    auto dense_hi = [&](int32_t lo) -> int32_t {
+      const int64_t h = lo < q8 ? (int64_t)lo + 4 * kWords : (int64_t)lo + width;
+      const int32_t h8 = lo < q8 && h > q8 ? q8 : (int32_t)(h < 0x7FFFFFFF ? h : 0x7FFFFFFF);
+      return h8 >= sparse_end ? sparse_end : h8;
+    };
     int32_t hwidth = 0, hash_end = 0;
     uint32_t cap = kCap;
     if (dense) {
@@ -906,7 +927,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         nxt[j] = ps < pe ? O.adj[ps] : kNone;
       }
     };
-    bool cursors = !(sparse_end == ehi && (hash_end >= ehi ? hwidth >= span : (hash_end == elo && width >= span)));
+    bool cursors = !(sparse_end == ehi && (hash_end >= ehi ? hwidth >= span : (hash_end == elo && dense_hi(elo) >= ehi)));
     // Resident mode: a multi-window start with at most 2 * kNT middles
     // keeps middle 2t + h's slice state in thread t's registers: the end of
     // its list below r (re), the start of its current slice (rcs), and raux
@@ -937,15 +958,17 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     for (;;) {
       int32_t hi_w;
       bool wdense = lo_w >= hash_end;
-      bool whalf = half && wdense;
       const bool seeded = lo_w >= sparse_end;
+      bool wquarter = wdense && !seeded && lo_w < q8;
+      bool whalf = half && wdense && !wquarter;
       if (!seeded) {
-        if (wdense) hi_w = (int64_t)lo_w + width >= sparse_end ? sparse_end : lo_w + width;
+        if (wdense) hi_w = dense_hi(lo_w);
         else hi_w = (int64_t)lo_w + hwidth >= hash_end ? hash_end : lo_w + hwidth;
       } else if (in_block && lo_w < ehi) {
         hi_w = ehi;
         wdense = true;
         whalf = false;
+        wquarter = false;
       } else {
         break;
       }
@@ -1225,7 +1248,16 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
           last_t = T;
           int32_t F0, F1;
           share(T, F0, F1);
-          if (wdense && whalf) {
+          if (wquarter) {
+            // counter w - lo_w: byte (w - lo_w) & 3 of word (w - lo_w) >> 2
+            char* tb = reinterpret_cast<char*>(table);
+            chunk_walk(O.adj, se, sd, nseg, T, &s_ticket, kWaves,
+                       [&](int32_t, int32_t, int32_t w) {
+                         const uint32_t i = (uint32_t)(w - lo_w);
+                         atomicAdd(reinterpret_cast<uint32_t*>(tb + (i & ~3u)), 1u << ((i & 3u) << 3));
+                       },
+                       [] { return false; });
+          } else if (wdense && whalf) {
             // lo_w is even: counter pair (w >> 1) - (lo_w >> 1), half (w & 1):
             // byte offset (w & ~1) * 2 from tw, add 1 or 1 << 16
             char* tw = reinterpret_cast<char*>(table) - 2 * lo_w;
@@ -1325,7 +1357,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
           seg_walk(O.adj, se, sd, nseg, F0, F1,
                    [&](int32_t sg, int32_t slot, int32_t w) {
                      const int32_t c =
-                         wdense ? dense_get(table, w - lo_w, whalf)
+                         wdense ? dense_get(table, w - lo_w, whalf, wquarter)
                                 : (wpacked ? packed_hash_get(reinterpret_cast<const uint32_t*>(table), cap - 1,
                                                              (uint32_t)(w - lo_w + 1))
                                            : hash_get(table, table + cap, cap - 1, w));
@@ -1376,7 +1408,11 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
                  [&](int32_t, int32_t, int32_t w) {
                    const int32_t i = w - lo_w;
                    int32_t c;
-                   if (whalf) {
+                   if (wquarter) {
+                     const uint32_t sh = (uint32_t)(i & 3) << 3;
+                     const uint32_t old = atomicAnd(reinterpret_cast<uint32_t*>(&table[i >> 2]), ~(0xFFu << sh));
+                     c = (int32_t)((old >> sh) & 0xFFu);
+                   } else if (whalf) {
                      const uint32_t sh = (uint32_t)(i & 1) << 4;
                      const uint32_t old = atomicAnd(reinterpret_cast<uint32_t*>(&table[i >> 1]), ~(0xFFFFu << sh));
                      c = (int32_t)((old >> sh) & 0xFFFFu);
@@ -1386,6 +1422,30 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
                    if (c > 1) start_acc += choose2(c);
                  },
                  [] { return false; });
+      } else if (wquarter && mode != kVertex) {
+        // sum of c (c - 1) over the 8-bit counters, branch-free (c (c - 1)
+        // is 0 for c = 0 or 1); the sum is even and halves exactly
+        const int32_t words = (hi_w - lo_w + 3) >> 2;
+        const int32_t quads = (words + 3) >> 2;
+        uint4* t4 = reinterpret_cast<uint4*>(table);
+        unsigned long long twice = 0;
+        for (int32_t i4 = t; i4 < quads; i4 += kNT) {
+          const uint4 q4 = t4[i4];
+          if ((q4.x | q4.y | q4.z | q4.w) == 0u) continue;
+          const uint32_t wd[4] = {q4.x, q4.y, q4.z, q4.w};
+          uint32_t part = 0;  // at most 16 x 255 x 254 < 2^21
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const uint32_t n = (wd[c] >> (8 * b)) & 0xFFu;
+              part += __umul24(n, n) - n;
+            }
+          }
+          twice += part;
+          t4[i4] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        start_acc += twice >> 1;
       } else if (wdense && whalf && mode != kVertex) {
         // sum of c (c - 1) over the 16-bit counters: c (c - 1) < 2^32 is
         // exact in a 24-bit multiply and is 0 for c = 0 or 1, so no branch
@@ -1409,7 +1469,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         start_acc += twice >> 1;
       } else if (wdense) {
         const int32_t wn = hi_w - lo_w;
-        const int32_t words = whalf ? (wn + 1) >> 1 : wn;
+        const int32_t words = wquarter ? (wn + 3) >> 2 : whalf ? (wn + 1) >> 1 : wn;
         const int32_t quads = (words + 3) >> 2;
         uint4* t4 = reinterpret_cast<uint4*>(table);
         for (int32_t i4 = t; i4 < quads; i4 += kNT) {
@@ -1421,7 +1481,17 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
             const uint32_t word = wd[c];
             if (!word) continue;
             const int32_t i = 4 * i4 + c;
-            if (whalf) {
+            if (wquarter) {
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                const int32_t cb = (int32_t)((word >> (8 * b)) & 0xFFu);
+                if (cb > 1) {
+                  const unsigned long long cc = choose2(cb);
+                  start_acc += cc;
+                  if (mode == kVertex) atomicAdd(&vs[lo_w + 4 * i + b], cc);
+                }
+              }
+            } else if (whalf) {
               const int32_t c0 = (int32_t)(word & 0xFFFFu), c1 = (int32_t)(word >> 16);
               if (c0 > 1) {
                 const unsigned long long cc = choose2(c0);
@@ -1506,7 +1576,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     } else {
       acc_total += start_acc;
     }
-    if (t == 0) s_entry = entry_of(next_ticket);
+    if (t == 0) s_entry = next_entry;
   }
   if (mode == kTotal && p.total) {
     const unsigned long long s = block_sum<unsigned long long, kNT>(acc_total, s_red64);
@@ -1721,6 +1791,8 @@ void count(bfc_graph_s* g, CountMode mode, int64_t* total_dev, int64_t* out0, in
   // Algorithm 3's per-start work (read when a list entry's clamps)
   if (sc.vpp & 1) p.sv[0].work = g->side[0].wpp.as<int64_t>();
   if (sc.vpp & 2) p.sv[1].work = g->side[1].wpp.as<int64_t>();
+  p.q8[0] = g->byte_rank[0];
+  p.q8[1] = g->byte_rank[1];
   // top bands: band starts' own-part work, band items' work and slice bounds
   for (int x = 0; x < 2; ++x) {
     p.band_lo[x] = 0;

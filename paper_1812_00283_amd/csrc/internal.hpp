@@ -208,7 +208,8 @@ struct bfc_graph_s {
   int32_t n_graphs = 1;
   bfc::DevBuf gid[2];
   bfc::DevBuf grank[2];   // per layer: first rank of each graph (G + 1), batches only
-  // build status (int32 [8]) and schedule totals (int64 [16] from byte 64),
+  // build status (int32 [10]: [8 + x] the first rank of degree >= 256 in layer x)
+  // and schedule totals (int64 [16] from byte 64),
   // the caterpillar partial sums (from byte kInfoCaterpillars), read back once
   // when the build is complete
   bfc::DevBuf info;
@@ -220,6 +221,10 @@ struct bfc_graph_s {
   int32_t key_span[2] = {-1, -1};  // largest layer of one graph of a batch (-1: one graph)
   int32_t light_max_cap() const { return light_packed ? 2048 : 1024; }
   int64_t rows_max[2] = {0, 0};  // window-table rows allocated per layer
+  // per layer: the vertices of rank below byte_rank have degree < 256, so as
+  // ends their counts fit 8-bit dense counters (0 in a batch, whose ranks
+  // do not follow degree across graphs)
+  int32_t byte_rank[2] = {0, 0};
   int32_t max_deg[2] = {0, 0};   // largest degree per layer
   // per-edge counts accumulate in 32-bit words while every B_e fits:
   // B_e <= (d_u - 1)(d_v - 1) <= (max_deg[0] - 1)(max_deg[1] - 1) < 2^32

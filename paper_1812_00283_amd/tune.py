@@ -84,11 +84,14 @@ def graph_buckets(edges: np.ndarray, offsets, n_upper, n_lower) -> list[str]:
 
 
 def tune_batch(edges: np.ndarray, offsets, n_upper, n_lower, sample_edges: int = 20_000_000,
-               candidates: dict | None = None, seed: int = 0, log=None) -> dict:
+               candidates: dict | None = None, seed: int = 0, log=None, min_gain: float = 0.03) -> dict:
     """Per bucket, the candidate setting with the fastest total count of a
     seeded sample of the bucket's graphs (one batch handle per sample).
-    Coordinate search: one field at a time, in the order of `candidates`,
-    keeping the best value of each.  Returns {bucket: {field: value}}."""
+    Coordinate search: one field at a time, in the order of `candidates`; a
+    value replaces the setting kept so far only when it counts at least
+    `min_gain` faster (timing noise does not install per-graph settings,
+    which cost a schedule rebuild).  A bucket whose defaults win keeps an
+    empty setting.  Returns {bucket: {"tuning": {field: value}, ...}}."""
     cand = candidates or BATCH_CANDIDATES
     offsets = np.asarray(offsets, dtype=np.int64)
     buckets = graph_buckets(edges, offsets, n_upper, n_lower)
@@ -112,16 +115,20 @@ def tune_batch(edges: np.ndarray, offsets, n_upper, n_lower, sample_edges: int =
         off[1:] = np.cumsum([offsets[i + 1] - offsets[i] for i in pick])
         dev = torch.from_numpy(np.ascontiguousarray(e)).cuda()
         with bfc.build_batch(dev, off, [int(n_upper[i]) for i in pick], [int(n_lower[i]) for i in pick]) as h:
+            defaults = h.get_tuning()
             best = {}
-            base_ms = time_count(h)
+            base_ms = best_ms = time_count(h, reps=3)
             for field, values in cand.items():
-                res = {}
                 for v in values:
-                    h.set_tuning(**{**best, field: v})
-                    res[v] = time_count(h)
-                best[field] = min(res, key=res.get)
-            h.set_tuning(**best)
-            tuned_ms = time_count(h)
+                    if v == best.get(field, defaults[field]):
+                        continue
+                    h.set_tuning(**{**defaults, **best, field: v})
+                    ms = time_count(h, reps=3)
+                    if ms < best_ms * (1.0 - min_gain):
+                        best[field] = v
+                        best_ms = ms
+            h.set_tuning(**{**defaults, **best})
+            tuned_ms = time_count(h, reps=3)
         table[b] = {"tuning": best, "graphs": len(idx), "sample_graphs": len(pick), "sample_edges": tot,
                     "default_ms": base_ms, "tuned_ms": tuned_ms}
         if log:
@@ -130,10 +137,14 @@ def tune_batch(edges: np.ndarray, offsets, n_upper, n_lower, sample_edges: int =
     return table
 
 
-def apply_table(h: bfc.Graph, table: dict, buckets: list[str]) -> None:
-    """Installs each graph's bucket setting on a batch handle."""
+def apply_table(h: bfc.Graph, table: dict, buckets: list[str]) -> bool:
+    """Installs each graph's bucket setting on a batch handle; installs
+    nothing (and returns False) when every bucket keeps the defaults."""
     per_graph = [table.get(b, {}).get("tuning", {}) for b in buckets]
+    if not any(per_graph):
+        return False
     h.set_graph_tuning(per_graph)
+    return True
 
 
 def save(table: dict, path: str) -> None:

@@ -208,6 +208,16 @@ def test_hub_graph_every_kernel_path(gpu_lib, hub_graph, hub_oracle, name):
     np.testing.assert_array_equal(be, o_be)
 
 
+def test_byte_counters_at_their_limit(gpu_lib):
+    """Ends of degree up to 255 count in 8-bit dense counters: complete
+    bipartite graphs where a pair's count reaches exactly 255 (and layers of
+    degree 256, which keep 16-bit counters), on dense windows and defaults."""
+    for a, b in [(300, 255), (255, 300), (256, 256), (257, 255), (40, 255)]:
+        g = gg.complete_bipartite(a, b)
+        for tun in (None, {"light_max_wedges": 1, "window_mode": 2}, {"light_max_wedges": 1, "vpp": 3}):
+            check_against_oracle(gpu_lib, g, tun)
+
+
 def test_mfma_block_covers_whole_small_graphs(gpu_lib):
     """Block sizes at or above the layer sizes: every start is in the block."""
     for a, b in [(3, 5), (40, 60), (64, 64), (100, 37)]:
