@@ -209,10 +209,12 @@ def test_hub_graph_every_kernel_path(gpu_lib, hub_graph, hub_oracle, name):
 
 
 def test_byte_counters_at_their_limit(gpu_lib):
-    """Ends of degree up to 255 count in 8-bit dense counters: complete
+    """Ends of degree below 256 count in 8-bit dense counters: complete
     bipartite graphs where a pair's count reaches exactly 255 (and layers of
-    degree 256, which keep 16-bit counters), on dense windows and defaults."""
-    for a, b in [(300, 255), (255, 300), (256, 256), (257, 255), (40, 255)]:
+    degree 256, which keep 16-bit counters), and small degrees, on dense
+    windows and defaults."""
+    for a, b in [(300, 255), (255, 300), (256, 256), (257, 255), (40, 255), (60, 15), (15, 60), (16, 16),
+                 (50, 3), (3, 50), (4, 4), (17, 4)]:
         g = gg.complete_bipartite(a, b)
         for tun in (None, {"light_max_wedges": 1, "window_mode": 2}, {"light_max_wedges": 1, "vpp": 3}):
             check_against_oracle(gpu_lib, g, tun)
