@@ -29,21 +29,22 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 DEFAULT_WORKLOAD = "chunglu-1m-500k-20m"
 
-# HBM traffic of one heavy-kernel launch on the default workload, from
-# rocprofv3 --pmc runs (mean of 3 dispatches): TCC_EA0_RDREQ_sum read
-# requests (none of them 32-byte requests, TCC_BUBBLE_sum about 30), each
-# 128 bytes -- a plain 1 GiB device-to-device copy issues 8,388,792 such
+# HBM traffic of one heavy-kernel launch per workload, from rocprofv3 --pmc
+# runs (mean over the profiled dispatches): TCC_EA0_RDREQ_sum read requests
+# (none of them 32-byte requests, TCC_BUBBLE_sum a few hundred), each 128
+# bytes -- a plain 1 GiB device-to-device copy issues 8,388,792 such
 # requests, and FETCH_SIZE counts them as 64 bytes, hence its factor 2 --
 # and, in a separate run, WRITE_SIZE (KiB, factor 1.0 on the same copy).
 # Reported only while the heavy kernel's sources hash to the value they were
-# measured with (any change voids the figure).
+# measured with (any change voids the figures).
 HEAVY_TRAFFIC = {
-    "workload": DEFAULT_WORKLOAD,
-    "sources_sha256": "7a98f2f4e0e1def5fd5deb1074a6a901abacdc275c405ad46542e86d7aea612d",
-    "read_requests": 270466575.7,
+    "sources_sha256": "d67df80dbaafde9f644eabb465972c2b9ba473d1cd351739f5a58c46ff5cede3",
     "bytes_per_read_request": 128.0,
-    "write_kib": 892015.0,
     "write_factor": 1.0,
+    "workloads": {
+        DEFAULT_WORKLOAD: {"read_requests": 249467827.3, "write_kib": 1405238.0},
+        "chunglu-16m-4m-200m-planted": {"read_requests": 9494341729.0, "write_kib": 64676178.0},
+    },
 }
 
 
@@ -73,12 +74,14 @@ def sources_sha256() -> str:
 
 
 def heavy_traffic(workload: str, tuned: bool):
-    """Measured HBM bytes per heavy-kernel launch, or None when they do not
-    apply (other workload, tuning, or sources changed since the counters)."""
+    """Measured HBM bytes per heavy-kernel launch (default settings), or None
+    when they do not apply (other workload, tuning, or sources changed since
+    the counters)."""
     t = HEAVY_TRAFFIC
-    if tuned or workload != t["workload"] or sources_sha256() != t["sources_sha256"]:
+    w = t["workloads"].get(workload)
+    if tuned or w is None or sources_sha256() != t["sources_sha256"]:
         return None
-    return t["read_requests"] * t["bytes_per_read_request"] + 1024.0 * t["write_kib"] * t["write_factor"]
+    return w["read_requests"] * t["bytes_per_read_request"] + 1024.0 * w["write_kib"] * t["write_factor"]
 
 
 def golden_caterpillars(name: str):
@@ -255,7 +258,8 @@ def secondary_record(name: str, steps: int, warmup: int) -> dict:
             "tuning": tun or "default", "ms_per_step": ms_step, "wedges_per_s": wed / (ms_step / 1e3),
             "count_ms": 1e3 * float(np.median(count_s)), "heavy_ms": hk,
             "heavy_roofline": {"achieved": hb / (hk / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": hb / (hk / 1e3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": hb},
+                               "frac": hb / (hk / 1e3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": hb,
+                               "traffic": heavy_traffic(name, bool(tun and any(tun.values())))},
             "butterflies": tot, "wedges": wed, "exact_vs_oracle": bool(gold and gold[0] == tot and gold[1] == wed),
         }
     return rec
