@@ -696,6 +696,7 @@ def main() -> int:
         },
         "count_ms": count_ms,
         "build_ms": ms_step - count_ms,
+        "library_built_from_current_sources": bfc.library_matches_sources(),
         "count_only_wedges_per_s": wedges / (count_ms / 1000.0),
         "count_phase_roofline": {
             "algorithmic_bytes": 4 * wedges + 16 * g.m + 8 * (g.n_upper + g.n_lower),

@@ -8,6 +8,7 @@ library has not been built, ``load()`` raises; there is no fallback.
 from __future__ import annotations
 
 import ctypes
+import sys
 import os
 
 import torch
@@ -68,6 +69,18 @@ class KernelTimes(ctypes.Structure):
                 ("other_ms", ctypes.c_double)]
 
 
+def library_matches_sources() -> bool:
+    """Whether the in-tree libbfc.so was built from the sources now in the
+    tree (the digest its build recorded beside it)."""
+    from . import build as _build
+
+    try:
+        with open(LIB_PATH + ".sources") as f:
+            return f.read().strip() == _build.sources_digest()
+    except OSError:
+        return False
+
+
 def load(path: str | None = None, torch_memory: bool = True):
     """Loads libbfc.so; raises if it has not been built.  With torch_memory
     (the default) the library takes its device memory from PyTorch's caching
@@ -78,6 +91,9 @@ def load(path: str | None = None, torch_memory: bool = True):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"{p} is missing: build it with `python -m paper_1812_00283_amd.build`")
+    if path is None and not library_matches_sources():
+        print(f"warning: {p} was not built from the current sources (rebuild with "
+              "`python -m paper_1812_00283_amd.build`)", file=sys.stderr, flush=True)
     lib = ctypes.CDLL(p)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     pi64, pi32 = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)

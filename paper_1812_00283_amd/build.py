@@ -22,6 +22,21 @@ SOURCES = ["alloc.hip", "primitives.hip", "build.hip", "count.hip", "dense.hip",
 ARCH = "gfx950"
 
 
+def sources_digest() -> str:
+    """sha256 over the library's sources (csrc/ and include/, by name), which
+    build() records beside the library so a stale build can be detected."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for d in (CSRC, INCLUDE):
+        for n in sorted(os.listdir(d)):
+            if n.endswith((".hip", ".hpp", ".h")):
+                h.update(n.encode())
+                with open(os.path.join(d, n), "rb") as f:
+                    h.update(f.read())
+    return h.hexdigest()
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -41,6 +56,7 @@ def flags() -> list[str]:
 def build(verbose: bool = False, jobs: int = 4) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     cc = hipcc()
+    digest = sources_digest()  # of the sources this build compiles
 
     def one(src: str) -> str:
         obj = os.path.join(OBJDIR, src.replace(".hip", ".o"))
@@ -64,6 +80,8 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    with open(LIB + ".sources", "w") as f:
+        f.write(digest + "\n")
     return LIB
 
 
