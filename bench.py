@@ -292,6 +292,8 @@ def bench_batch(args) -> int:
     tune_s = time.perf_counter() - t
     log(f"tuned {len(table)} buckets in {tune_s:.1f}s")
 
+    installed = []
+
     def batched(tuned: bool):
         """Steps of batched build (+ per-graph settings) + captured count,
         replayed; returns (build s, count s, totals, wedges)."""
@@ -302,7 +304,7 @@ def bench_batch(args) -> int:
             t0 = time.perf_counter()
             h = bfc.build_batch(edges, b.offsets, b.n_upper, b.n_lower, stream)
             if tuned:
-                tune.apply_table(h, table, buckets)
+                installed.append(tune.apply_table(h, table, buckets))
             t1 = time.perf_counter()
             h.capture_total(totals, stream)
             torch.cuda.synchronize()
@@ -355,9 +357,9 @@ def bench_batch(args) -> int:
         "batched_count_ms": 1e3 * t_count,
         "default_tuning": {"graphs_per_s": b.count / (d_build + d_count), "build_ms": 1e3 * d_build,
                            "count_ms": 1e3 * d_count},
-        "tuner": {"seconds": tune_s, "buckets": {k: {kk: v[kk] for kk in ("tuning", "graphs", "default_ms",
-                                                                            "tuned_ms")}
-                                                 for k, v in table.items()}},
+        "tuner": {"seconds": tune_s, "installed": bool(installed and installed[-1]),
+                  "buckets": {k: {kk: v[kk] for kk in ("tuning", "graphs", "default_ms", "tuned_ms", "est_saving_ms")}
+                              for k, v in table.items()}},
         "plain_graphs_per_s": b.count / plain_s, "plain_ms": 1e3 * plain_s,
         "speedup_vs_plain": plain_s / batched_s,
         "capture": "count only: the build waits on the device twice (degree check, schedule sizes), so it is "

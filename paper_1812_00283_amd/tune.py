@@ -129,17 +129,23 @@ def tune_batch(edges: np.ndarray, offsets, n_upper, n_lower, sample_edges: int =
                         best_ms = ms
             h.set_tuning(**{**defaults, **best})
             tuned_ms = time_count(h, reps=3)
+        # the saving scaled from the sample to the bucket's graphs
+        saving = max(base_ms - tuned_ms, 0.0) * len(idx) / len(pick) if best else 0.0
         table[b] = {"tuning": best, "graphs": len(idx), "sample_graphs": len(pick), "sample_edges": tot,
-                    "default_ms": base_ms, "tuned_ms": tuned_ms}
+                    "default_ms": base_ms, "tuned_ms": tuned_ms, "est_saving_ms": saving}
         if log:
             log(f"tune {b}: {len(pick)} of {len(idx)} graphs, {tot} edges: default {base_ms:.2f} ms, "
                 f"tuned {tuned_ms:.2f} ms with {best}")
     return table
 
 
-def apply_table(h: bfc.Graph, table: dict, buckets: list[str]) -> bool:
-    """Installs each graph's bucket setting on a batch handle; installs
-    nothing (and returns False) when every bucket keeps the defaults."""
+def apply_table(h: bfc.Graph, table: dict, buckets: list[str], min_saving_ms: float = 10.0) -> bool:
+    """Installs each graph's bucket setting on a batch handle when the
+    buckets' estimated savings add up to at least `min_saving_ms` per count
+    (installing rebuilds the schedule: about 8 ms on the 4,096-graph batch of
+    5.9e8 edges); otherwise installs nothing and returns False."""
+    if sum(v.get("est_saving_ms", 0.0) for v in table.values()) < min_saving_ms:
+        return False
     per_graph = [table.get(b, {}).get("tuning", {}) for b in buckets]
     if not any(per_graph):
         return False
