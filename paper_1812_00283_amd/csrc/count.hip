@@ -751,7 +751,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
   __shared__ __align__(16) int32_t table[kWords];
   __shared__ __align__(16) int32_t segbuf[kSW];
   __shared__ unsigned long long s_red64[kWaves + 1];
-  __shared__ int32_t s_fill, s_over, s_cut_j, s_cut_lex;
+  __shared__ int32_t s_fill, s_over, s_cut_j, s_cut_lex, s_nact;
   __shared__ int4 s_entry;      // the next start's list entry (code -1: none left)
   __shared__ int32_t s_ticket;  // chunk ticket of the dense walk
   __shared__ unsigned long long s_emit;  // resident emission: count << 32 | total length
@@ -760,11 +760,15 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
   const int lane = __lane_id();
   const int wv = t >> 6;
   constexpr int mode = kMode;
-  // per-middle cursor state of multi-window starts: next slot, end id at
-  // that slot (kNone when exhausted), and the window's end slot
-  int32_t* pos = p.cursor + (int64_t)blockIdx.x * 3 * p.cursor_stride;
-  int32_t* nxt = pos + p.cursor_stride;
-  int32_t* cend = nxt + p.cursor_stride;
+  // per-middle cursor state of multi-window starts, one 16-byte record per
+  // middle: {middle, end of its slice, next slot (the slice's first slot for
+  // a table middle), end id at that slot (kNone when exhausted)}, so a sweep
+  // reads each middle's state with one coalesced load; and the window's end
+  // slot per middle
+  int4* rec = reinterpret_cast<int4*>(p.cursor + (int64_t)blockIdx.x * 7 * p.cursor_stride);
+  int32_t* cend = reinterpret_cast<int32_t*>(rec + p.cursor_stride);
+  // a window's non-empty slices [cs, ce) of such a start, in any order
+  int2* act = reinterpret_cast<int2*>(cend + p.cursor_stride);
   for (int i = t; i < kWords; i += kNT) table[i] = 0;
   unsigned long long acc_total = 0;
 
@@ -922,9 +926,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
       for (int32_t j = t; j < pre; j += kNT) {
         int32_t v, ps, pe;
         mid_slice(vpp, S, O, base + j, j, lo_r, clb, v, ps, pe);
-        if (v >= tfirst) continue;
-        pos[j] = ps;
-        nxt[j] = ps < pe ? O.adj[ps] : kNone;
+        rec[j] = make_int4(v, pe, ps, v >= tfirst ? 0 : (ps < pe ? O.adj[ps] : kNone));
       }
     };
     bool cursors = !(sparse_end == ehi && (hash_end >= ehi ? hwidth >= span : (hash_end == elo && dense_hi(elo) >= ehi)));
@@ -992,9 +994,24 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
                       unsigned long long* sdel, int32_t& rj, int32_t& nseg, int32_t& T) {
         nseg = 0;
         T = 0;
+        // cursor records of this sweep's middles, and of the next sweep's,
+        // loaded before this one is compacted (the usual next sweep)
+        int4 pf[kFill];
+        auto load_rec = [&](int32_t j0) {
+#pragma unroll
+          for (int h = 0; h < kFill; ++h) {
+            const int32_t j = j0 + kFill * t + h;
+            pf[h] = (cursors && j < npre) ? rec[j] : make_int4(0, 0, 0, 0);
+          }
+        };
+        load_rec(rj);
         while (nseg < segcap && rj < npre) {
           int32_t jv[kFill], csv[kFill], cev[kFill], ev[kFill], vv[kFill];
           bool actv[kFill];
+          int4 rc[kFill];
+#pragma unroll
+          for (int h = 0; h < kFill; ++h) rc[h] = pf[h];
+          if (cursors && npre - rj > kFill * kNT) load_rec(rj + kFill * kNT);
 #pragma unroll
           for (int h = 0; h < kFill; ++h) {
             const int32_t j = rj + kFill * t + h;
@@ -1002,10 +1019,16 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
             actv[h] = false;
             csv[h] = cev[h] = ev[h] = vv[h] = 0;
             if (j < npre) {
-              int32_t v, s0, e;
-              mid_slice(vpp, S, O, base + j, j, lo_r, clb, v, s0, e);
-              const int32_t pj = cursors ? pos[j] : 0;  // cursor state (meaningful below tfirst)
-              const int32_t nj = cursors ? nxt[j] : kNone;
+              int32_t v, s0, e, pj = 0, nj = kNone;  // cursor state (meaningful below tfirst)
+              if (cursors) {
+                v = rc[h].x;
+                e = rc[h].y;
+                pj = rc[h].z;
+                nj = rc[h].w;
+                s0 = rc[h].z;  // (a table middle's record keeps its first slot)
+              } else {
+                mid_slice(vpp, S, O, base + j, j, lo_r, clb, v, s0, e);
+              }
               ev[h] = e;
               vv[h] = v;
               if (!cursors) {
@@ -1060,8 +1083,8 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
               }
               if (cursors && vv[h] < tfirst) {
                 if (second || advance_now) {
-                  pos[jv[h]] = cev[h];
-                  nxt[jv[h]] = cev[h] < ev[h] ? O.adj[cev[h]] : kNone;
+                  *reinterpret_cast<int2*>(&rec[jv[h]].z) =
+                      make_int2(cev[h], cev[h] < ev[h] ? O.adj[cev[h]] : kNone);
                 } else {
                   cend[jv[h]] = cev[h];
                 }
@@ -1201,9 +1224,107 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         bool over = false;
         batches = 0;
         if (resident) res_slices();
-        while (rj < pre1) {
+        // A cursor start's window: every middle's slice in one barrier-free
+        // pass (kA middles per thread and round, their loads issued
+        // together), the non-empty ones appended to `act` with one LDS
+        // atomic per wavefront and round; batches then take kS1 of them.
+        const bool compact = cursors && !resident && !seeded;
+        int32_t n_act = 0;
+        if (compact) {
+          constexpr int kA = 4;
+          if (t == 0) s_nact = 0;
+          __syncthreads();
+          for (int32_t j0 = 0; j0 < pre1; j0 += kA * kNT) {
+            int4 rc[kA];
+#pragma unroll
+            for (int a = 0; a < kA; ++a) {
+              const int32_t j = j0 + a * kNT + t;
+              rc[a] = j < pre1 ? rec[j] : make_int4(0, 0, 0, kNone);
+            }
+#pragma unroll
+            for (int a = 0; a < kA; ++a) {
+              const int32_t j = j0 + a * kNT + t;
+              const int32_t v = rc[a].x, e = rc[a].y;
+              int32_t cs = 0, ce = 0;
+              bool ac = false;
+              if (j < pre1) {
+                if (v >= tfirst) {
+                  const int32_t* rowp = tab + (int64_t)(v - tfirst) * trow;
+                  cs = table_lb(O.adj, rowp, lo_w);
+                  if (vpp || clb) cs = cs > rc[a].z ? cs : rc[a].z;  // (rc.z: the slice's first slot)
+                  ce = e;
+                  if (hi_w < ehi) {
+                    const int32_t c2 = table_lb(O.adj, rowp, hi_w);
+                    ce = c2 < e ? c2 : e;
+                  }
+                  ac = ce > cs;
+                } else if (rc[a].w < hi_w) {
+                  cs = rc[a].z;  // O.adj[cs] = rc.w < hi_w
+                  int32_t nv = kNone;  // end id at ce (the search returns it)
+                  if (hi_w >= ehi) {
+                    ce = e;
+                  } else {
+                    ce = near_lower_bound_v(O.adj, cs + 1, e, hi_w, nv);
+                    if (ce >= e) nv = kNone;
+                  }
+                  ac = true;
+                  if (advance_now) *reinterpret_cast<int2*>(&rec[j].z) = make_int2(ce, nv);
+                  else cend[j] = ce;
+                }
+              }
+              const uint64_t bal = __ballot(ac);
+              int32_t wb = 0;
+              if (lane == 0 && bal) wb = atomicAdd(&s_nact, (int32_t)__popcll(bal));
+              wb = __shfl(wb, 0, 64);
+              if (ac) act[mbcnt(bal, wb)] = make_int2(cs, ce);
+            }
+          }
+          __syncthreads();
+          n_act = s_nact;
+        }
+        while (compact ? rj < n_act : rj < pre1) {
           int32_t nseg, T;
-          if (resident) {
+          if (compact) {
+            // batch [rj, rj + kS1) of the window's slices: two per thread,
+            // positions from a wavefront scan and one LDS atomic per wavefront
+            if (t == 0) s_emit = 0ull;
+            __syncthreads();
+            const int32_t i0 = rj + 2 * t, i1 = i0 + 1;
+            const int32_t lim = n_act - rj < kS1 ? n_act : rj + kS1;
+            int2 c0 = make_int2(0, 0), c1 = make_int2(0, 0);
+            if (i0 < lim) c0 = act[i0];
+            if (i1 < lim) c1 = act[i1];
+            const uint32_t l0 = (uint32_t)(c0.y - c0.x), l1 = (uint32_t)(c1.y - c1.x);
+            const unsigned long long v =
+                ((unsigned long long)((int)(i0 < lim) + (int)(i1 < lim)) << 32) | (l0 + l1);
+            const unsigned long long inc = wave_inclusive_scan(v);
+            const unsigned long long wt = __shfl(inc, 63, 64);
+            unsigned long long wb = 0;
+            if (lane == 63 && wt) wb = atomicAdd(&s_emit, wt);
+            wb = __shfl(wb, 63, 64);
+            unsigned long long at = wb + inc - v;
+            if (i0 < lim) {
+              const int32_t ps = (int32_t)(at >> 32), L = (int32_t)(uint32_t)at;
+              se[ps] = L;
+              sd[ps] = c0.x - L;
+              at += (1ull << 32) | l0;
+            }
+            if (i1 < lim) {
+              const int32_t ps = (int32_t)(at >> 32), L = (int32_t)(uint32_t)at;
+              se[ps] = L;
+              sd[ps] = c1.x - L;
+            }
+            __syncthreads();
+            const unsigned long long all = s_emit;
+            nseg = (int32_t)(all >> 32);
+            T = (int32_t)(uint32_t)all;
+            if (t == 0) {
+              se[nseg] = T;
+              s_ticket = 0;
+            }
+            __syncthreads();
+            rj = lim;
+          } else if (resident) {
             {
               // every slice fits one batch, in any order: each wavefront
               // reserves its entries and positions with one LDS atomic
@@ -1388,12 +1509,10 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
       } else if (cursors && !advance_now && !resident) {
         // hash window of a total count: advance the cursors now that the window is final
         for (int32_t j = t; j < pre1; j += kNT) {
-          int32_t v, s0, e;
-          mid_slice(vpp, S, O, base + j, j, lo_r, clb, v, s0, e);
-          if (v < tfirst && nxt[j] < hi_w) {
+          const int4 r4 = rec[j];
+          if (r4.x < tfirst && r4.w < hi_w) {
             const int32_t ce = cend[j];
-            pos[j] = ce;
-            nxt[j] = ce < e ? O.adj[ce] : kNone;
+            *reinterpret_cast<int2*>(&rec[j].z) = make_int2(ce, ce < r4.y ? O.adj[ce] : kNone);
           }
         }
       }
@@ -1636,8 +1755,10 @@ int64_t cursor_stride_for(const bfc_graph_s* g) { return ((int64_t)g->sched.max_
 
 // scratch: three cursor arrays per big workgroup, three per medium workgroup
 // (stride kMedPre), then 256 bytes: the two tickets
-size_t big_wg_bytes(const bfc_graph_s* g) { return 3 * (size_t)cursor_stride_for(g) * sizeof(int32_t); }
-size_t med_wg_bytes() { return 3 * (size_t)kMedPre * sizeof(int32_t); }
+// per workgroup and middle: a 16-byte cursor record, a window end slot and
+// an 8-byte slice of the window's compacted list
+size_t big_wg_bytes(const bfc_graph_s* g) { return 7 * (size_t)cursor_stride_for(g) * sizeof(int32_t); }
+size_t med_wg_bytes() { return 7 * (size_t)kMedPre * sizeof(int32_t); }
 size_t big_cursor_bytes(const bfc_graph_s* g) { return (size_t)big_grid_for(g) * big_wg_bytes(g); }
 size_t med_cursor_bytes(const bfc_graph_s* g) { return (size_t)med_grid_for(g) * med_wg_bytes(); }
 
