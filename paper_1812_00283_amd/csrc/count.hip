@@ -498,8 +498,7 @@ constexpr int kBigNT = 1024;
 constexpr int kBigWords = 32768;
 constexpr int kMedNT = 256;
 constexpr int kMedWords = 8192;
-constexpr int kMedPre = kMediumMaxPre;  // = 2 * kMedNT: medium starts keep their middles resident
-static_assert(kMedPre == 2 * kMedNT, "medium starts must fit the resident mode");
+constexpr int kMedPre = kMediumMaxPre;  // middles of a medium start (its cursor stride)
 constexpr int32_t kNone = 0x7FFFFFFF;       // "no further end" in a middle's cursor
 
 // Inserts end w into the workgroup hash table (count 1, or bumps its count).
@@ -744,7 +743,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
   constexpr int kWaves = kNT / 64;
   constexpr int kCap = kWords / 2;          // hash entries (keys | counts)
   constexpr int kSingleMax = kCap / 2;      // one hash window suffices below this many wedges
-  constexpr int kS1 = 2 * kNT;              // segment list capacity, pass 1 (and resident middles)
+  constexpr int kS1 = 2 * kNT;              // segment list capacity, pass 1
   constexpr int kS2 = kNT;                  // segment list capacity, pass 2
   constexpr int kFill = 2;                  // middles per thread and sweep of a segment-list fill (4 measured slower: sweeps past the list capacity redo their cut middles)
   constexpr int kSW = ((2 * kS1 + 1 > 5 * kS2 + 2 ? 2 * kS1 + 1 : 5 * kS2 + 2) + 3) / 4 * 4;
@@ -754,7 +753,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
   __shared__ int32_t s_fill, s_over, s_cut_j, s_cut_lex, s_nact;
   __shared__ int4 s_entry;      // the next start's list entry (code -1: none left)
   __shared__ int32_t s_ticket;  // chunk ticket of the dense walk
-  __shared__ unsigned long long s_emit;  // resident emission: count << 32 | total length
+  __shared__ unsigned long long s_emit;  // batch emission: count << 32 | total length
 
   const int t = threadIdx.x;
   const int lane = __lane_id();
@@ -930,31 +929,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
       }
     };
     bool cursors = !(sparse_end == ehi && (hash_end >= ehi ? hwidth >= span : (hash_end == elo && dense_hi(elo) >= ehi)));
-    // Resident mode: a multi-window start with at most 2 * kNT middles
-    // keeps middle 2t + h's slice state in thread t's registers: the end of
-    // its list below r (re), the start of its current slice (rcs), and raux
-    // = the middle's table row offset (>= 0) or -1 - (end id at rcs).  A
-    // window's slice ends (rce, and rnv = end id there) are computed from
-    // these, and committed once the window is final.
-    const bool resident = cursors && pre <= 2 * kNT;
-    int32_t re[2], rcs[2], raux[2], rce[2], rnv[2];
-    if (resident) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int32_t j = 2 * t + h;
-        re[h] = rcs[h] = rce[h] = 0;
-        raux[h] = rnv[h] = -1 - kNoEnd;
-        if (j < pre) {
-          int32_t v, cs, e;
-          mid_slice(vpp, S, O, base + j, j, lo_r, clb, v, cs, e);
-          re[h] = e;
-          rcs[h] = rce[h] = cs;
-          raux[h] = v >= tfirst ? (v - tfirst) * trow : -1 - (cs < e ? O.adj[cs] : kNoEnd);
-        }
-      }
-    } else if (cursors) {
-      init_cursors();
-    }
+    if (cursors) init_cursors();
     unsigned long long start_acc = 0;
     int32_t lo_w = elo;
     for (;;) {
@@ -1116,102 +1091,6 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         F1 = (int32_t)((int64_t)T * (wv + 1) / kWaves);
       };
 
-      // Resident mode: slice ends of window [lo_w, hi_w) for the thread's middles.
-      auto res_slices = [&] {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int32_t e = re[h], cs = rcs[h];
-          int32_t ce = cs, nv = -1 - raux[h];
-          if (cs < e) {
-            if (raux[h] >= 0) {
-              if (hi_w >= ehi) {
-                ce = e;
-              } else {
-                // (Algorithm 3: the table's slot can lie before the slice)
-                const int32_t c2 = table_lb(O.adj, tab + raux[h], hi_w);
-                ce = c2 < e ? c2 : e;
-                if (vpp || clb) ce = ce > cs ? ce : cs;
-              }
-            } else if (nv < hi_w) {
-              if (hi_w >= ehi) {
-                ce = e;
-                nv = kNoEnd;
-              } else {
-                ce = near_lower_bound_v(O.adj, cs + 1, e, hi_w, nv);
-              }
-            }
-          }
-          rce[h] = ce;
-          rnv[h] = nv;
-        }
-      };
-      // Resident mode: writes the non-empty slices of middles j < lim whose
-      // rank among them (in middle order) lies in [b0, b0 + segcap) to the
-      // segment list; returns the segment count, their total length and the
-      // number of non-empty slices among j < lim.
-      auto res_emit = [&](int32_t lim, int32_t b0, int32_t segcap, bool second, int32_t* se, int32_t* sd,
-                          int32_t* sj, unsigned long long* sdel, int32_t& nseg, int32_t& T, int32_t& nact) {
-        bool actv[2];
-        int32_t len[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          actv[h] = 2 * t + h < lim && rce[h] > rcs[h];
-          len[h] = actv[h] ? rce[h] - rcs[h] : 0;
-        }
-        const unsigned long long packed =
-            ((unsigned long long)((int)actv[0] + (int)actv[1]) << 32) | (uint32_t)(len[0] + len[1]);
-        unsigned long long tot;
-        const unsigned long long ex = block_exclusive_scan<unsigned long long, kNT>(packed, s_red64, &tot);
-        nact = (int32_t)(tot >> 32);
-        int32_t ia = (int32_t)(ex >> 32);
-        int32_t lex = (int32_t)(uint32_t)ex;
-        if (b0 > 0) {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            if (actv[h] && ia == b0) s_cut_lex = lex;
-            if (actv[h]) { ++ia; lex += len[h]; }
-          }
-          __syncthreads();
-          ia = (int32_t)(ex >> 32);
-          lex = (int32_t)(uint32_t)ex;
-        }
-        const int32_t lex0 = b0 > 0 ? s_cut_lex : 0;
-        const int32_t hi_idx = nact < b0 + segcap ? nact : b0 + segcap;
-        nseg = hi_idx - b0;
-        T = (hi_idx == nact ? (int32_t)(uint32_t)tot : 0) - lex0;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          if (!actv[h]) continue;
-          if (ia >= b0 && ia < b0 + segcap) {
-            const int32_t ps = ia - b0;
-            se[ps] = lex - lex0;
-            sd[ps] = rcs[h] - (lex - lex0);
-            if (second) {
-              sj[ps] = 2 * t + h;
-              sdel[ps] = 0ull;
-            }
-          } else if (ia == b0 + segcap) {
-            s_cut_j = lex;  // total length of the batch's slices + lex0
-          }
-          ++ia;
-          lex += len[h];
-        }
-        if (hi_idx < nact) {
-          __syncthreads();
-          T = s_cut_j - lex0;
-        }
-        if (t == 0) { se[nseg] = T; s_ticket = 0; }
-        __syncthreads();
-      };
-      // Resident mode: the window is final; its slice ends become the next starts.
-      auto res_commit = [&] {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          if (raux[h] < 0) raux[h] = -1 - rnv[h];
-          rcs[h] = rce[h];
-        }
-      };
-
       // ---- pass 1: count the wedges whose end lies in [lo_w, hi_w)
       int32_t halvings = 0;
       int32_t batches = 0, last_n = 0, last_t = 0;
@@ -1223,12 +1102,11 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         int32_t rj = 0;
         bool over = false;
         batches = 0;
-        if (resident) res_slices();
         // A cursor start's window: every middle's slice in one barrier-free
         // pass (kA middles per thread and round, their loads issued
         // together), the non-empty ones appended to `act` with one LDS
         // atomic per wavefront and round; batches then take kS1 of them.
-        const bool compact = cursors && !resident && !seeded;
+        const bool compact = cursors && !seeded;
         int32_t n_act = 0;
         if (compact) {
           constexpr int kA = 4;
@@ -1324,43 +1202,6 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
             }
             __syncthreads();
             rj = lim;
-          } else if (resident) {
-            {
-              // every slice fits one batch, in any order: each wavefront
-              // reserves its entries and positions with one LDS atomic
-              const bool a0 = 2 * t < pre1 && rce[0] > rcs[0];
-              const bool a1 = 2 * t + 1 < pre1 && rce[1] > rcs[1];
-              const uint32_t l0 = a0 ? (uint32_t)(rce[0] - rcs[0]) : 0u;
-              const uint32_t l1 = a1 ? (uint32_t)(rce[1] - rcs[1]) : 0u;
-              const unsigned long long v = ((unsigned long long)((int)a0 + (int)a1) << 32) | (l0 + l1);
-              const unsigned long long inc = wave_inclusive_scan(v);
-              const unsigned long long wt = __shfl(inc, 63, 64);
-              unsigned long long wb = 0;
-              if (lane == 63 && wt) wb = atomicAdd(&s_emit, wt);
-              wb = __shfl(wb, 63, 64);
-              unsigned long long at = wb + inc - v;
-              if (a0) {
-                const int32_t ps = (int32_t)(at >> 32), L = (int32_t)(uint32_t)at;
-                se[ps] = L;
-                sd[ps] = rcs[0] - L;
-                at += (1ull << 32) | l0;
-              }
-              if (a1) {
-                const int32_t ps = (int32_t)(at >> 32), L = (int32_t)(uint32_t)at;
-                se[ps] = L;
-                sd[ps] = rcs[1] - L;
-              }
-              __syncthreads();
-              const unsigned long long all = s_emit;
-              nseg = (int32_t)(all >> 32);
-              T = (int32_t)(uint32_t)all;
-              if (t == 0) {
-                se[nseg] = T;
-                s_ticket = 0;
-              }
-              __syncthreads();
-            }
-            rj = pre1;  // one batch holds every slice (pre <= kS1)
           } else {
             fill(pre1, kS1, false, se, sd, nullptr, nullptr, rj, nseg, T);
           }
@@ -1458,17 +1299,10 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         int32_t* sd = segbuf + kS2 + 1;
         int32_t* sj = sd + kS2;
         unsigned long long* sdel = reinterpret_cast<unsigned long long*>(segbuf + 3 * kS2 + 2);
-        int32_t rj = 0, b0 = 0;
+        int32_t rj = 0;
         while (rj < pre) {
           int32_t nseg, T;
-          if (resident) {
-            int32_t nact;
-            res_emit(pre, b0, kS2, true, se, sd, sj, sdel, nseg, T, nact);
-            b0 += kS2;
-            if (b0 >= nact) rj = pre;
-          } else {
-            fill(pre, kS2, true, se, sd, sj, sdel, rj, nseg, T);
-          }
+          fill(pre, kS2, true, se, sd, sj, sdel, rj, nseg, T);
           int32_t F0, F1;
           share(T, F0, F1);
           // a lane's segments only increase along its positions: sum its
@@ -1506,7 +1340,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
           }
           __syncthreads();
         }
-      } else if (cursors && !advance_now && !resident) {
+      } else if (cursors && !advance_now) {
         // hash window of a total count: advance the cursors now that the window is final
         for (int32_t j = t; j < pre1; j += kNT) {
           const int4 r4 = rec[j];
@@ -1516,7 +1350,6 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
           }
         }
       }
-      if (resident) res_commit();
       // ---- finalize the window: C(count,2) per end, then clear the table
       unsigned long long* vs = pick_ptr(p.vout, x);
       if (mode == kTotal && wdense && !seeded && batches == 1 && last_t < kRewalkMax) {
