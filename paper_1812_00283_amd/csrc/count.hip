@@ -1109,7 +1109,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         const bool compact = cursors && !seeded;
         int32_t n_act = 0;
         if (compact) {
-          constexpr int kA = 4;
+          constexpr int kA = 2;
           if (t == 0) s_nact = 0;
           __syncthreads();
           for (int32_t j0 = 0; j0 < pre1; j0 += kA * kNT) {
