@@ -750,7 +750,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
   __shared__ __align__(16) int32_t table[kWords];
   __shared__ __align__(16) int32_t segbuf[kSW];
   __shared__ unsigned long long s_red64[kWaves + 1];
-  __shared__ int32_t s_fill, s_over, s_cut_j, s_cut_lex, s_nact;
+  __shared__ int32_t s_fill, s_over, s_cut_j, s_cut_lex;
   __shared__ int4 s_entry;      // the next start's list entry (code -1: none left)
   __shared__ int32_t s_ticket;  // chunk ticket of the dense walk
   __shared__ unsigned long long s_emit;  // batch emission: count << 32 | total length
@@ -1104,14 +1104,14 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         batches = 0;
         // A cursor start's window: every middle's slice in one barrier-free
         // pass (kA middles per thread and round, their loads issued
-        // together), the non-empty ones appended to `act` with one LDS
-        // atomic per wavefront and round; batches then take kS1 of them.
+        // together).  Each wavefront reserves positions for its non-empty
+        // slices with one LDS atomic per round (count and total length): the
+        // first kS1 go straight into the segment list as the first batch,
+        // the rest to `act`, from which later batches take kS1 each.
         const bool compact = cursors && !seeded;
-        int32_t n_act = 0;
+        int32_t n_act = 0, nseg0 = 0, T0 = 0;
         if (compact) {
           constexpr int kA = 2;
-          if (t == 0) s_nact = 0;
-          __syncthreads();
           for (int32_t j0 = 0; j0 < pre1; j0 += kA * kNT) {
             int4 rc[kA];
 #pragma unroll
@@ -1150,28 +1150,54 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
                   else cend[j] = ce;
                 }
               }
-              const uint64_t bal = __ballot(ac);
-              int32_t wb = 0;
-              if (lane == 0 && bal) wb = atomicAdd(&s_nact, (int32_t)__popcll(bal));
-              wb = __shfl(wb, 0, 64);
-              if (ac) act[mbcnt(bal, wb)] = make_int2(cs, ce);
+              const unsigned long long pv = ac ? (1ull << 32) | (uint32_t)(ce - cs) : 0ull;
+              const unsigned long long inc = wave_inclusive_scan(pv);
+              const unsigned long long wt = __shfl(inc, 63, 64);
+              unsigned long long wb = 0;
+              if (lane == 63 && wt) wb = atomicAdd(&s_emit, wt);
+              wb = __shfl(wb, 63, 64);
+              if (ac) {
+                const unsigned long long at = wb + inc - pv;
+                const int32_t ps = (int32_t)(at >> 32), L = (int32_t)(uint32_t)at;
+                if (ps < kS1) {
+                  se[ps] = L;
+                  sd[ps] = cs - L;
+                } else {
+                  act[ps - kS1] = make_int2(cs, ce);
+                  if (ps == kS1) s_cut_lex = L;  // the first batch's total length
+                }
+              }
             }
           }
           __syncthreads();
-          n_act = s_nact;
+          const unsigned long long all = s_emit;
+          n_act = (int32_t)(all >> 32);
+          nseg0 = n_act < kS1 ? n_act : kS1;
+          T0 = n_act <= kS1 ? (int32_t)(uint32_t)all : s_cut_lex;
+          if (t == 0) {
+            se[nseg0] = T0;
+            s_ticket = 0;
+          }
+          __syncthreads();
         }
         while (compact ? rj < n_act : rj < pre1) {
           int32_t nseg, T;
-          if (compact) {
-            // batch [rj, rj + kS1) of the window's slices: two per thread,
-            // positions from a wavefront scan and one LDS atomic per wavefront
+          if (compact && rj == 0) {
+            // the first batch, emitted by the pass
+            nseg = nseg0;
+            T = T0;
+            rj = nseg0;
+          } else if (compact) {
+            // batch [rj, rj + kS1) of the window's slices (act holds those
+            // from kS1 on): two per thread, positions from a wavefront scan
+            // and one LDS atomic per wavefront
             if (t == 0) s_emit = 0ull;
             __syncthreads();
             const int32_t i0 = rj + 2 * t, i1 = i0 + 1;
             const int32_t lim = n_act - rj < kS1 ? n_act : rj + kS1;
             int2 c0 = make_int2(0, 0), c1 = make_int2(0, 0);
-            if (i0 < lim) c0 = act[i0];
-            if (i1 < lim) c1 = act[i1];
+            if (i0 < lim) c0 = act[i0 - kS1];
+            if (i1 < lim) c1 = act[i1 - kS1];
             const uint32_t l0 = (uint32_t)(c0.y - c0.x), l1 = (uint32_t)(c1.y - c1.x);
             const unsigned long long v =
                 ((unsigned long long)((int)(i0 < lim) + (int)(i1 < lim)) << 32) | (l0 + l1);
