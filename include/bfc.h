@@ -95,8 +95,8 @@ bfc_status bfc_count_total_async(bfc_graph g, void* stream, int64_t* total_dev);
  *   total_dev  device int64 [1], receives B_G (same value as bfc_count_total).
  * When the full grid's cursors do not fit the array the count runs on fewer
  * workgroups (slower, same result); BFC_ERR_TOO_LARGE when not even one
- * workgroup's cursors fit (a start with more than about 5.5 million
- * lower-priority neighbours).  The array is shared by every call on a
+ * workgroup's cursors fit (28 bytes per middle: a start with more than
+ * about 2.4 million lower-priority neighbours).  The array is shared by every call on a
  * device and keeps the last call's contents (the call clears what must
  * start at zero): calls that overlap on one device, on different streams
  * or from different threads, race and give wrong results; order them.

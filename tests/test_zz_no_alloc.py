@@ -86,7 +86,7 @@ def test_static_is_capturable(gpu_lib):
 
 def test_static_rejects_a_start_beyond_the_array(gpu_lib):
     """Two upper vertices sharing 6M lower neighbours: the second has 6M
-    lower-priority middles, whose cursors (12 bytes each) exceed 64 MiB."""
+    lower-priority middles, whose cursors (28 bytes each) exceed 64 MiB."""
     bfc = gpu_lib
     lib = bfc.load()
     n = 6_000_000
