@@ -8,7 +8,7 @@
 // (2) an exclusive scan of the histograms laid out digit-major, so that
 // counts[d * tiles + t] becomes the output position of tile t's first key
 // with digit d, and (3) a stable scatter.  In the scatter each wavefront
-// owns 1024 consecutive keys of the tile and ranks them 64 at a time: lanes
+// owns 512 consecutive keys of the tile and ranks them 64 at a time: lanes
 // with equal digits are found with eight ballots (one per digit bit), and a
 // per-wavefront running count per digit in LDS orders successive rounds, so
 // no workgroup barrier is needed inside the ranking loop.  Keys are then
@@ -98,13 +98,15 @@ void exclusive_scan_impl(const T* in, T* out, int64_t n, T* total, hipStream_t s
 }
 
 // ------------------------------------------------------------------ sort
-// 8192 keys per workgroup (512 threads): each tile writes 256 digit runs
-// of 32 keys on average, long enough to keep the scatter's writes coalesced.
+// 4096 keys per workgroup (512 threads): each tile writes 256 digit runs
+// of 16 keys on average.  The tile's 36 KB of LDS (64-bit keys) lets four
+// workgroups share a CU; measured against 2,048- to 12,288-key tiles and
+// 256 or 1,024 threads, this shape sorted fastest.
 constexpr int kSortNT = 512;
-constexpr int kSortVT = 16;
-constexpr int kSortTile = kSortNT * kSortVT;   // 8192 keys per workgroup
+constexpr int kSortVT = 8;
+constexpr int kSortTile = kSortNT * kSortVT;   // 4096 keys per workgroup
 constexpr int kSortWaves = kSortNT / 64;
-constexpr int kPerWave = kSortTile / kSortWaves;  // 1024
+constexpr int kPerWave = kSortTile / kSortWaves;  // 512
 
 template <typename K>
 __global__ __launch_bounds__(kSortNT) void sort_hist_kernel(const K* __restrict__ keys, int64_t n, int shift,
