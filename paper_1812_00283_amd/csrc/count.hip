@@ -867,7 +867,7 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
     // dense windows below q8 hold 8-bit counters: four ranks per word (q8
     // rounded down to even: the 16-bit windows that follow pair ranks from
     // an even first rank)
-    const int32_t q8 = (x ? p.q8[1] : p.q8[0]) & ~1;
+    int32_t q8 = (x ? p.q8[1] : p.q8[0]) & ~1;
     auto dense_hi = [&](int32_t lo) -> int32_t {
       const int64_t h = lo < q8 ? (int64_t)lo + 4 * kWords : (int64_t)lo + width;
       const int32_t h8 = lo < q8 && h > q8 ? q8 : (int32_t)(h < 0x7FFFFFFF ? h : 0x7FFFFFFF);
@@ -908,6 +908,18 @@ __global__ __launch_bounds__(kNT) void heavy_kernel(CountParams p) {
         hwidth = (int32_t)(wd < 256 ? 256 : (wd > span ? span : wd));
         cap = cmax;
       }
+    }
+    // The last 8-bit window stops at q8, so a short stretch below q8 can
+    // cost a window more than wider-counter windows over the whole dense
+    // range; and four counters to a word put more of a start's LDS atomics
+    // on the same word.  So the 8-bit windows are kept only when they save
+    // at least one window.
+    if (hash_end < q8 && hash_end < sparse_end) {
+      const int64_t e8 = q8 < sparse_end ? q8 : sparse_end;
+      const int64_t n8 = (e8 - hash_end + 4 * kWords - 1) / (4 * kWords);
+      const int64_t nw = q8 < sparse_end ? ((int64_t)sparse_end - q8 + width - 1) / width : 0;
+      const int64_t n1 = ((int64_t)sparse_end - hash_end + width - 1) / width;
+      if (n8 + nw >= n1) q8 = 0;
     }
     int32_t pre_out = pre;
     if (in_block) {
