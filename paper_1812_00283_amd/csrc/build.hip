@@ -22,6 +22,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "sort.hpp"
 
 namespace bfc {
 
@@ -187,22 +188,43 @@ __global__ void invert_kernel(const uint32_t* __restrict__ id_of, int32_t* __res
 // Arc keys (rank_u << bits_dst | rank_v).  bits_idx > 0: the key is shifted
 // up by bits_idx and the edge index fills the low bits (no value array);
 // otherwise vals receives the edge index.
-__global__ void arc_keys_kernel(const int32_t* __restrict__ edges, int64_t m, int src_col,
-                                const int32_t* __restrict__ rank_src, const int32_t* __restrict__ rank_dst,
-                                int bits_dst, int bits_idx, uint64_t* __restrict__ keys,
-                                uint32_t* __restrict__ vals) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+// The key kernels below write one radix-sort tile per workgroup
+// (kSortTileKeys keys, 512 threads) and count the tile's first sort digit,
+// bits [shift, shift + 8) of each key, into counts[d * tiles + tile].
+constexpr int kKeyNT = 512;
+
+__device__ __forceinline__ void tile_digit_counts(uint32_t* h, uint32_t* __restrict__ counts, int64_t tiles) {
+  __syncthreads();
+  if (threadIdx.x < 256) counts[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kKeyNT) void arc_keys_kernel(const int32_t* __restrict__ edges, int64_t m, int src_col,
+                                                          const int32_t* __restrict__ rank_src,
+                                                          const int32_t* __restrict__ rank_dst, int bits_dst,
+                                                          int bits_idx, uint64_t* __restrict__ keys,
+                                                          uint32_t* __restrict__ vals, int shift,
+                                                          uint32_t* __restrict__ counts, int64_t tiles) {
+  __shared__ uint32_t h[256];
+  if (threadIdx.x < 256) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTileKeys;
+#pragma unroll
+  for (int j = 0; j < kSortTileKeys / kKeyNT; ++j) {
+    const int64_t i = base + j * kKeyNT + threadIdx.x;
+    if (i >= m) break;
     const int2 e = reinterpret_cast<const int2*>(edges)[i];
     const int32_t a = src_col == 0 ? e.x : e.y;
     const int32_t b = src_col == 0 ? e.y : e.x;
-    const uint64_t key = ((uint64_t)(uint32_t)rank_src[a] << bits_dst) | (uint64_t)(uint32_t)rank_dst[b];
+    uint64_t key = ((uint64_t)(uint32_t)rank_src[a] << bits_dst) | (uint64_t)(uint32_t)rank_dst[b];
     if (bits_idx > 0) {
-      keys[i] = (key << bits_idx) | (uint64_t)i;
+      key = (key << bits_idx) | (uint64_t)i;
     } else {
-      keys[i] = key;
       vals[i] = (uint32_t)i;
     }
+    keys[i] = key;
+    atomicAdd(&h[(uint32_t)(key >> shift) & 255u], 1u);
   }
+  tile_digit_counts(h, counts, tiles);
 }
 
 __global__ void arc_unpack_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t m,
@@ -234,10 +256,23 @@ __global__ void transpose_keys_kernel(const int32_t* __restrict__ adj0, int64_t 
 // other.
 // Packed transpose: key (v << (bu + bs)) | (u << bs) | s0 per side-0 slot
 // s0 = (u, v); sorted on its v bits, it yields side 1 without gathers.
-__global__ void transpose_keys_packed_kernel(const int32_t* __restrict__ adj0, const int32_t* __restrict__ src0,
-                                             int64_t m, int bu, int bs, uint64_t* __restrict__ key) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
-    key[k] = ((uint64_t)(uint32_t)adj0[k] << (bu + bs)) | ((uint64_t)(uint32_t)src0[k] << bs) | (uint64_t)k;
+__global__ __launch_bounds__(kKeyNT) void transpose_keys_packed_kernel(const int32_t* __restrict__ adj0,
+                                                                       const int32_t* __restrict__ src0, int64_t m,
+                                                                       int bu, int bs, uint64_t* __restrict__ key,
+                                                                       uint32_t* __restrict__ counts, int64_t tiles) {
+  __shared__ uint32_t h[256];
+  if (threadIdx.x < 256) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTileKeys;
+#pragma unroll
+  for (int j = 0; j < kSortTileKeys / kKeyNT; ++j) {
+    const int64_t k = base + j * kKeyNT + threadIdx.x;
+    if (k >= m) break;
+    const uint32_t v = (uint32_t)adj0[k];
+    key[k] = ((uint64_t)v << (bu + bs)) | ((uint64_t)(uint32_t)src0[k] << bs) | (uint64_t)k;
+    atomicAdd(&h[v & 255u], 1u);  // the sort's first digit: the low 8 bits of v
+  }
+  tile_digit_counts(h, counts, tiles);
 }
 __global__ void transpose_unpack_packed_kernel(const uint64_t* __restrict__ key, int64_t m, int bu, int bs,
                                                int32_t* __restrict__ adj1, int32_t* __restrict__ src1,
@@ -563,14 +598,21 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
     // keys only (8 bytes per arc and pass instead of 12)
     const int bits_idx = bits_for((uint64_t)(m - 1));
     const bool packed = bits[0] + bits[1] + bits_idx <= 64;
-    arc_keys_kernel<<<grid_1d(m), 256, 0, s>>>(edges, m, 0, rank_of[0].as<int32_t>(), rank_of[1].as<int32_t>(),
-                                                 bits[1], packed ? bits_idx : 0, keys.as<uint64_t>(),
-                                                 vals.as<uint32_t>());
+    // the key kernels also count each sort tile's first digit, which
+    // spares each sort its first histogram pass
+    const int64_t tiles = sort_tiles(m);
+    TmpBuf counts;
+    counts.alloc(sizeof(uint32_t) * 256 * (size_t)tiles, s);
+    arc_keys_kernel<<<(unsigned)tiles, kKeyNT, 0, s>>>(edges, m, 0, rank_of[0].as<int32_t>(),
+                                                       rank_of[1].as<int32_t>(), bits[1], packed ? bits_idx : 0,
+                                                       keys.as<uint64_t>(), vals.as<uint32_t>(),
+                                                       packed ? bits_idx : 0, counts.as<uint32_t>(), tiles);
     BFC_LAUNCH_CHECK();
     const bool in_tmp =
-        packed ? radix_sort_u64_keys_any(keys.as<uint64_t>(), ktmp.as<uint64_t>(), m, bits_idx, bits[0] + bits[1], s)
-               : radix_sort_u64_any(keys.as<uint64_t>(), vals.as<uint32_t>(), ktmp.as<uint64_t>(),
-                                    vtmp.as<uint32_t>(), m, bits[0] + bits[1], s);
+        packed ? radix_sort_u64_keys_counted(keys.as<uint64_t>(), ktmp.as<uint64_t>(), m, bits_idx,
+                                             bits[0] + bits[1], counts.as<uint32_t>(), s)
+               : radix_sort_u64_counted(keys.as<uint64_t>(), vals.as<uint32_t>(), ktmp.as<uint64_t>(),
+                                        vtmp.as<uint32_t>(), m, bits[0] + bits[1], counts.as<uint32_t>(), s);
     arc_unpack_kernel<<<grid_1d(m), 256, 0, s>>>(in_tmp ? ktmp.as<uint64_t>() : keys.as<uint64_t>(),
                                                  in_tmp ? vtmp.as<uint32_t>() : vals.as<uint32_t>(), m, bits[1],
                                                  packed ? bits_idx : 0, g->side[0].adj.as<int32_t>(),
@@ -579,11 +621,13 @@ void build_graph(bfc_graph_s* g, const int32_t* edges, hipStream_t s, const int3
     BFC_LAUNCH_CHECK();
     if (packed) {
       // side 1: one 64-bit key per side-0 slot carrying (v, u, slot), sorted on v
-      transpose_keys_packed_kernel<<<grid_1d(m), 256, 0, s>>>(g->side[0].adj.as<int32_t>(), src[0].as<int32_t>(), m,
-                                                              bits[0], bits_idx, keys.as<uint64_t>());
+      transpose_keys_packed_kernel<<<(unsigned)tiles, kKeyNT, 0, s>>>(g->side[0].adj.as<int32_t>(),
+                                                                      src[0].as<int32_t>(), m, bits[0], bits_idx,
+                                                                      keys.as<uint64_t>(), counts.as<uint32_t>(),
+                                                                      tiles);
       BFC_LAUNCH_CHECK();
-      const bool t_tmp =
-          radix_sort_u64_keys_any(keys.as<uint64_t>(), ktmp.as<uint64_t>(), m, bits[0] + bits_idx, bits[1], s);
+      const bool t_tmp = radix_sort_u64_keys_counted(keys.as<uint64_t>(), ktmp.as<uint64_t>(), m, bits[0] + bits_idx,
+                                                     bits[1], counts.as<uint32_t>(), s);
       transpose_unpack_packed_kernel<<<grid_1d(m), 256, 0, s>>>(
           t_tmp ? ktmp.as<uint64_t>() : keys.as<uint64_t>(), m, bits[0], bits_idx, g->side[1].adj.as<int32_t>(),
           src[1].as<int32_t>(), g->side[1].rev.as<int32_t>(), g->side[0].rev.as<int32_t>());

@@ -16,6 +16,7 @@
 // write consecutive addresses of one digit's run.
 #include "device.hpp"
 #include "internal.hpp"
+#include "sort.hpp"
 
 namespace bfc {
 
@@ -105,6 +106,7 @@ void exclusive_scan_impl(const T* in, T* out, int64_t n, T* total, hipStream_t s
 constexpr int kSortNT = 512;
 constexpr int kSortVT = 8;
 constexpr int kSortTile = kSortNT * kSortVT;   // 4096 keys per workgroup
+static_assert(kSortTile == kSortTileKeys, "the tile that sort.hpp announces");
 constexpr int kSortWaves = kSortNT / 64;
 constexpr int kPerWave = kSortTile / kSortWaves;  // 512
 
@@ -212,9 +214,10 @@ __global__ __launch_bounds__(kSortNT) void sort_scatter_kernel(const K* __restri
 
 // Sorts on key bits [lo_bit, lo_bit + bits); vals may be null (keys only).
 // Returns true when the sorted data ends in (ktmp, vtmp) (copy_back false).
+// first_counts: the first pass's tile histograms, already counted (or null).
 template <typename K>
 bool radix_sort_impl(K* keys, uint32_t* vals, K* ktmp, uint32_t* vtmp, int64_t n, int bits, hipStream_t s,
-                     bool copy_back = true, int lo_bit = 0) {
+                     bool copy_back = true, int lo_bit = 0, uint32_t* first_counts = nullptr) {
   if (n <= 1 || bits <= 0) return false;
   const int64_t tiles = (n + kSortTile - 1) / kSortTile;
   uint32_t* counts = nullptr;
@@ -224,13 +227,18 @@ bool radix_sort_impl(K* keys, uint32_t* vals, K* ktmp, uint32_t* vtmp, int64_t n
   uint32_t* vs = vals;
   uint32_t* vd = vtmp;
   for (int shift = lo_bit; shift < lo_bit + bits; shift += 8) {
-    sort_hist_kernel<K><<<(unsigned)tiles, kSortNT, 0, s>>>(ks, n, shift, counts, tiles);
-    BFC_LAUNCH_CHECK();
-    exclusive_scan_impl<uint32_t>(counts, counts, 256 * tiles, nullptr, s);
+    uint32_t* c = counts;
+    if (shift == lo_bit && first_counts) {
+      c = first_counts;
+    } else {
+      sort_hist_kernel<K><<<(unsigned)tiles, kSortNT, 0, s>>>(ks, n, shift, counts, tiles);
+      BFC_LAUNCH_CHECK();
+    }
+    exclusive_scan_impl<uint32_t>(c, c, 256 * tiles, nullptr, s);
     if (vals)
-      sort_scatter_kernel<K, true><<<(unsigned)tiles, kSortNT, 0, s>>>(ks, vs, kd, vd, n, shift, counts, tiles);
+      sort_scatter_kernel<K, true><<<(unsigned)tiles, kSortNT, 0, s>>>(ks, vs, kd, vd, n, shift, c, tiles);
     else
-      sort_scatter_kernel<K, false><<<(unsigned)tiles, kSortNT, 0, s>>>(ks, vs, kd, vd, n, shift, counts, tiles);
+      sort_scatter_kernel<K, false><<<(unsigned)tiles, kSortNT, 0, s>>>(ks, vs, kd, vd, n, shift, c, tiles);
     BFC_LAUNCH_CHECK();
     K* tk = ks; ks = kd; kd = tk;
     uint32_t* tv = vs; vs = vd; vd = tv;
@@ -269,6 +277,14 @@ bool radix_sort_u64_any(uint64_t* keys, uint32_t* vals, uint64_t* ktmp, uint32_t
 }
 bool radix_sort_u64_keys_any(uint64_t* keys, uint64_t* ktmp, int64_t n, int lo_bit, int bits, hipStream_t s) {
   return radix_sort_impl<uint64_t>(keys, nullptr, ktmp, nullptr, n, bits, s, false, lo_bit);
+}
+bool radix_sort_u64_keys_counted(uint64_t* keys, uint64_t* ktmp, int64_t n, int lo_bit, int bits,
+                                 uint32_t* first_counts, hipStream_t s) {
+  return radix_sort_impl<uint64_t>(keys, nullptr, ktmp, nullptr, n, bits, s, false, lo_bit, first_counts);
+}
+bool radix_sort_u64_counted(uint64_t* keys, uint32_t* vals, uint64_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
+                            uint32_t* first_counts, hipStream_t s) {
+  return radix_sort_impl<uint64_t>(keys, vals, ktmp, vtmp, n, bits, s, false, 0, first_counts);
 }
 
 }  // namespace bfc
