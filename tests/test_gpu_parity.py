@@ -220,6 +220,22 @@ def test_byte_counters_at_their_limit(gpu_lib):
             check_against_oracle(gpu_lib, g, tun)
 
 
+def test_byte_counters_in_wide_end_ranges(gpu_lib):
+    """A start keeps 8-bit windows only where they save a window, which the
+    small graphs above never reach.  Here the same blocks sit above 300,000
+    isolated edges, so a block start's end range spans three 8-bit windows
+    (five 16-bit ones) and its ends, of degree 255 or less, count up to 255
+    in the third; also on defaults, where a hash prefix may take the padding."""
+    pad = 300_000
+    iu = np.arange(pad, dtype=np.int32)
+    for a, b in [(40, 255), (255, 255), (3, 255), (255, 3)]:
+        k = gg.complete_bipartite(a, b)
+        e = np.concatenate([k.edges, np.stack([a + iu, b + iu], axis=1)]).astype(np.int32)
+        g = gg.Graph(np.ascontiguousarray(e), a + pad, b + pad, f"K{a},{b}+{pad} isolated edges")
+        for tun in ({"light_max_wedges": 1, "window_mode": 2}, None):
+            check_against_oracle(gpu_lib, g, tun)
+
+
 def test_mfma_block_covers_whole_small_graphs(gpu_lib):
     """Block sizes at or above the layer sizes: every start is in the block."""
     for a, b in [(3, 5), (40, 60), (64, 64), (100, 37)]:
