@@ -626,15 +626,20 @@ __device__ __forceinline__ void seg_walk(const int32_t* __restrict__ oadj, const
       // the steps are independent
       const int32_t e0 = b - f0 - 1;  // start offset - 1 relative to step 0
       const int32_t pos0 = f0 + lane;
+      // lane 63's start lies beyond the iteration, so its bias is never
+      // read (c <= 63): it carries the current segment's bias instead, which
+      // c = 0 reads (byte address -4 selects lane 63)
+      const int32_t g63 = lane == 63 ? sd0 : g;
 #pragma unroll
       for (int q = 0; q < kSegSteps; ++q) {
         const int32_t e = e0 - 64 * q;
         const bool mk = (uint32_t)e < 63u;  // start inside (f, f + 64)
         const int32_t mark = __builtin_amdgcn_ds_permute(mk ? (e + 1) << 2 : 0, mk ? 1 : 0);
         const int32_t cb = __popcll(__ballot(e < 0));  // starts at or before f
-        const int32_t c = mbcnt(__ballot(mark != 0), mark + cb);
-        const int32_t gc = __builtin_amdgcn_ds_bpermute((c << 2) - 4, g);
-        slot[q] = (c == 0 ? sd0 : gc) + pos0 + 64 * q;
+        // lane 0 is never marked (a start at f counts in cb), so the marks
+        // at or below this lane are the marks shifted down one lane below it
+        const int32_t c = mbcnt(__ballot(mark != 0) >> 1, cb);
+        slot[q] = __builtin_amdgcn_ds_bpermute((c << 2) - 4, g63) + pos0 + 64 * q;
         sg[q] = s0 + c;
         w[q] = load_end(oadj, slot[q]);
       }
