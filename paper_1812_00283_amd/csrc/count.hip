@@ -665,10 +665,12 @@ __device__ __forceinline__ void seg_walk(const int32_t* __restrict__ oadj, const
         }
         const int32_t d = b - f;
         const int32_t mark = __builtin_amdgcn_ds_permute(d < 64 ? 4 * d : 0, d < 64 ? 1 : 0);
-        const int32_t c = mbcnt(__ballot(mark != 0), mark);
-        const int32_t gc = __builtin_amdgcn_ds_bpermute((c << 2) - 4, g);
+        // as above: lane 0 is never marked (d >= 1), and at most 63 starts
+        // fall inside the step, so lane 63 may carry the current bias
+        const int32_t c = mbcnt(__ballot(mark != 0) >> 1, 0);
+        const int32_t gc = __builtin_amdgcn_ds_bpermute((c << 2) - 4, lane == 63 ? sd0 : g);
         if (f + lane < F1) {
-          slot[q] = (c == 0 ? sd0 : gc) + f + lane;
+          slot[q] = gc + f + lane;
           sg[q] = s0 + c;
           w[q] = load_end(oadj, slot[q]);
         }
